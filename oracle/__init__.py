@@ -1,0 +1,425 @@
+"""CPU oracle for the emulated-FP64 (Ozaki) GEMM, H_eff.psi and Davidson.
+
+TEST INFRASTRUCTURE ONLY.  The test suite, the smoke check and the
+benchmark's CPU-baseline leg are the only users.  The HIP library never
+imports, links or calls anything here, and nothing here imports the HIP
+library: the two sides meet only through the seeded inputs of
+``paper_2510_04795_amd.workloads``.
+
+The arithmetic of the emulated GEMM lives in ``oracle.c`` (plain C, FP64,
+contraction off); this module builds it with gcc, wraps it with ctypes and
+adds the plain drivers that compose GEMMs into the effective-Hamiltonian
+application and the Davidson eigensolver.
+
+Functions and the passage of the paper they follow:
+
+* ``dgemm_fp64``      plain FP64 GEMM (the definition of C = AB).
+* ``dgemm_dd``        double-double GEMM, the error reference.
+* ``split``           steps 1-2 of the emulation strategy ("Theory of emulated
+                      FP64 arithmetic") with the slice/bit rule of "Numerical
+                      procedure".
+* ``pair_products``   step 3 (every slice pair multiplied exactly, summed per
+                      diagonal s + t; the worked 7 x 7 = 49 count and the
+                      dropped lower triangle).
+* ``recombine``       step 4 (accumulate and convert back to FP64).
+* ``ozaki_dgemm``     steps 1-4 in order.
+* ``heff_dense``, ``heff_sparse``  the two-site matvec sigma = sum_k L_k psi R_k^T
+                      ("Theory of TNS/DMRG": the effective Hamiltonian of the
+                      second subroutine acting on the two-site tensor), built
+                      from GEMM calls.
+* ``davidson``        lowest eigenpair by a Davidson iteration with a
+                      diagonal preconditioner (the Krylov solver of the second
+                      subroutine; its details are not given in the paper and
+                      follow the standard method).
+* ``ozaki_bound``     a-priori componentwise error bound of the emulated GEMM.
+
+Parity status: every function above is pinned by the CPU tests
+(``tests/test_oracle_pins.py``) except ``heff_sparse``'s synthetic block
+structure, whose composition is checked against an exact rational
+computation on a tiny case only.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+CONVERGED, RUNNING, STAGNATED, MAX_ITER = "converged", "running", "stagnated", "max_iter"
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so next to it (gcc, OpenMP, no contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
+            L = ctypes.CDLL(_LIB)
+            i64, i32, dbl, ptr = ctypes.c_int64, ctypes.c_int, ctypes.c_double, ctypes.c_void_p
+            L.oracle_num_threads.restype = i32
+            L.oracle_dgemm_fp64.argtypes = [i64, i64, i64, dbl, ptr, i64, ptr, i64, dbl, ptr, i64]
+            L.oracle_dgemm_fp64.restype = None
+            L.oracle_dgemm_dd.argtypes = [i64, i64, i64, ptr, i64, ptr, i64, ptr, ptr, i64]
+            L.oracle_dgemm_dd.restype = None
+            L.oracle_split.argtypes = [i32, i64, i64, ptr, i64, i32, ptr, ptr, ptr]
+            L.oracle_split.restype = i64
+            L.oracle_pair_products.argtypes = [i64, i64, i64, i32, i32, ptr, ptr, ptr]
+            L.oracle_pair_products.restype = None
+            L.oracle_recombine.argtypes = [i64, i64, i32, ptr, ptr, ptr, ptr, ptr, dbl, dbl, ptr, i64]
+            L.oracle_recombine.restype = None
+            L.oracle_ozaki_dgemm.argtypes = [ctypes.c_char, ctypes.c_char, i64, i64, i64, dbl, ptr,
+                                             i64, ptr, i64, dbl, ptr, i64, i32, i32]
+            L.oracle_ozaki_dgemm.restype = i32
+            _lib = L
+    return _lib
+
+
+def num_threads() -> int:
+    return int(lib().oracle_num_threads())
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _op(X: np.ndarray, trans: str) -> np.ndarray:
+    return _f64(X.T if trans.upper() == "T" else X)
+
+
+# ----------------------------------------------------------------------------
+# GEMMs
+# ----------------------------------------------------------------------------
+def dgemm_fp64(A, B, alpha=1.0, beta=0.0, C=None, transa="N", transb="N") -> np.ndarray:
+    """C = alpha op(A) op(B) + beta C in plain FP64 (k ascending, fma per term)."""
+    A, B = _op(A, transa), _op(B, transb)
+    M, K = A.shape
+    K2, N = B.shape
+    assert K == K2
+    out = np.zeros((M, N)) if C is None else _f64(C).copy()
+    lib().oracle_dgemm_fp64(M, N, K, alpha, _p(A), K, _p(B), N, beta, _p(out), N)
+    return out
+
+
+def dgemm_dd(A, B):
+    """Double-double A B: returns (hi, lo) with hi + lo ~ AB to ~K 2^-104 |A||B|."""
+    A, B = _f64(A), _f64(B)
+    M, K = A.shape
+    K2, N = B.shape
+    assert K == K2
+    hi = np.zeros((M, N))
+    lo = np.zeros((M, N))
+    lib().oracle_dgemm_dd(M, N, K, _p(A), K, _p(B), N, _p(hi), _p(lo), N)
+    return hi, lo
+
+
+def slices_for_bits(mantissa_bits: int) -> int:
+    """S = ceildiv(bits + 1, 8) ("Numerical procedure"; +1 for the sign bit)."""
+    return -(-(mantissa_bits + 1) // 8)
+
+
+def pair_count(S: int, G: int) -> int:
+    """Number of slice pairs (s, t), 0 <= s, t < S, with s + t < G."""
+    return sum(1 for s in range(S) for t in range(S) if s + t < G)
+
+
+def split(X, S: int, by_columns: bool = False):
+    """Steps 1-2: (digits [S][rows][cols] int8, exponents int32, bad uint8)."""
+    X = _f64(X)
+    rows, cols = X.shape
+    digits = np.zeros((S, rows, cols), dtype=np.int8)
+    ng = cols if by_columns else rows
+    exps = np.zeros(ng, dtype=np.int32)
+    bad = np.zeros(ng, dtype=np.uint8)
+    lib().oracle_split(int(bool(by_columns)), rows, cols, _p(X), cols, S, _p(digits), _p(exps),
+                       _p(bad))
+    return digits, exps, bad
+
+
+def pair_products(Ad: np.ndarray, Bd: np.ndarray, G: int) -> np.ndarray:
+    """Step 3: Q[g] = sum_{s+t=g} A_s B_t exactly (int64), Ad [S][M][K], Bd [S][K][N]."""
+    Ad = np.ascontiguousarray(Ad, dtype=np.int8)
+    Bd = np.ascontiguousarray(Bd, dtype=np.int8)
+    S, M, K = Ad.shape
+    S2, K2, N = Bd.shape
+    assert S == S2 and K == K2
+    Q = np.zeros((G, M, N), dtype=np.int64)
+    lib().oracle_pair_products(M, N, K, S, G, _p(Ad), _p(Bd), _p(Q))
+    return Q
+
+
+def recombine(Q, e, f, row_bad=None, col_bad=None, alpha=1.0, beta=0.0, C=None) -> np.ndarray:
+    """Step 4: Horner over diagonals, scale 2^(e_i + f_j - 14), alpha/beta."""
+    Q = np.ascontiguousarray(Q, dtype=np.int64)
+    G, M, N = Q.shape
+    e = np.ascontiguousarray(e, dtype=np.int32)
+    f = np.ascontiguousarray(f, dtype=np.int32)
+    rb = np.zeros(M, np.uint8) if row_bad is None else np.ascontiguousarray(row_bad, np.uint8)
+    cb = np.zeros(N, np.uint8) if col_bad is None else np.ascontiguousarray(col_bad, np.uint8)
+    out = np.zeros((M, N)) if C is None else _f64(C).copy()
+    lib().oracle_recombine(M, N, G, _p(Q), _p(e), _p(f), _p(rb), _p(cb), alpha, beta, _p(out), N)
+    return out
+
+
+def ozaki_dgemm(A, B, S: int, G: int | None = None, alpha=1.0, beta=0.0, C=None,
+                transa="N", transb="N") -> np.ndarray:
+    """Steps 1-4: emulated C = alpha op(A) op(B) + beta C, S slices, G diagonals."""
+    G = S if G is None else G
+    A, B = _f64(A), _f64(B)
+    M = A.shape[1] if transa.upper() == "T" else A.shape[0]
+    K = A.shape[0] if transa.upper() == "T" else A.shape[1]
+    N = B.shape[0] if transb.upper() == "T" else B.shape[1]
+    out = np.zeros((M, N)) if C is None else _f64(C).copy()
+    rc = lib().oracle_ozaki_dgemm(transa.upper().encode(), transb.upper().encode(), M, N, K,
+                                  alpha, _p(A), A.shape[1], _p(B), B.shape[1], beta, _p(out), N,
+                                  S, G)
+    if rc != 0:
+        raise ValueError("oracle_ozaki_dgemm: bad arguments")
+    return out
+
+
+def gemm(A, B, S: int = 0, G: int | None = None, **kw) -> np.ndarray:
+    """FP64 GEMM when S == 0, otherwise the emulated GEMM with S slices."""
+    if S == 0:
+        return dgemm_fp64(A, B, **kw)
+    return ozaki_dgemm(A, B, S, G, **kw)
+
+
+# ----------------------------------------------------------------------------
+# Error metrics and the a-priori bound
+# ----------------------------------------------------------------------------
+def rel_frobenius(C, hi, lo) -> float:
+    """||C - (hi + lo)||_F / ||hi + lo||_F with the difference formed as (C - hi) - lo."""
+    d = (C - hi) - lo
+    return float(np.linalg.norm(d) / np.linalg.norm(hi))
+
+
+def componentwise(C, hi, lo, absAB) -> float:
+    """max_ij |(C - hi) - lo| / (|A||B|)_ij."""
+    d = np.abs((C - hi) - lo)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        r = np.where(absAB > 0, d / absAB, np.where(d > 0, np.inf, 0.0))
+    return float(np.max(r))
+
+
+def ozaki_bound(A, B, S: int, G: int | None = None) -> np.ndarray:
+    """Componentwise bound on |ozaki(A, B) - AB| for the slice representation used here.
+
+    Three parts: (i) representation error of the rounded operands,
+    |a~ - a| <= 2^(e_i - 8S), |b~ - b| <= 2^(f_j - 8S), propagated through the
+    product; (ii) the dropped diagonals g >= G, bounded through |digits|;
+    (iii) the G - 1 Horner roundings and the final alpha scaling, each at most
+    one unit roundoff of a partial sum bounded by the sum of |Q_g| terms.
+    Computed from the operands' exponents and digits only (no emulated product).
+    """
+    G = S if G is None else G
+    A, B = _f64(A), _f64(B)
+    Ad, e, _ = split(A, S, by_columns=False)
+    Bd, f, _ = split(B, S, by_columns=True)
+    u = 2.0 ** -53
+    absA, absB = np.abs(A), np.abs(B)
+    # rounded operands a~ = 2^(e-7) sum_t d_t 2^(-8t)
+    wA = np.array([2.0 ** (-8 * t) for t in range(S)])
+    At = np.einsum("t,tik->ik", wA, Ad.astype(np.float64)) * np.ldexp(1.0, e - 7)[:, None]
+    Bt = np.einsum("t,tkj->kj", wA, Bd.astype(np.float64)) * np.ldexp(1.0, f - 7)[None, :]
+    rep = (np.ldexp(1.0, e - 8 * S)[:, None] * np.abs(Bt).sum(axis=0)[None, :]
+           + np.ldexp(1.0, f - 8 * S)[None, :] * absA.sum(axis=1)[:, None])
+    # magnitude of every diagonal's contribution, bounded through |digits|
+    aD = np.abs(Ad).astype(np.float64)
+    bD = np.abs(Bd).astype(np.float64)
+    scale = np.ldexp(1.0, (e[:, None] + f[None, :] - 14))
+    dropped = np.zeros_like(rep)
+    kept = np.zeros_like(rep)
+    for s in range(S):
+        for t in range(S):
+            term = (aD[s] @ bD[t]) * 2.0 ** (-8 * (s + t))
+            if s + t >= G:
+                dropped += term
+            else:
+                kept += term
+    horner = (G + 1) * u * kept * scale
+    return rep + dropped * scale + horner + 4 * u * (absA @ absB)
+
+
+# ----------------------------------------------------------------------------
+# Two-site effective Hamiltonian: sigma = sum_k L_k psi R_k^T
+# ----------------------------------------------------------------------------
+def heff_dense(L, R, psi, S: int = 0, G: int | None = None, diag=None) -> np.ndarray:
+    """sigma[:, j, :] = sum_k L_k psi[:, j, :] R_k^T for every physical index j.
+
+    Each operator pair costs two GEMM calls in ascending k: T_k = L_k Psi with
+    Psi the D x (p D) view of psi, then sigma += T_k' R_k^T with T_k' the
+    (p D) x D view of T_k.  sigma starts at +0 and every term is added as
+    fma(1, c, sigma).  With a diagonal, sigma <- sigma + diag * psi (two
+    FP64 roundings).  S = 0 uses the FP64 GEMM, S >= 1 the emulated one.
+    """
+    L = _f64(L)
+    R = _f64(R)
+    psi = _f64(psi)
+    D, p, D2 = psi.shape
+    Psi = psi.reshape(D, p * D2)
+    sigma = np.zeros((D * p, D2))
+    for k in range(L.shape[0]):
+        T = gemm(L[k], Psi, S, G)
+        sigma = gemm(T.reshape(D * p, D2), R[k], S, G, alpha=1.0, beta=1.0, C=sigma,
+                     transb="T")
+    sigma = sigma.reshape(D, p, D2)
+    if diag is not None:
+        sigma = sigma + _f64(diag) * psi
+    return sigma
+
+
+def heff_dense_rows(L, R, psi, rows, S: int = 0, G: int | None = None) -> np.ndarray:
+    """Rows alpha' in ``rows`` of heff_dense (all j and beta'), computed alone.
+
+    Exactly the same arithmetic as heff_dense restricted to those rows: a row
+    (alpha', j) of the second GEMM needs only row alpha' of T_k, and the
+    emulated GEMM's exponents are per row of A and per column of B, so the
+    rows come out identical to the full computation.  The column split of
+    Psi (the same for every k) is done once.
+    """
+    L = _f64(L)
+    R = _f64(R)
+    psi = _f64(psi)
+    D, p, D2 = psi.shape
+    Psi = psi.reshape(D, p * D2)
+    rows = list(rows)
+    out = np.zeros((len(rows), p, D2))
+    if S:
+        Gv = S if G is None else G
+        Bd, f, cb = split(Psi, S, by_columns=True)
+    for n, a in enumerate(rows):
+        sig = np.zeros((p, D2))
+        for k in range(L.shape[0]):
+            if S:
+                Ad, e, rb = split(L[k][a:a + 1], S, by_columns=False)
+                T = recombine(pair_products(Ad, Bd, Gv), e, f, rb, cb)
+            else:
+                T = dgemm_fp64(L[k][a:a + 1], Psi)
+            sig = gemm(T.reshape(p, D2), R[k], S, G, alpha=1.0, beta=1.0, C=sig, transb="T")
+        out[n] = sig
+    return out
+
+
+def heff_sparse(prob, S: int = 0, G: int | None = None) -> dict:
+    """Block-sparse sigma: for each triple (op, lo, li, ri, ro, alpha) in list order,
+    T = L[op][lo, li] psi[li, ri] and sigma[lo, ro] = fma(alpha, T R[op][ro, ri]^T, sigma[lo, ro]).
+
+    sigma blocks start at +0 (blocks that no triple reaches stay zero).
+    """
+    sigma = {b: np.zeros((int(prob.dims[b[0]]), int(prob.dims[b[1]]))) for b in prob.psi_blocks}
+    for (op, lo, li, ri, ro, alpha) in prob.triples:
+        T = gemm(prob.L[(op, lo, li)], prob.psi[(li, ri)], S, G)
+        sigma[(lo, ro)] = gemm(T, prob.R[(op, ro, ri)], S, G, alpha=alpha, beta=1.0,
+                               C=sigma[(lo, ro)], transb="T")
+    return sigma
+
+
+# ----------------------------------------------------------------------------
+# Davidson (lowest eigenpair) with a diagonal preconditioner
+# ----------------------------------------------------------------------------
+def davidson(matvec, hdiag, x0, m_max: int = 32, tol: float = 1e-8, max_iter: int = 300,
+             stall_window: int = 20, trace=None):
+    """Lowest eigenpair of the symmetric operator ``matvec``.
+
+    Start: v0 = x0 / |x0|, w0 = H v0, G = [v0.w0].  Each step:
+      1. Rayleigh-Ritz: lowest eigenpair (theta, y) of the projected m x m
+         matrix (numpy eigh), sign fixed so the largest |y_i| is positive;
+      2. x = V y, hx = W y, r = hx - theta x, rho = |r|;
+      3. stop (converged) when rho <= tol;
+      4. correction t = r / (hdiag - theta), denominators below 1e-8 in
+         magnitude replaced by +-1e-8;
+      5. if the basis is full (m = m_max) collapse it to [x] (W to [hx]);
+      6. orthogonalise t twice against the basis (classical Gram-Schmidt), fall
+         back to r when |t| < 1e-10, normalise;
+      7. w = H t; new column G[i, m] = G[m, i] = v_i . w; m += 1.
+    Stagnation: after more than ``stall_window`` steps, stop when the smallest
+    residual of the last ``stall_window`` steps exceeds half the smallest before.
+    Returns (theta, x, status, iterations, residual history).
+    """
+    hdiag = np.asarray(hdiag, dtype=np.float64).ravel()
+    n = hdiag.size
+    V = np.zeros((m_max, n))
+    W = np.zeros((m_max, n))
+    Gm = np.zeros((m_max, m_max))
+    v = np.asarray(x0, dtype=np.float64).ravel().copy()
+    v /= np.linalg.norm(v)
+    V[0] = v
+    W[0] = matvec(v)
+    Gm[0, 0] = V[0] @ W[0]
+    m = 1
+    hist = []
+    theta, x = 0.0, v
+    for it in range(1, max_iter + 1):
+        evals, evecs = np.linalg.eigh(Gm[:m, :m])
+        theta = float(evals[0])
+        y = evecs[:, 0]
+        if y[np.argmax(np.abs(y))] < 0:
+            y = -y
+        x = y @ V[:m]
+        hx = y @ W[:m]
+        r = hx - theta * x
+        rho = float(np.linalg.norm(r))
+        hist.append(rho)
+        if trace is not None:
+            trace(it, theta, rho, m)
+        if rho <= tol:
+            return theta, x, CONVERGED, it, hist
+        if len(hist) > stall_window and min(hist[-stall_window:]) > 0.5 * min(hist[:-stall_window]):
+            return theta, x, STAGNATED, it, hist
+        den = hdiag - theta
+        den = np.where(np.abs(den) < 1e-8, np.copysign(1e-8, den), den)
+        t = r / den
+        if m == m_max:
+            V[0] = x
+            W[0] = hx
+            Gm[:, :] = 0.0
+            Gm[0, 0] = theta
+            m = 1
+        for _ in range(2):
+            t = t - (V[:m] @ t) @ V[:m]
+        if np.linalg.norm(t) < 1e-10:
+            t = r.copy()
+            for _ in range(2):
+                t = t - (V[:m] @ t) @ V[:m]
+        t /= np.linalg.norm(t)
+        V[m] = t
+        W[m] = matvec(t)
+        col = V[:m + 1] @ W[m]
+        Gm[:m + 1, m] = col
+        Gm[m, :m + 1] = col
+        m += 1
+    return theta, x, MAX_ITER, max_iter, hist
+
+
+def heff_matvec(L, R, diag=None, S: int = 0, G: int | None = None):
+    """x (length D^2) -> sigma (length D^2) for phys = 1, via heff_dense."""
+    D = L.shape[1]
+
+    def mv(x):
+        s = heff_dense(L, R, np.asarray(x).reshape(D, 1, D), S, G,
+                       None if diag is None else np.asarray(diag).reshape(D, 1, D))
+        return s.ravel()
+    return mv
