@@ -1,0 +1,232 @@
+/*
+ * ozaki.h - emulated-FP64 (Ozaki scheme) GEMM, two-site H_eff.psi and a
+ * Davidson eigensolver step on AMD Instinct MI355X (gfx950).
+ *
+ * Method (arXiv 2510.04795, "Theory of emulated FP64 arithmetic"): for
+ * C = A B, (1) convert A and B to fixed point with one power-of-two exponent
+ * per row of A and per column of B, (2) split both into S int8 slices,
+ * (3) multiply slice pairs exactly in low precision (int8 MFMA, int32
+ * accumulation), (4) accumulate the pair products and convert back to FP64.
+ * The slice count follows "Numerical procedure": S slices carry 8S - 1
+ * mantissa bits plus the sign, S = ceildiv(bits + 1, 8).
+ *
+ * Conventions shared by every entry point
+ *  - Matrices are FP64, row-major, with a leading dimension (elements).
+ *    Matrix and vector pointers are DEVICE pointers owned by the caller
+ *    unless stated otherwise.
+ *  - stream is a hipStream_t passed as void* (NULL = the null stream).
+ *    Enqueue calls (ozaki_dgemm, heff_apply) are asynchronous, allocate
+ *    nothing and never synchronise, so they can be captured in a hipGraph.
+ *    *_create calls may allocate and synchronise; *_destroy frees what the
+ *    matching *_create allocated.
+ *  - Every call returns an int status (OZ_*): 0 success, > 0 informational,
+ *    < 0 error.  No exception crosses this interface.  The text of the last
+ *    error raised on the calling host thread is ozaki_last_error().
+ *  - An ozaki_ctx (and every plan made from it) is bound to one device and
+ *    must be used by one host thread at a time.
+ *  - Emulated arithmetic: S = slices in [2, 8]; G = ndiag diagonals of the
+ *    S x S slice-pair grid are kept (pairs with s + t < G).  ndiag = 0 means
+ *    G = S (drop the less significant lower triangle); the accepted values
+ *    are G in {S, S + 1, 2S - 1} (2S - 1 keeps all S^2 pairs).  slices = 0
+ *    selects the native FP64 MFMA path where an entry point offers it.
+ *  - Results of the emulated path are deterministic and independent of the
+ *    launch configuration: integer pair products are exact, the FP64
+ *    recombination runs in one fixed order per output element.
+ *  - A row of op(A) or a column of op(B) that holds a NaN or an Inf makes
+ *    the matching row / column of the result NaN and sets the sticky
+ *    OZ_FLAG_NONFINITE bit of the context (ozaki_ctx_flags).
+ */
+#ifndef OZAKI_H
+#define OZAKI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define OZ_OK 0
+#define OZ_CONVERGED 1        /* davidson_step: residual norm <= tol          */
+#define OZ_STAGNATED 2        /* davidson_step: residual stopped decreasing   */
+#define OZ_MAX_ITER 3         /* davidson_step: iteration limit reached       */
+#define OZ_ERR_ARG (-1)       /* invalid argument (message in ozaki_last_error) */
+#define OZ_ERR_WORKSPACE (-2) /* workspace missing or too small               */
+#define OZ_ERR_HIP (-3)       /* HIP runtime error (no device, launch failure) */
+#define OZ_ERR_UNSUPPORTED (-4) /* valid request this build does not provide  */
+#define OZ_ERR_STATE (-5)     /* object used in the wrong state               */
+#define OZ_ERR_NOMEM (-6)     /* device or host allocation failed             */
+
+#define OZ_FLAG_NONFINITE 1u  /* some input row/column held NaN or Inf        */
+
+/* Exponent reported by ozaki_split for a row/column holding NaN or Inf. */
+#define OZ_EXP_NONFINITE INT32_MIN
+
+typedef struct ozaki_ctx_s *ozaki_ctx;
+typedef struct heff_plan_s *heff_plan;
+typedef struct davidson_s *davidson;
+
+/* Text for a status code (static storage). */
+const char *ozaki_status_string(int status);
+/* Text of the last error on this host thread ("" if none). */
+const char *ozaki_last_error(void);
+/* Library version as major * 10000 + minor * 100 + patch. */
+int ozaki_version(void);
+
+/* ---- context --------------------------------------------------------- */
+/* Bind a context to HIP device `device`.  Allocates a 4-byte flag word on
+ * that device.  OZ_ERR_HIP when the device does not exist. */
+int ozaki_ctx_create(ozaki_ctx *out, int device);
+int ozaki_ctx_destroy(ozaki_ctx ctx);
+/* Read and clear the sticky flags (synchronises the device). */
+int ozaki_ctx_flags(ozaki_ctx ctx, uint32_t *flags_out);
+
+/* ---- parameters ------------------------------------------------------ */
+/* S = ceildiv(mantissa_bits + 1, 8) ("Numerical procedure"); OZ_ERR_ARG if
+ * bits < 1. */
+int ozaki_slices_for_bits(int mantissa_bits);
+/* Number of slice pairs (s, t) with s + t < ndiag (0 -> S); the worked
+ * example of the paper's four-step strategy has 7 x 7 = 49 in full mode.
+ * < 0 for invalid arguments. */
+int ozaki_pair_count(int slices, int ndiag);
+/* Largest inner dimension whose int32 diagonal sums cannot overflow
+ * (every product is at most 2^14 in magnitude); above it ozaki_dgemm
+ * accumulates K-chunks in int64 workspace, with an identical result. */
+int64_t ozaki_max_exact_k(int slices, int ndiag);
+
+/* ---- emulated / native DGEMM ---------------------------------------- */
+/* Workspace (bytes) ozaki_dgemm needs for this problem (0 for slices = 0).
+ * Holds the int8 slices of op(A) and op(B) with their exponents, plus int64
+ * partial sums when K > ozaki_max_exact_k. */
+size_t ozaki_dgemm_workspace_bytes(int64_t M, int64_t N, int64_t K, int slices, int ndiag);
+
+/* C = alpha op(A) op(B) + beta C   ("Theory of emulated FP64 arithmetic").
+ *  transa/transb 'N' or 'T' (row-major BLAS meaning: op(A) is M x K);
+ *  beta == 0: C is not read (may hold NaN);
+ *  slices in [2, 8] (emulated) or 0 (native FP64 MFMA GEMM);
+ *  the emulated output element is
+ *     h = Q_{G-1}; h = h * 2^-8 + Q_g (g = G-2 .. 0), c = h * 2^(e_i + f_j - 14),
+ *     C = alpha * c (beta == 0) or fma(alpha, c, beta * C),
+ *  with Q_g the exact int sum of slice pairs on diagonal g, e_i / f_j the
+ *  shared exponents of row i of op(A) and column j of op(B).
+ *  workspace: device memory of at least ozaki_dgemm_workspace_bytes, 256-byte
+ *  aligned; it may be NULL when that size is 0.  Errors: OZ_ERR_ARG (bad
+ *  sizes, lda/ldb/ldc, trans, slices, ndiag), OZ_ERR_WORKSPACE, OZ_ERR_HIP. */
+int ozaki_dgemm(ozaki_ctx ctx, char transa, char transb, int64_t M, int64_t N, int64_t K,
+                double alpha, const double *A, int64_t lda, const double *B, int64_t ldb,
+                double beta, double *C, int64_t ldc, int slices, int ndiag,
+                void *workspace, size_t workspace_bytes, void *stream);
+
+/* ---- test and debug surface (steps 1-3 on their own) ---------------- */
+/* Steps 1-2: shared exponents and slices of X (rows x cols, row-major, ld).
+ *  by_columns = 0: one exponent per row, digits[S][rows][cols];
+ *  by_columns = 1: one exponent per column, digits[S][cols][rows] (each
+ *  column's digits contiguous, as the B operand is consumed).
+ *  Digits are balanced base 256 (most significant slice first):
+ *  RNE(x 2^(8S-1-e)) = sum_t d_t 256^(S-1-t), d_t in [-128, 127].
+ *  exps gets e per group, OZ_EXP_NONFINITE for a group holding NaN/Inf (its
+ *  digits are 0).  Uses context-owned scratch (may allocate; not for graph
+ *  capture).  Synchronises the stream before returning. */
+int ozaki_split(ozaki_ctx ctx, int by_columns, int64_t rows, int64_t cols, const double *X,
+                int64_t ld, int slices, int8_t *digits, int32_t *exps, void *stream);
+/* Step 3: Q[g][i][j] = sum over kept pairs (s + t = g) and k of
+ * Adig[s][i][k] * BTdig[t][j][k], g < G, as int32 (exact for
+ * K <= ozaki_max_exact_k, else OZ_ERR_ARG).  Adig [S][M][K], BTdig [S][N][K],
+ * Q [G][M][N].  Uses context-owned scratch; synchronises the stream. */
+int ozaki_pair_products(ozaki_ctx ctx, int64_t M, int64_t N, int64_t K, int slices, int ndiag,
+                        const int8_t *Adig, const int8_t *BTdig, int32_t *Q, void *stream);
+
+/* ---- two-site effective Hamiltonian -------------------------------- */
+/* sigma = H_eff psi with H_eff = sum over triples of alpha L_op (x) R_op
+ * restricted to symmetry blocks ("Theory of TNS/DMRG": the update of the
+ * second subroutine diagonalises this operator on the two-site tensor).
+ *
+ * Layout: left sectors with sizes left_dim[n_left], right sectors with
+ * right_dim[n_right], physical dimension phys (16 = d^2 for d = 4, or 1).
+ * psi (and sigma, same layout) is a list of blocks; block b couples left
+ * sector psi_lr[2b] with right sector psi_lr[2b+1] and is stored at element
+ * offset psi_offset[b] as a [left_dim][phys][right_dim] row-major array.
+ * L block i (operator L_key[3i], left sectors (L_key[3i+1], L_key[3i+2]))
+ * is a left_dim x left_dim row-major matrix at L_offset[i] in L_data; R
+ * blocks likewise with right sectors in R_data.  All arrays of the layout
+ * struct are HOST arrays, copied by heff_plan_create.
+ *
+ * Triple t adds alpha * L[op][lo, li] psi[li, ri] R[op][ro, ri]^T to the
+ * sigma block (lo, ro): per physical index j, a left GEMM
+ * T = L[op][lo, li] Psi[li, ri] (Psi: the left_dim x phys*right_dim view),
+ * then sigma' += alpha T' R^T (T', sigma': the left_dim*phys x right_dim
+ * views).  Each sigma block starts at +0 and adds its triples in list order
+ * as sigma = fma(alpha, c, sigma), so results do not depend on scheduling.
+ * A non-null diag (device, laid out like psi) then adds sigma + diag * psi.
+ * Dense two-site H_eff is one left and one right sector of size D, phys 16,
+ * one psi block and triples (k, 0, 0, 0, 0, 1) for k < Kop. */
+typedef struct {
+    int32_t op, lo, li, ri, ro;
+    double alpha;
+} heff_triple;
+
+typedef struct {
+    int32_t n_left, n_right, phys;
+    const int32_t *left_dim;    /* [n_left]  */
+    const int32_t *right_dim;   /* [n_right] */
+    int32_t n_psi_blocks;
+    const int32_t *psi_lr;      /* [2 * n_psi_blocks] */
+    const int64_t *psi_offset;  /* [n_psi_blocks] element offsets */
+    int32_t n_L_blocks;
+    const int32_t *L_key;       /* [3 * n_L_blocks] (op, lo, li) */
+    const int64_t *L_offset;    /* [n_L_blocks] */
+    int32_t n_R_blocks;
+    const int32_t *R_key;       /* [3 * n_R_blocks] (op, ro, ri) */
+    const int64_t *R_offset;    /* [n_R_blocks] */
+} heff_layout;
+
+/* Build a plan.  L_data / R_data / diag are device pointers that must stay
+ * valid and unchanged for the plan's lifetime.  slices in [2, 8] caches the
+ * int8 slices of every L and R block once (the operators are fixed during a
+ * Davidson run); slices = 0 uses the native FP64 MFMA path.  triples is a
+ * host array.  The plan owns every buffer it needs, so heff_apply never
+ * allocates.  Synchronises `stream`. */
+int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *layout,
+                     const double *L_data, const double *R_data, int32_t n_triples,
+                     const heff_triple *triples, const double *diag, int slices, int ndiag,
+                     void *stream);
+/* sigma = H_eff psi (sigma overwritten; psi and sigma must not overlap).
+ * One grouped launch per phase; enqueue only. */
+int heff_apply(heff_plan plan, const double *psi, double *sigma, void *stream);
+/* Total elements of psi for the plan's layout. */
+int64_t heff_vector_length(heff_plan plan);
+/* FP64-equivalent flops of one heff_apply (2 m n k summed over all GEMMs). */
+double heff_flops(heff_plan plan);
+int heff_plan_destroy(heff_plan plan);
+
+/* ---- Davidson eigensolver (lowest eigenpair) ------------------------ */
+/* A standard Davidson iteration with diagonal preconditioner for the
+ * Krylov diagonalisation of the second DMRG subroutine ("Theory of
+ * TNS/DMRG"; convergence threshold on the residual as in "Numerical
+ * procedure").  The matvec is heff_apply of H; orthogonalisation,
+ * Rayleigh-Ritz and the residual run in FP64 on the device.
+ * davidson_create: hdiag = diag(H) and x0 (device, heff_vector_length
+ * elements) are copied; 2 <= m_max <= 64; allocates V and W (m_max vectors
+ * each), normalises x0 and performs the first matvec.
+ * davidson_step: one iteration (Rayleigh-Ritz on the current basis, Ritz
+ * vector and residual, then, unless converged, preconditioned correction,
+ * two classical Gram-Schmidt passes, one matvec).  Synchronises the stream
+ * to fill *info (theta, residual norm, iteration, basis size, status) and
+ * returns OZ_OK while running, or OZ_CONVERGED / OZ_STAGNATED / OZ_MAX_ITER.
+ * davidson_get_vector copies the current Ritz vector (unit norm). */
+typedef struct {
+    double theta, resnorm;
+    int32_t iter, m, status;
+} davidson_info;
+
+int davidson_create(ozaki_ctx ctx, davidson *out, heff_plan H, const double *hdiag,
+                    const double *x0, int m_max, double tol, int max_iter, void *stream);
+int davidson_step(davidson dav, davidson_info *info, void *stream);
+int davidson_get_vector(davidson dav, double *x_out, void *stream);
+int davidson_destroy(davidson dav);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OZAKI_H */

@@ -1,0 +1,143 @@
+// Internal declarations shared by the HIP kernels and the host runtime.
+//
+// Packed slice layout (the operand format of the int8 pair GEMM).  An
+// operand with R rows (rows of op(A), or columns of op(B)) and inner length
+// K is stored as S int8 digit planes, padded to Rp = roundup(R, 32) rows and
+// Kp = roundup(K, 32).  Byte (r, k) of slice s lives at
+//
+//     ((k / 32 * S + s) * 2 + (k / 16) % 2) * Rp * 16 + r * 16 + k % 16
+//
+// i.e. for every 32-wide K block and slice there are two runs of Rp 16-byte
+// chunks.  A run of consecutive rows is contiguous, so a tile load is a
+// straight copy of 2S runs, and the LDS image of a tile (same order) gives
+// each 32x32x32 int8 MFMA operand as 1 KiB read by consecutive lanes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace oz {
+
+constexpr int kKB = 32;      // inner-dimension block of the packed layout
+constexpr int kRowQ = 32;    // row granularity of the packed layout
+constexpr int32_t kExpBad = INT32_MIN;
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+inline int64_t ceil_div(int64_t x, int64_t m) { return (x + m - 1) / m; }
+
+// One product contributing to an output tile: c = ozaki(A rows, B rows), weight alpha.
+struct TermDesc {
+    const int8_t *A;       // packed A operand (rows = rows of op(A))
+    const int32_t *e;      // its row exponents
+    const int8_t *B;       // packed B operand (rows = columns of op(B))
+    const int32_t *f;      // its column exponents
+    int64_t a_rows_p;      // padded row count of A's packed planes
+    int64_t b_rows_p;      // padded row count of B's packed planes
+    int32_t kblocks;       // Kp / 32
+    int32_t pad_;
+    double alpha;
+};
+
+// A BM x BN output tile and the list of terms summed into it.
+struct TileDesc {
+    int32_t term_begin, term_end;
+    int32_t m0, n0;        // tile origin (also the row offsets into A and B)
+    int32_t out;           // index of the output matrix
+    int32_t pad_;
+};
+
+struct OutDesc {
+    double *C;
+    int64_t ldc;
+    int32_t M, N;          // valid extent (stores outside are skipped)
+};
+
+enum PairMode : int32_t {
+    kModeGemm = 0,     // one term; C = alpha*c (beta == 0) or fma(alpha, c, beta*C)
+    kModeAccum = 1,    // term list; sigma = +0, then sigma = fma(alpha_t, c_t, sigma)
+    kModeQ = 2,        // one term; write the int32 diagonal sums Q[g][i][j]
+    kModeQ64 = 3,      // one term over one K chunk; store (qw_first) or add its sums to Qw
+};
+
+struct PairArgs {
+    // grouped launch
+    const TileDesc *tiles;
+    const TermDesc *terms;
+    const OutDesc *outs;
+    int32_t ntiles;
+    // single-GEMM launch (tiles from the grid)
+    int32_t tiles_n;
+    TermDesc term;
+    OutDesc out;
+    int32_t mode;
+    int32_t qw_first;      // kModeQ64: first chunk stores instead of adding
+    double beta;
+    int32_t *Q;            // kModeQ output, [G][M][N]
+    // int64 partial sums [G][tiles_m*BM][tiles_n*BN] of earlier K chunks when
+    // K exceeds the exact int32 range; added in the kModeGemm epilogue if set
+    int64_t *Qw;
+    int64_t qw_ld;         // leading dimension of one Qw plane (tiles_n * BN)
+    int64_t qw_plane;      // elements per Qw plane
+};
+
+// FP64 GEMM term: op(A) (M x K) times op(B) (K x N), both plain FP64.
+struct Term64 {
+    const double *A;
+    const double *B;
+    int64_t lda, ldb;
+    int32_t K;
+    int32_t pad_;
+    double alpha;
+};
+
+struct Dgemm64Args {
+    const TileDesc *tiles;
+    const Term64 *terms;
+    const OutDesc *outs;
+    int32_t ntiles;
+    int32_t tiles_n;
+    Term64 term;
+    OutDesc out;
+    int32_t mode;          // kModeGemm or kModeAccum
+    int32_t pad_;
+    double beta;
+};
+
+// ---- launchers (kernels.hip) -------------------------------------------
+// Shared exponents of each row of X (R x K, row-major, ld): e[r], flag on NaN/Inf.
+hipError_t launch_row_exponents(const double *X, int64_t ld, int64_t R, int64_t K, int32_t *e,
+                                uint32_t *flag, hipStream_t s);
+// Shared exponents of each column of X (K x R, row-major, ld).  part: scratch
+// of col_exponent_scratch(K, R) bytes.
+size_t col_exponent_scratch(int64_t K, int64_t R);
+hipError_t launch_col_exponents(const double *X, int64_t ld, int64_t K, int64_t R, int32_t *e,
+                                double *part, uint32_t *flag, hipStream_t s);
+// Slice X into the packed layout.  trans = false: X is R x K (groups are rows);
+// trans = true: X is K x R (groups are columns).  Pads rows to Rp, K to Kp with 0.
+hipError_t launch_slice(int S, bool trans, const double *X, int64_t ld, int64_t R, int64_t K,
+                        const int32_t *e, int8_t *packed, int64_t Rp, hipStream_t s);
+// Debug conversions between [S][R][K] digits and the packed layout.
+hipError_t launch_pack(int S, const int8_t *canon, int64_t R, int64_t K, int8_t *packed,
+                       int64_t Rp, hipStream_t s);
+hipError_t launch_unpack(int S, const int8_t *packed, int64_t Rp, int64_t R, int64_t K,
+                         int8_t *canon, hipStream_t s);
+
+// Tile shape of the int8 pair GEMM for (S, G).
+struct PairShape { int bm, bn; };
+PairShape pair_shape(int S, int G);
+bool pair_supported(int S, int G);
+hipError_t launch_pair_single(int S, int G, const PairArgs &a, int tiles_m, hipStream_t s);
+hipError_t launch_pair_grouped(int S, int G, const PairArgs &a, int grid, hipStream_t s);
+
+// FP64 MFMA GEMM.
+PairShape dgemm_shape();
+hipError_t launch_dgemm_single(bool ta, bool tb, const Dgemm64Args &a, int tiles_m,
+                               hipStream_t s);
+hipError_t launch_dgemm_grouped(bool tb, const Dgemm64Args &a, int grid, hipStream_t s);
+
+// sigma[i] = sigma[i] + diag[i] * psi[i] (two roundings), i < n.
+hipError_t launch_diag_axpy(const double *diag, const double *psi, double *sigma, int64_t n,
+                            hipStream_t s);
+
+}  // namespace oz

@@ -1,0 +1,6 @@
+// Pair-GEMM kernels for S = 8 slices (G = S, S + 1, 2S - 1).
+#include "pairgemm_impl.h"
+
+namespace oz {
+OZ_DEFINE_PAIR_S(8)
+}  // namespace oz

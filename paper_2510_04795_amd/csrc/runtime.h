@@ -1,0 +1,37 @@
+// Host-side internals shared by the runtime translation units.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/ozaki.h"
+#include "internal.h"
+
+struct ozaki_ctx_s {
+    int device = 0;
+    int num_cu = 0;
+    uint32_t *d_flags = nullptr;  // sticky OZ_FLAG_* bits on the device
+    void *scratch = nullptr;      // grow-only scratch of the debug entry points
+    size_t scratch_bytes = 0;
+};
+
+namespace oz {
+
+int fail(int code, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+bool valid_sg(int S, int G);
+int resolve_ndiag(int S, int ndiag);
+int64_t max_exact_k(int S, int G);
+size_t align256(size_t x);
+int ctx_scratch(ozaki_ctx ctx, size_t bytes);
+
+// Byte offsets inside the ozaki_dgemm workspace.
+struct GemmWorkspace {
+    size_t a_dig, b_dig, e, f, part, qw, total;
+};
+GemmWorkspace gemm_workspace(int64_t M, int64_t N, int64_t K, int S, int G);
+
+hipError_t slice_operand(int S, bool by_rows, const double *X, int64_t ld, int64_t R, int64_t K,
+                         int32_t *e, int8_t *packed, double *part, uint32_t *flag, hipStream_t s);
+
+}  // namespace oz

@@ -1,0 +1,359 @@
+// C-ABI of libozaki: context, argument checking, workspace layout and the
+// GEMM-level entry points.  The effective-Hamiltonian plans live in heff.hip,
+// the Davidson solver in davidson.hip.
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/ozaki.h"
+#include "internal.h"
+#include "runtime.h"
+
+namespace oz {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(OZ_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool valid_sg(int S, int G) { return pair_supported(S, G); }
+
+int resolve_ndiag(int S, int ndiag) { return ndiag == 0 ? S : ndiag; }
+
+int64_t max_exact_k(int S, int G) {
+    const int nmax = G < S ? G : S;  // most pairs on one kept diagonal
+    return static_cast<int64_t>(2147483647LL / (static_cast<int64_t>(nmax) << 14));
+}
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+GemmWorkspace gemm_workspace(int64_t M, int64_t N, int64_t K, int S, int G) {
+    GemmWorkspace w{};
+    if (S == 0) return w;
+    const int64_t Mp = round_up(M, kRowQ), Np = round_up(N, kRowQ), Kp = round_up(K, kKB);
+    size_t off = 0;
+    w.a_dig = off; off += align256(static_cast<size_t>(S) * Mp * Kp);
+    w.b_dig = off; off += align256(static_cast<size_t>(S) * Np * Kp);
+    w.e = off; off += align256(sizeof(int32_t) * (Mp > 0 ? Mp : 1));
+    w.f = off; off += align256(sizeof(int32_t) * (Np > 0 ? Np : 1));
+    w.part = off; off += align256(col_exponent_scratch(K, M > N ? M : N));
+    w.qw = off;
+    if (K > max_exact_k(S, G)) {
+        const PairShape sh = pair_shape(S, G);
+        const int64_t mt = round_up(M, sh.bm), nt = round_up(N, sh.bn);
+        off += align256(sizeof(int64_t) * static_cast<size_t>(G) * mt * nt);
+    }
+    w.total = off;
+    return w;
+}
+
+// Exponents + slices of op(X) as an operand with R rows (groups) and inner K.
+// by_rows: the groups are rows of the stored matrix (stored R x K), else its
+// columns (stored K x R).
+hipError_t slice_operand(int S, bool by_rows, const double *X, int64_t ld, int64_t R, int64_t K,
+                         int32_t *e, int8_t *packed, double *part, uint32_t *flag, hipStream_t s) {
+    hipError_t err;
+    if (by_rows)
+        err = launch_row_exponents(X, ld, R, K, e, flag, s);
+    else
+        err = launch_col_exponents(X, ld, K, R, e, part, flag, s);
+    if (err != hipSuccess) return err;
+    return launch_slice(S, !by_rows, X, ld, R, K, e, packed, round_up(R, kRowQ), s);
+}
+
+}  // namespace oz
+
+using namespace oz;
+
+extern "C" {
+
+const char *ozaki_status_string(int status) {
+    switch (status) {
+        case OZ_OK: return "ok";
+        case OZ_CONVERGED: return "converged";
+        case OZ_STAGNATED: return "stagnated";
+        case OZ_MAX_ITER: return "maximum iterations reached";
+        case OZ_ERR_ARG: return "invalid argument";
+        case OZ_ERR_WORKSPACE: return "workspace missing or too small";
+        case OZ_ERR_HIP: return "HIP runtime error";
+        case OZ_ERR_UNSUPPORTED: return "unsupported";
+        case OZ_ERR_STATE: return "invalid state";
+        case OZ_ERR_NOMEM: return "out of memory";
+        default: return "unknown status";
+    }
+}
+
+const char *ozaki_last_error(void) { return g_last_error.c_str(); }
+
+int ozaki_version(void) { return 10000; }
+
+int ozaki_ctx_create(ozaki_ctx *out, int device) {
+    if (!out) return fail(OZ_ERR_ARG, "ozaki_ctx_create: out is NULL");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n == 0) return fail(OZ_ERR_HIP, "ozaki_ctx_create: no HIP device");
+    if (device < 0 || device >= n) return fail(OZ_ERR_ARG, "ozaki_ctx_create: device %d of %d", device, n);
+    if ((e = hipSetDevice(device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+    auto *c = new ozaki_ctx_s();
+    c->device = device;
+    hipDeviceProp_t prop;
+    if ((e = hipGetDeviceProperties(&prop, device)) != hipSuccess) {
+        delete c;
+        return hip_fail(e, "hipGetDeviceProperties");
+    }
+    c->num_cu = prop.multiProcessorCount;
+    if ((e = hipMalloc(&c->d_flags, sizeof(uint32_t))) != hipSuccess) {
+        delete c;
+        return hip_fail(e, "hipMalloc(flags)");
+    }
+    if ((e = hipMemset(c->d_flags, 0, sizeof(uint32_t))) != hipSuccess) {
+        hipFree(c->d_flags);
+        delete c;
+        return hip_fail(e, "hipMemset(flags)");
+    }
+    *out = c;
+    return OZ_OK;
+}
+
+int ozaki_ctx_destroy(ozaki_ctx ctx) {
+    if (!ctx) return OZ_OK;
+    hipSetDevice(ctx->device);
+    hipDeviceSynchronize();
+    if (ctx->scratch) hipFree(ctx->scratch);
+    if (ctx->d_flags) hipFree(ctx->d_flags);
+    delete ctx;
+    return OZ_OK;
+}
+
+int ozaki_ctx_flags(ozaki_ctx ctx, uint32_t *flags_out) {
+    if (!ctx || !flags_out) return fail(OZ_ERR_ARG, "ozaki_ctx_flags: NULL argument");
+    hipError_t e;
+    if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    uint32_t v = 0;
+    if ((e = hipMemcpy(&v, ctx->d_flags, sizeof(v), hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "hipMemcpy(flags)");
+    if ((e = hipMemset(ctx->d_flags, 0, sizeof(uint32_t))) != hipSuccess) return hip_fail(e, "hipMemset");
+    *flags_out = v;
+    return OZ_OK;
+}
+
+int ozaki_slices_for_bits(int mantissa_bits) {
+    if (mantissa_bits < 1) return fail(OZ_ERR_ARG, "ozaki_slices_for_bits: bits = %d", mantissa_bits);
+    return (mantissa_bits + 1 + 7) / 8;
+}
+
+int ozaki_pair_count(int slices, int ndiag) {
+    if (slices < 1 || slices > 8) return fail(OZ_ERR_ARG, "slices = %d", slices);
+    const int G = resolve_ndiag(slices, ndiag);
+    if (G < 1 || G > 2 * slices - 1) return fail(OZ_ERR_ARG, "ndiag = %d", ndiag);
+    int n = 0;
+    for (int s = 0; s < slices; ++s)
+        for (int t = 0; t < slices; ++t)
+            if (s + t < G) ++n;
+    return n;
+}
+
+int64_t ozaki_max_exact_k(int slices, int ndiag) {
+    if (slices < 1 || slices > 8) return fail(OZ_ERR_ARG, "slices = %d", slices);
+    const int G = resolve_ndiag(slices, ndiag);
+    if (G < 1 || G > 2 * slices - 1) return fail(OZ_ERR_ARG, "ndiag = %d", ndiag);
+    return max_exact_k(slices, G);
+}
+
+size_t ozaki_dgemm_workspace_bytes(int64_t M, int64_t N, int64_t K, int slices, int ndiag) {
+    if (slices == 0 || M < 0 || N < 0 || K < 0) return 0;
+    if (slices < 2 || slices > 8) return 0;
+    return gemm_workspace(M, N, K, slices, resolve_ndiag(slices, ndiag)).total;
+}
+
+int ozaki_dgemm(ozaki_ctx ctx, char transa, char transb, int64_t M, int64_t N, int64_t K,
+                double alpha, const double *A, int64_t lda, const double *B, int64_t ldb,
+                double beta, double *C, int64_t ldc, int slices, int ndiag, void *workspace,
+                size_t workspace_bytes, void *stream) {
+    if (!ctx) return fail(OZ_ERR_ARG, "ozaki_dgemm: ctx is NULL");
+    const bool ta = (transa == 'T' || transa == 't');
+    const bool tb = (transb == 'T' || transb == 't');
+    if (!ta && transa != 'N' && transa != 'n') return fail(OZ_ERR_ARG, "ozaki_dgemm: transa '%c'", transa);
+    if (!tb && transb != 'N' && transb != 'n') return fail(OZ_ERR_ARG, "ozaki_dgemm: transb '%c'", transb);
+    if (M < 0 || N < 0 || K < 0) return fail(OZ_ERR_ARG, "ozaki_dgemm: negative size");
+    if (M > INT32_MAX / 2 || N > INT32_MAX / 2 || K > INT32_MAX / 2)
+        return fail(OZ_ERR_ARG, "ozaki_dgemm: dimension above 2^30");
+    const int64_t a_cols = ta ? M : K, b_cols = tb ? K : N;
+    if (lda < (a_cols > 1 ? a_cols : 1)) return fail(OZ_ERR_ARG, "ozaki_dgemm: lda = %lld", (long long)lda);
+    if (ldb < (b_cols > 1 ? b_cols : 1)) return fail(OZ_ERR_ARG, "ozaki_dgemm: ldb = %lld", (long long)ldb);
+    if (ldc < (N > 1 ? N : 1)) return fail(OZ_ERR_ARG, "ozaki_dgemm: ldc = %lld", (long long)ldc);
+    if (slices != 0 && (slices < 2 || slices > 8)) return fail(OZ_ERR_ARG, "ozaki_dgemm: slices = %d", slices);
+    const int G = slices ? resolve_ndiag(slices, ndiag) : 0;
+    if (slices && !valid_sg(slices, G))
+        return fail(OZ_ERR_ARG, "ozaki_dgemm: ndiag = %d for slices = %d (use S, S+1 or 2S-1)", ndiag, slices);
+    if (M == 0 || N == 0) return OZ_OK;
+    if (!C) return fail(OZ_ERR_ARG, "ozaki_dgemm: C is NULL");
+    if (K > 0 && (!A || !B)) return fail(OZ_ERR_ARG, "ozaki_dgemm: A or B is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+
+    if (slices == 0) {
+        const PairShape sh = dgemm_shape();
+        Dgemm64Args a{};
+        a.tiles_n = static_cast<int32_t>(ceil_div(N, sh.bn));
+        a.term = Term64{A, B, lda, ldb, static_cast<int32_t>(K), 0, alpha};
+        a.out = OutDesc{C, ldc, static_cast<int32_t>(M), static_cast<int32_t>(N)};
+        a.mode = kModeGemm;
+        a.beta = beta;
+        e = launch_dgemm_single(ta, tb, a, static_cast<int>(ceil_div(M, sh.bm)), s);
+        return e == hipSuccess ? OZ_OK : hip_fail(e, "ozaki_dgemm (fp64) launch");
+    }
+
+    const GemmWorkspace w = gemm_workspace(M, N, K, slices, G);
+    if (workspace_bytes < w.total || (w.total > 0 && !workspace))
+        return fail(OZ_ERR_WORKSPACE, "ozaki_dgemm: workspace %zu bytes, need %zu", workspace_bytes, w.total);
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+        return fail(OZ_ERR_WORKSPACE, "ozaki_dgemm: workspace not 256-byte aligned");
+    char *ws = static_cast<char *>(workspace);
+    int8_t *adig = reinterpret_cast<int8_t *>(ws + w.a_dig);
+    int8_t *bdig = reinterpret_cast<int8_t *>(ws + w.b_dig);
+    int32_t *ev = reinterpret_cast<int32_t *>(ws + w.e);
+    int32_t *fv = reinterpret_cast<int32_t *>(ws + w.f);
+    double *part = reinterpret_cast<double *>(ws + w.part);
+    const int64_t Mp = round_up(M, kRowQ), Np = round_up(N, kRowQ), Kp = round_up(K, kKB);
+
+    // op(A) rows are stored rows when transa = 'N'; op(B) columns are stored rows when transb = 'T'
+    if ((e = slice_operand(slices, !ta, A, lda, M, K, ev, adig, part, ctx->d_flags, s)) != hipSuccess)
+        return hip_fail(e, "ozaki_dgemm: slicing A");
+    if ((e = slice_operand(slices, tb, B, ldb, N, K, fv, bdig, part, ctx->d_flags, s)) != hipSuccess)
+        return hip_fail(e, "ozaki_dgemm: slicing B");
+
+    const PairShape sh = pair_shape(slices, G);
+    PairArgs a{};
+    a.tiles_n = static_cast<int32_t>(ceil_div(N, sh.bn));
+    const int tiles_m = static_cast<int>(ceil_div(M, sh.bm));
+    a.term = TermDesc{adig, ev, bdig, fv, Mp, Np, static_cast<int32_t>(Kp / kKB), 0, alpha};
+    a.out = OutDesc{C, ldc, static_cast<int32_t>(M), static_cast<int32_t>(N)};
+    a.mode = kModeGemm;
+    a.beta = beta;
+    const int64_t kmax = max_exact_k(slices, G);
+    if (K > kmax) {
+        // exact int32 sums per K chunk, carried between chunk launches in int64
+        const int64_t chunk = kmax / kKB;
+        const int64_t nkb = Kp / kKB;
+        a.qw_ld = static_cast<int64_t>(a.tiles_n) * sh.bn;
+        a.qw_plane = a.qw_ld * static_cast<int64_t>(tiles_m) * sh.bm;
+        int64_t *qw = reinterpret_cast<int64_t *>(ws + w.qw);
+        for (int64_t kb0 = 0; kb0 < nkb; kb0 += chunk) {
+            const int64_t n = nkb - kb0 < chunk ? nkb - kb0 : chunk;
+            PairArgs c = a;
+            c.term.A = adig + kb0 * 2 * slices * Mp * 16;
+            c.term.B = bdig + kb0 * 2 * slices * Np * 16;
+            c.term.kblocks = static_cast<int32_t>(n);
+            const bool last = kb0 + n >= nkb;
+            c.mode = last ? kModeGemm : kModeQ64;
+            c.qw_first = kb0 == 0;
+            c.Qw = qw;
+            if ((e = launch_pair_single(slices, G, c, tiles_m, s)) != hipSuccess)
+                return hip_fail(e, "ozaki_dgemm: pair GEMM launch (chunked)");
+        }
+        return OZ_OK;
+    }
+    e = launch_pair_single(slices, G, a, tiles_m, s);
+    return e == hipSuccess ? OZ_OK : hip_fail(e, "ozaki_dgemm: pair GEMM launch");
+}
+
+int ozaki_split(ozaki_ctx ctx, int by_columns, int64_t rows, int64_t cols, const double *X,
+                int64_t ld, int slices, int8_t *digits, int32_t *exps, void *stream) {
+    if (!ctx) return fail(OZ_ERR_ARG, "ozaki_split: ctx is NULL");
+    if (slices < 2 || slices > 8) return fail(OZ_ERR_ARG, "ozaki_split: slices = %d", slices);
+    if (rows < 0 || cols < 0 || ld < (cols > 1 ? cols : 1)) return fail(OZ_ERR_ARG, "ozaki_split: bad shape");
+    if (rows == 0 || cols == 0) return OZ_OK;
+    if (!X || !digits || !exps) return fail(OZ_ERR_ARG, "ozaki_split: NULL pointer");
+    const int64_t R = by_columns ? cols : rows;
+    const int64_t K = by_columns ? rows : cols;
+    const int64_t Rp = round_up(R, kRowQ), Kp = round_up(K, kKB);
+    hipError_t e;
+    if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+    const size_t need = align256(static_cast<size_t>(slices) * Rp * Kp) + col_exponent_scratch(K, R);
+    int rc = ctx_scratch(ctx, need);
+    if (rc != OZ_OK) return rc;
+    int8_t *packed = static_cast<int8_t *>(ctx->scratch);
+    double *part = reinterpret_cast<double *>(static_cast<char *>(ctx->scratch) +
+                                              align256(static_cast<size_t>(slices) * Rp * Kp));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((e = slice_operand(slices, !by_columns, X, ld, R, K, exps, packed, part, ctx->d_flags, s)) != hipSuccess)
+        return hip_fail(e, "ozaki_split: slicing");
+    if ((e = launch_unpack(slices, packed, Rp, R, K, digits, s)) != hipSuccess)
+        return hip_fail(e, "ozaki_split: unpack");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "ozaki_split: sync");
+    return OZ_OK;
+}
+
+int ozaki_pair_products(ozaki_ctx ctx, int64_t M, int64_t N, int64_t K, int slices, int ndiag,
+                        const int8_t *Adig, const int8_t *BTdig, int32_t *Q, void *stream) {
+    if (!ctx) return fail(OZ_ERR_ARG, "ozaki_pair_products: ctx is NULL");
+    if (slices < 2 || slices > 8) return fail(OZ_ERR_ARG, "ozaki_pair_products: slices = %d", slices);
+    const int G = resolve_ndiag(slices, ndiag);
+    if (!valid_sg(slices, G)) return fail(OZ_ERR_ARG, "ozaki_pair_products: ndiag = %d", ndiag);
+    if (M < 0 || N < 0 || K < 0) return fail(OZ_ERR_ARG, "ozaki_pair_products: negative size");
+    if (K > max_exact_k(slices, G))
+        return fail(OZ_ERR_ARG, "ozaki_pair_products: K = %lld exceeds the exact int32 range %lld",
+                    (long long)K, (long long)max_exact_k(slices, G));
+    if (M == 0 || N == 0) return OZ_OK;
+    if (!Q || (K > 0 && (!Adig || !BTdig))) return fail(OZ_ERR_ARG, "ozaki_pair_products: NULL pointer");
+    const int64_t Mp = round_up(M, kRowQ), Np = round_up(N, kRowQ), Kp = round_up(K, kKB);
+    hipError_t e;
+    if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+    const size_t asz = align256(static_cast<size_t>(slices) * Mp * Kp);
+    const size_t bsz = align256(static_cast<size_t>(slices) * Np * Kp);
+    int rc = ctx_scratch(ctx, asz + bsz + 256);
+    if (rc != OZ_OK) return rc;
+    int8_t *pa = static_cast<int8_t *>(ctx->scratch);
+    int8_t *pb = pa + asz;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((e = launch_pack(slices, Adig, M, K, pa, Mp, s)) != hipSuccess) return hip_fail(e, "pack A");
+    if ((e = launch_pack(slices, BTdig, N, K, pb, Np, s)) != hipSuccess) return hip_fail(e, "pack B");
+    const PairShape sh = pair_shape(slices, G);
+    PairArgs a{};
+    a.tiles_n = static_cast<int32_t>(ceil_div(N, sh.bn));
+    a.term = TermDesc{pa, nullptr, pb, nullptr, Mp, Np, static_cast<int32_t>(Kp / kKB), 0, 1.0};
+    a.out = OutDesc{nullptr, 0, static_cast<int32_t>(M), static_cast<int32_t>(N)};
+    a.mode = kModeQ;
+    a.Q = Q;
+    if ((e = launch_pair_single(slices, G, a, static_cast<int>(ceil_div(M, sh.bm)), s)) != hipSuccess)
+        return hip_fail(e, "ozaki_pair_products: launch");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "ozaki_pair_products: sync");
+    return OZ_OK;
+}
+
+}  // extern "C"
+
+namespace oz {
+int ctx_scratch(ozaki_ctx ctx, size_t bytes) {
+    if (ctx->scratch_bytes >= bytes) return OZ_OK;
+    hipError_t e;
+    if (ctx->scratch) {
+        if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+        hipFree(ctx->scratch);
+        ctx->scratch = nullptr;
+        ctx->scratch_bytes = 0;
+    }
+    if ((e = hipMalloc(&ctx->scratch, bytes)) != hipSuccess)
+        return fail(OZ_ERR_NOMEM, "scratch of %zu bytes: %s", bytes, hipGetErrorString(e));
+    ctx->scratch_bytes = bytes;
+    return OZ_OK;
+}
+}  // namespace oz

@@ -1,0 +1,274 @@
+// Steps 1 and 2 of the emulated GEMM ("Theory of emulated FP64 arithmetic"):
+// one power-of-two exponent per row of A / column of B, then S balanced
+// int8 slices per element, written in the packed layout of internal.h.
+//
+// All three kernels are HBM-bound: the exponent pass reads X once (8 B per
+// element); the slice pass reads it again and writes S bytes per element.
+#include "internal.h"
+
+namespace oz {
+namespace {
+
+// Exponent e of a group whose largest magnitude is mu: with mu = m 2^E,
+// m in [0.5, 1), e = E + [m > 127/128], so |x| 2^(8S-1-e) <= 127 256^(S-1)
+// and the leading slice fits in int8.  Computed from the bit pattern.
+__device__ inline int32_t shared_exponent(double mu) {
+    if (mu == 0.0) return 0;
+    const uint64_t b = static_cast<uint64_t>(__double_as_longlong(mu));
+    const int be = static_cast<int>((b >> 52) & 0x7ff);
+    const uint64_t fr = b & ((1ull << 52) - 1);
+    if (be != 0) return be - 1022 + (fr > (63ull << 46) ? 1 : 0);
+    // subnormal: mu = fr 2^-1074 with top bit p; frexp gives E = p - 1073, m = fr / 2^(p+1)
+    const int p = 63 - __clzll(static_cast<long long>(fr));
+    return p - 1073 + ((fr << 7) > (127ull << (p + 1)) ? 1 : 0);
+}
+
+// |x| for a finite x, NaN for NaN or +-Inf (marks the group as non-finite).
+__device__ inline double abs_or_nan(double x) {
+    if (!(fabs(x) <= 1.79769313486231570815e308)) return __longlong_as_double(0x7ff8000000000000ll);
+    return fabs(x);
+}
+
+// Maximum that propagates NaN from either side.
+__device__ inline double combine_max(double a, double b) {
+    if (a != a || b != b) return __longlong_as_double(0x7ff8000000000000ll);
+    return a > b ? a : b;
+}
+
+__device__ inline int32_t finish_exponent(double mu, uint32_t *flag) {
+    if (mu != mu) {
+        atomicOr(flag, 1u);
+        return kExpBad;
+    }
+    return shared_exponent(mu);
+}
+
+// One wave per row; 4 rows per 256-thread block.
+__global__ __launch_bounds__(256) void k_row_exponents(const double *__restrict__ X, int64_t ld,
+                                                        int64_t R, int64_t K,
+                                                        int32_t *__restrict__ e,
+                                                        uint32_t *flag) {
+    const int lane = threadIdx.x & 63;
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (r >= R) return;
+    const double *row = X + r * ld;
+    double mu = 0.0;
+    for (int64_t k = lane; k < K; k += 64) mu = combine_max(mu, abs_or_nan(row[k]));
+    for (int off = 32; off >= 1; off >>= 1) mu = combine_max(mu, __shfl_xor(mu, off, 64));
+    if (lane == 0) e[r] = finish_exponent(mu, flag);
+}
+
+// Column maxima of X (K x R): block (column strip of 256, row chunk of 256).
+constexpr int kColChunk = 256;
+
+__global__ __launch_bounds__(256) void k_col_partial(const double *__restrict__ X, int64_t ld,
+                                                      int64_t K, int64_t R,
+                                                      double *__restrict__ part) {
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (c >= R) return;
+    const int64_t k0 = static_cast<int64_t>(blockIdx.y) * kColChunk;
+    const int64_t k1 = k0 + kColChunk < K ? k0 + kColChunk : K;
+    double mu = 0.0;
+    for (int64_t k = k0; k < k1; ++k) mu = combine_max(mu, abs_or_nan(X[k * ld + c]));
+    part[static_cast<int64_t>(blockIdx.y) * R + c] = mu;
+}
+
+__global__ __launch_bounds__(256) void k_col_final(const double *__restrict__ part, int64_t nchunk,
+                                                    int64_t R, int32_t *__restrict__ e,
+                                                    uint32_t *flag) {
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (c >= R) return;
+    double mu = 0.0;
+    for (int64_t q = 0; q < nchunk; ++q) mu = combine_max(mu, part[q * R + c]);
+    e[c] = finish_exponent(mu, flag);
+}
+
+// Balanced base-256 digits of RNE(x 2^(8S-1-e)), most significant first, as
+// bytes of four consecutive elements packed into one word per slice.
+template <int S>
+__device__ inline void slice4(const double (&x)[4], int32_t e, uint32_t (&w)[S]) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) w[s] = 0;
+    if (e == kExpBad) return;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        long long X = static_cast<long long>(rint(ldexp(x[q], 8 * S - 1 - e)));
+        int d[S];
+#pragma unroll
+        for (int t = S - 1; t >= 1; --t) {
+            d[t] = static_cast<int>((X + 128) & 255) - 128;
+            X = (X - d[t]) >> 8;
+        }
+        d[0] = static_cast<int>(X);
+#pragma unroll
+        for (int s = 0; s < S; ++s) w[s] |= (static_cast<uint32_t>(d[s]) & 0xffu) << (8 * q);
+    }
+}
+
+// 32 groups x 32 inner elements per block.  TRANS = false: X is R x K and a
+// group is a row; TRANS = true: X is K x R and a group is a column.
+template <int S, bool TRANS>
+__global__ __launch_bounds__(256) void k_slice(const double *__restrict__ X, int64_t ld, int64_t R,
+                                                int64_t K, const int32_t *__restrict__ e,
+                                                int8_t *__restrict__ packed, int64_t Rp) {
+    __shared__ uint4 tile[S * 2][32];
+    const int t = threadIdx.x;
+    const int64_t r0 = static_cast<int64_t>(blockIdx.x) * 32;
+    const int64_t kb = blockIdx.y;
+    const int64_t k0 = kb * 32;
+    int r, kq;
+    if (TRANS) {
+        r = t & 31;
+        kq = t >> 5;
+    } else {
+        r = t >> 3;
+        kq = t & 7;
+    }
+    const int64_t gr = r0 + r;
+    double x[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t k = k0 + kq * 4 + q;
+        x[q] = 0.0;
+        if (gr < R && k < K) x[q] = TRANS ? X[k * ld + gr] : X[gr * ld + k];
+    }
+    const int32_t ee = gr < R ? e[gr] : 0;
+    uint32_t w[S];
+    slice4<S>(x, ee, w);
+    const int c = kq >> 2;     // which 16-byte half of the 32-wide block
+    const int word = kq & 3;   // which 4-byte word inside the half
+#pragma unroll
+    for (int s = 0; s < S; ++s) reinterpret_cast<uint32_t *>(&tile[s * 2 + c][r])[word] = w[s];
+    __syncthreads();
+    // write 2S runs of 32 rows x 16 bytes
+    uint4 *out = reinterpret_cast<uint4 *>(packed);
+    for (int q = t; q < S * 2 * 32; q += 256) {
+        const int sc = q >> 5;
+        const int rr = q & 31;
+        out[(kb * S * 2 + sc) * Rp + r0 + rr] = tile[sc][rr];
+    }
+}
+
+template <int S>
+hipError_t slice_s(bool trans, const double *X, int64_t ld, int64_t R, int64_t K,
+                   const int32_t *e, int8_t *packed, int64_t Rp, hipStream_t s) {
+    dim3 grid(static_cast<unsigned>(Rp / 32), static_cast<unsigned>(ceil_div(K, kKB)));
+    if (trans)
+        hipLaunchKernelGGL((k_slice<S, true>), grid, dim3(256), 0, s, X, ld, R, K, e, packed, Rp);
+    else
+        hipLaunchKernelGGL((k_slice<S, false>), grid, dim3(256), 0, s, X, ld, R, K, e, packed, Rp);
+    return hipGetLastError();
+}
+
+// Debug layout conversions, one byte per thread.
+__global__ void k_pack(int S, const int8_t *__restrict__ canon, int64_t R, int64_t K,
+                       int8_t *__restrict__ packed, int64_t Rp, int64_t Kp) {
+    const int64_t total = static_cast<int64_t>(S) * Rp * Kp;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t s = i / (Rp * Kp);
+        const int64_t r = (i / Kp) % Rp;
+        const int64_t k = i % Kp;
+        const int8_t v = (r < R && k < K) ? canon[(s * R + r) * K + k] : int8_t(0);
+        packed[((k / 32 * S + s) * 2 + (k / 16) % 2) * Rp * 16 + r * 16 + k % 16] = v;
+    }
+}
+
+__global__ void k_unpack(int S, const int8_t *__restrict__ packed, int64_t Rp, int64_t R,
+                         int64_t K, int8_t *__restrict__ canon) {
+    const int64_t total = static_cast<int64_t>(S) * R * K;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t s = i / (R * K);
+        const int64_t r = (i / K) % R;
+        const int64_t k = i % K;
+        canon[i] = packed[((k / 32 * S + s) * 2 + (k / 16) % 2) * Rp * 16 + r * 16 + k % 16];
+    }
+}
+
+__global__ void k_diag_axpy(const double *__restrict__ diag, const double *__restrict__ psi,
+                            double *__restrict__ sigma, int64_t n) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const double p = diag[i] * psi[i];
+        sigma[i] = sigma[i] + p;
+    }
+}
+
+unsigned grid_for(int64_t n, int64_t per_block, unsigned cap) {
+    const int64_t g = ceil_div(n, per_block);
+    return static_cast<unsigned>(g < 1 ? 1 : (g > cap ? cap : g));
+}
+
+}  // namespace
+
+hipError_t launch_row_exponents(const double *X, int64_t ld, int64_t R, int64_t K, int32_t *e,
+                                uint32_t *flag, hipStream_t s) {
+    if (R == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_row_exponents, dim3(static_cast<unsigned>(ceil_div(R, 4))), dim3(256), 0,
+                       s, X, ld, R, K, e, flag);
+    return hipGetLastError();
+}
+
+size_t col_exponent_scratch(int64_t K, int64_t R) {
+    const int64_t nchunk = ceil_div(K, kColChunk) < 1 ? 1 : ceil_div(K, kColChunk);
+    return static_cast<size_t>(nchunk * R) * sizeof(double);
+}
+
+hipError_t launch_col_exponents(const double *X, int64_t ld, int64_t K, int64_t R, int32_t *e,
+                                double *part, uint32_t *flag, hipStream_t s) {
+    if (R == 0) return hipSuccess;
+    const int64_t nchunk = ceil_div(K, kColChunk);
+    if (nchunk > 0) {
+        hipLaunchKernelGGL(k_col_partial,
+                           dim3(static_cast<unsigned>(ceil_div(R, 256)), static_cast<unsigned>(nchunk)),
+                           dim3(256), 0, s, X, ld, K, R, part);
+    }
+    hipLaunchKernelGGL(k_col_final, dim3(static_cast<unsigned>(ceil_div(R, 256))), dim3(256), 0, s,
+                       part, nchunk, R, e, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_slice(int S, bool trans, const double *X, int64_t ld, int64_t R, int64_t K,
+                        const int32_t *e, int8_t *packed, int64_t Rp, hipStream_t s) {
+    if (Rp == 0 || K == 0) return hipSuccess;
+    switch (S) {
+        case 2: return slice_s<2>(trans, X, ld, R, K, e, packed, Rp, s);
+        case 3: return slice_s<3>(trans, X, ld, R, K, e, packed, Rp, s);
+        case 4: return slice_s<4>(trans, X, ld, R, K, e, packed, Rp, s);
+        case 5: return slice_s<5>(trans, X, ld, R, K, e, packed, Rp, s);
+        case 6: return slice_s<6>(trans, X, ld, R, K, e, packed, Rp, s);
+        case 7: return slice_s<7>(trans, X, ld, R, K, e, packed, Rp, s);
+        case 8: return slice_s<8>(trans, X, ld, R, K, e, packed, Rp, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_pack(int S, const int8_t *canon, int64_t R, int64_t K, int8_t *packed,
+                       int64_t Rp, hipStream_t s) {
+    const int64_t Kp = round_up(K, kKB);
+    const int64_t total = static_cast<int64_t>(S) * Rp * Kp;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack, dim3(grid_for(total, 256, 65535)), dim3(256), 0, s, S, canon, R, K,
+                       packed, Rp, Kp);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack(int S, const int8_t *packed, int64_t Rp, int64_t R, int64_t K,
+                         int8_t *canon, hipStream_t s) {
+    const int64_t total = static_cast<int64_t>(S) * R * K;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_unpack, dim3(grid_for(total, 256, 65535)), dim3(256), 0, s, S, packed, Rp,
+                       R, K, canon);
+    return hipGetLastError();
+}
+
+hipError_t launch_diag_axpy(const double *diag, const double *psi, double *sigma, int64_t n,
+                            hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_diag_axpy, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, diag, psi,
+                       sigma, n);
+    return hipGetLastError();
+}
+
+}  // namespace oz

@@ -1,0 +1,342 @@
+"""Python binding of libozaki: emulated-FP64 (Ozaki scheme) GEMM, two-site
+H_eff.psi and a Davidson step on MI355X (gfx950).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libozaki.so.  PyTorch supplies device memory (``data_ptr``) and
+streams.  The library must have been built (``python -m
+paper_2510_04795_amd._build``); importing this module without it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libozaki.so")
+
+OZ_OK, OZ_CONVERGED, OZ_STAGNATED, OZ_MAX_ITER = 0, 1, 2, 3
+OZ_FLAG_NONFINITE = 1
+OZ_EXP_NONFINITE = -(2 ** 31)
+STATUS = {0: "running", 1: "converged", 2: "stagnated", 3: "max_iter"}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libozaki.so is not built: run `python -m paper_2510_04795_amd._build` "
+                      "(expected at %s)" % LIB_PATH)
+
+_lib = ctypes.CDLL(LIB_PATH)
+_i32, _i64, _dbl, _ptr, _sz = ctypes.c_int, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
+
+
+class HeffTriple(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("lo", ctypes.c_int32), ("li", ctypes.c_int32),
+                ("ri", ctypes.c_int32), ("ro", ctypes.c_int32), ("alpha", ctypes.c_double)]
+
+
+class HeffLayout(ctypes.Structure):
+    _fields_ = [("n_left", ctypes.c_int32), ("n_right", ctypes.c_int32), ("phys", ctypes.c_int32),
+                ("left_dim", _ptr), ("right_dim", _ptr),
+                ("n_psi_blocks", ctypes.c_int32), ("psi_lr", _ptr), ("psi_offset", _ptr),
+                ("n_L_blocks", ctypes.c_int32), ("L_key", _ptr), ("L_offset", _ptr),
+                ("n_R_blocks", ctypes.c_int32), ("R_key", _ptr), ("R_offset", _ptr)]
+
+
+class DavidsonInfo(ctypes.Structure):
+    _fields_ = [("theta", ctypes.c_double), ("resnorm", ctypes.c_double), ("iter", ctypes.c_int32),
+                ("m", ctypes.c_int32), ("status", ctypes.c_int32)]
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_sig("ozaki_status_string", ctypes.c_char_p, [_i32])
+_sig("ozaki_last_error", ctypes.c_char_p, [])
+_sig("ozaki_version", _i32, [])
+_sig("ozaki_ctx_create", _i32, [ctypes.POINTER(_ptr), _i32])
+_sig("ozaki_ctx_destroy", _i32, [_ptr])
+_sig("ozaki_ctx_flags", _i32, [_ptr, ctypes.POINTER(ctypes.c_uint32)])
+_sig("ozaki_slices_for_bits", _i32, [_i32])
+_sig("ozaki_pair_count", _i32, [_i32, _i32])
+_sig("ozaki_max_exact_k", _i64, [_i32, _i32])
+_sig("ozaki_dgemm_workspace_bytes", _sz, [_i64, _i64, _i64, _i32, _i32])
+_sig("ozaki_dgemm", _i32, [_ptr, ctypes.c_char, ctypes.c_char, _i64, _i64, _i64, _dbl, _ptr, _i64,
+                           _ptr, _i64, _dbl, _ptr, _i64, _i32, _i32, _ptr, _sz, _ptr])
+_sig("ozaki_split", _i32, [_ptr, _i32, _i64, _i64, _ptr, _i64, _i32, _ptr, _ptr, _ptr])
+_sig("ozaki_pair_products", _i32, [_ptr, _i64, _i64, _i64, _i32, _i32, _ptr, _ptr, _ptr, _ptr])
+_sig("heff_plan_create", _i32, [_ptr, ctypes.POINTER(_ptr), ctypes.POINTER(HeffLayout), _ptr, _ptr,
+                                _i32, ctypes.POINTER(HeffTriple), _ptr, _i32, _i32, _ptr])
+_sig("heff_apply", _i32, [_ptr, _ptr, _ptr, _ptr])
+_sig("heff_vector_length", _i64, [_ptr])
+_sig("heff_flops", _dbl, [_ptr])
+_sig("heff_plan_destroy", _i32, [_ptr])
+_sig("davidson_create", _i32, [_ptr, ctypes.POINTER(_ptr), _ptr, _ptr, _ptr, _i32, _dbl, _i32, _ptr])
+_sig("davidson_step", _i32, [_ptr, ctypes.POINTER(DavidsonInfo), _ptr])
+_sig("davidson_get_vector", _i32, [_ptr, _ptr, _ptr])
+_sig("davidson_destroy", _i32, [_ptr])
+
+EXPORTED = [
+    "ozaki_status_string", "ozaki_last_error", "ozaki_version", "ozaki_ctx_create",
+    "ozaki_ctx_destroy", "ozaki_ctx_flags", "ozaki_slices_for_bits", "ozaki_pair_count",
+    "ozaki_max_exact_k", "ozaki_dgemm_workspace_bytes", "ozaki_dgemm", "ozaki_split",
+    "ozaki_pair_products", "heff_plan_create", "heff_apply", "heff_vector_length", "heff_flops",
+    "heff_plan_destroy", "davidson_create", "davidson_step", "davidson_get_vector",
+    "davidson_destroy",
+]
+
+
+class OzakiError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = _lib.ozaki_last_error().decode() or _lib.ozaki_status_string(status).decode()
+        super().__init__("%s: %s (status %d)" % (where, msg, status))
+        self.status = status
+
+
+def _check(rc: int, where: str) -> int:
+    if rc < 0:
+        raise OzakiError(rc, where)
+    return rc
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _dev_f64(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError("%s must be a float64 CUDA tensor" % name)
+    return t
+
+
+def _ld(t: torch.Tensor, name: str) -> int:
+    """Leading dimension of a row-major 2-D view (unit column stride)."""
+    if t.dim() != 2:
+        raise ValueError("%s must be 2-D" % name)
+    if t.numel() == 0:
+        return max(t.size(1), 1)
+    if t.size(1) > 1 and t.stride(1) != 1:
+        raise ValueError("%s must be a row-major 2-D tensor with unit column stride" % name)
+    return max(t.stride(0), t.size(1), 1)
+
+
+def slices_for_bits(bits: int) -> int:
+    return _check(_lib.ozaki_slices_for_bits(bits), "ozaki_slices_for_bits")
+
+
+def pair_count(slices: int, ndiag: int = 0) -> int:
+    return _check(_lib.ozaki_pair_count(slices, ndiag), "ozaki_pair_count")
+
+
+def max_exact_k(slices: int, ndiag: int = 0) -> int:
+    return _check(_lib.ozaki_max_exact_k(slices, ndiag), "ozaki_max_exact_k")
+
+
+def workspace_bytes(M: int, N: int, K: int, slices: int, ndiag: int = 0) -> int:
+    return int(_lib.ozaki_dgemm_workspace_bytes(M, N, K, slices, ndiag))
+
+
+class Context:
+    """An ozaki_ctx bound to one device."""
+
+    def __init__(self, device: int | None = None):
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = device
+        h = _ptr()
+        _check(_lib.ozaki_ctx_create(ctypes.byref(h), device), "ozaki_ctx_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.ozaki_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def flags(self) -> int:
+        v = ctypes.c_uint32(0)
+        _check(_lib.ozaki_ctx_flags(self.handle, ctypes.byref(v)), "ozaki_ctx_flags")
+        return int(v.value)
+
+    # ---- GEMM -----------------------------------------------------------
+    def workspace(self, M, N, K, slices, ndiag=0) -> torch.Tensor | None:
+        n = workspace_bytes(M, N, K, slices, ndiag)
+        if n == 0:
+            return None
+        return torch.empty(n, dtype=torch.uint8, device="cuda:%d" % self.device)
+
+    def dgemm(self, A, B, slices: int = 6, ndiag: int = 0, alpha: float = 1.0, beta: float = 0.0,
+              C=None, transa: str = "N", transb: str = "N", workspace=None, stream=None):
+        """C = alpha op(A) op(B) + beta C; slices = 0 runs the native FP64 MFMA GEMM."""
+        _dev_f64(A, "A")
+        _dev_f64(B, "B")
+        ta, tb = transa.upper() == "T", transb.upper() == "T"
+        M = A.size(1) if ta else A.size(0)
+        K = A.size(0) if ta else A.size(1)
+        N = B.size(0) if tb else B.size(1)
+        if (B.size(1) if tb else B.size(0)) != K:
+            raise ValueError("inner dimensions differ")
+        if C is None:
+            C = torch.empty((M, N), dtype=torch.float64, device=A.device)
+            if beta != 0.0:
+                raise ValueError("beta != 0 needs C")
+        _dev_f64(C, "C")
+        if workspace is None:
+            workspace = self.workspace(M, N, K, slices, ndiag)
+        wptr = workspace.data_ptr() if workspace is not None else None
+        wlen = workspace.numel() * workspace.element_size() if workspace is not None else 0
+        _check(_lib.ozaki_dgemm(self.handle, transa.upper().encode(), transb.upper().encode(), M, N,
+                                K, alpha, A.data_ptr(), _ld(A, "A"), B.data_ptr(), _ld(B, "B"),
+                                beta, C.data_ptr(), _ld(C, "C"), slices, ndiag, wptr, wlen,
+                                _stream(stream)), "ozaki_dgemm")
+        return C
+
+    # ---- steps on their own (tests) --------------------------------------
+    def split(self, X, slices: int, by_columns: bool = False, stream=None):
+        """(digits int8 [S][groups][len], exps int32 [groups]) of X's slices."""
+        _dev_f64(X, "X")
+        rows, cols = X.shape
+        groups, length = (cols, rows) if by_columns else (rows, cols)
+        digits = torch.empty((slices, groups, length), dtype=torch.int8, device=X.device)
+        exps = torch.empty(groups, dtype=torch.int32, device=X.device)
+        _check(_lib.ozaki_split(self.handle, int(by_columns), rows, cols, X.data_ptr(), _ld(X, "X"),
+                                slices, digits.data_ptr(), exps.data_ptr(), _stream(stream)),
+               "ozaki_split")
+        return digits, exps
+
+    def pair_products(self, Adig, BTdig, slices: int, ndiag: int = 0, stream=None):
+        """int32 Q[g][i][j] = sum over kept pairs on diagonal g of Adig[s] BTdig[t]^T."""
+        S, M, K = Adig.shape
+        _, N, _ = BTdig.shape
+        G = slices if ndiag == 0 else ndiag
+        Q = torch.empty((G, M, N), dtype=torch.int32, device=Adig.device)
+        Adig = Adig.contiguous()
+        BTdig = BTdig.contiguous()
+        _check(_lib.ozaki_pair_products(self.handle, M, N, K, slices, ndiag, Adig.data_ptr(),
+                                        BTdig.data_ptr(), Q.data_ptr(), _stream(stream)),
+               "ozaki_pair_products")
+        return Q
+
+
+# ---- effective Hamiltonian ----------------------------------------------------
+class HeffPlan:
+    """A planned H_eff.psi (dense or block-sparse); see heff_plan_create in ozaki.h.
+
+    The layout arrays are host data; L_data, R_data (and diag) are flat float64
+    CUDA tensors that must outlive the plan.
+    """
+
+    def __init__(self, ctx: Context, layout: dict, L_data, R_data, triples, diag=None,
+                 slices: int = 6, ndiag: int = 0, stream=None):
+        import numpy as np
+        self.ctx = ctx
+        self._keep = [L_data, R_data, diag]
+        arr = {}
+
+        def a32(x):
+            v = np.ascontiguousarray(np.asarray(x, dtype=np.int32))
+            arr[id(v)] = v
+            return v.ctypes.data
+
+        def a64(x):
+            v = np.ascontiguousarray(np.asarray(x, dtype=np.int64))
+            arr[id(v)] = v
+            return v.ctypes.data
+
+        lay = HeffLayout(
+            n_left=len(layout["left_dim"]), n_right=len(layout["right_dim"]), phys=layout["phys"],
+            left_dim=a32(layout["left_dim"]), right_dim=a32(layout["right_dim"]),
+            n_psi_blocks=len(layout["psi_offset"]), psi_lr=a32(layout["psi_lr"]),
+            psi_offset=a64(layout["psi_offset"]),
+            n_L_blocks=len(layout["L_offset"]), L_key=a32(layout["L_key"]),
+            L_offset=a64(layout["L_offset"]),
+            n_R_blocks=len(layout["R_offset"]), R_key=a32(layout["R_key"]),
+            R_offset=a64(layout["R_offset"]))
+        tri = (HeffTriple * max(1, len(triples)))()
+        for n, (op, lo, li, ri, ro, al) in enumerate(triples):
+            tri[n] = HeffTriple(op, lo, li, ri, ro, al)
+        h = _ptr()
+        _check(_lib.heff_plan_create(ctx.handle, ctypes.byref(h), ctypes.byref(lay),
+                                     _dev_f64(L_data, "L").data_ptr(),
+                                     _dev_f64(R_data, "R").data_ptr(), len(triples), tri,
+                                     diag.data_ptr() if diag is not None else None, slices, ndiag,
+                                     _stream(stream)), "heff_plan_create")
+        self.handle = h
+        self.n = int(_lib.heff_vector_length(h))
+        self.flops = float(_lib.heff_flops(h))
+
+    def apply(self, psi, sigma=None, stream=None):
+        _dev_f64(psi, "psi")
+        if psi.numel() != self.n or not psi.is_contiguous():
+            raise ValueError("psi must be contiguous with %d elements" % self.n)
+        if sigma is None:
+            sigma = torch.empty_like(psi)
+        _check(_lib.heff_apply(self.handle, psi.data_ptr(), sigma.data_ptr(), _stream(stream)),
+               "heff_apply")
+        return sigma
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.heff_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Davidson:
+    """Device-resident Davidson iteration for the lowest eigenpair of a HeffPlan."""
+
+    def __init__(self, ctx: Context, plan: HeffPlan, hdiag, x0, m_max: int = 32,
+                 tol: float = 1e-8, max_iter: int = 300, stream=None):
+        self.ctx = ctx
+        self.plan = plan
+        h = _ptr()
+        _check(_lib.davidson_create(ctx.handle, ctypes.byref(h), plan.handle,
+                                    _dev_f64(hdiag, "hdiag").data_ptr(),
+                                    _dev_f64(x0, "x0").data_ptr(), m_max, tol, max_iter,
+                                    _stream(stream)), "davidson_create")
+        self.handle = h
+
+    def step(self, stream=None) -> DavidsonInfo:
+        info = DavidsonInfo()
+        _check(_lib.davidson_step(self.handle, ctypes.byref(info), _stream(stream)), "davidson_step")
+        return info
+
+    def vector(self, out=None, stream=None):
+        if out is None:
+            out = torch.empty(self.plan.n, dtype=torch.float64, device="cuda:%d" % self.ctx.device)
+        _check(_lib.davidson_get_vector(self.handle, out.data_ptr(), _stream(stream)),
+               "davidson_get_vector")
+        return out
+
+    def run(self, stream=None):
+        """Iterate until a terminal status; returns (theta, status, iterations, residual)."""
+        while True:
+            info = self.step(stream)
+            if info.status != OZ_OK:
+                return info.theta, STATUS[info.status], info.iter, info.resnorm
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.davidson_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

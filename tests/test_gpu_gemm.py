@@ -1,0 +1,202 @@
+"""GPU parity of the emulated-FP64 GEMM against the CPU oracle.
+
+Steps 1-2 (exponents, slices) and step 3 (int32 diagonal sums) must agree bit
+for bit; the whole emulated GEMM must agree bit for bit as well (both sides
+run the same FP64 recombination order).  The native FP64 MFMA path is held to
+the textbook gamma_K |A||B| bound against the double-double reference.
+Shapes span several tiles with ragged edges.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2510_04795_amd import workloads as wl
+from tests.helpers import assert_bitexact
+
+pytestmark = pytest.mark.gpu
+
+SG = [(S, G) for S in range(2, 9) for G in sorted({S, S + 1, 2 * S - 1})]
+
+
+@pytest.fixture(scope="module")
+def oz():
+    import torch
+    from paper_2510_04795_amd import ozaki
+    torch.cuda.init()
+    ctx = ozaki.Context(0)
+    yield ozaki, ctx, torch
+    ctx.close()
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def edge_matrix(rng, rows, cols, U):
+    X = wl.wide_normal(rng, (rows, cols), U)
+    X[min(1, rows - 1), :] = 0.0                  # a zero row
+    X[rows // 2, cols // 3] = 5e-324              # a subnormal
+    X[-1, 0] = 127 / 128 * 2.0 ** 40              # at the exponent bump boundary
+    X[-1, -1] = -(127 / 128 + 2.0 ** -52) * 2.0 ** 40
+    return X
+
+
+@pytest.mark.parametrize("S", range(2, 9))
+@pytest.mark.parametrize("by_columns", [False, True])
+def test_split_bitexact(oz, S, by_columns):
+    ozaki, ctx, torch = oz
+    rng = np.random.default_rng(S * 10 + by_columns)
+    for (rows, cols, U) in [(77, 45, 10), (33, 130, 30), (1, 1, 5)]:
+        X = edge_matrix(rng, rows, cols, U) if rows > 2 else wl.wide_normal(rng, (rows, cols), U)
+        d, e = ctx.split(dev(torch, X), S, by_columns=by_columns)
+        rd, re_, rb = oracle.split(X, S, by_columns=by_columns)
+        if by_columns:
+            rd = np.transpose(rd, (0, 2, 1))
+        assert np.array_equal(e.cpu().numpy(), np.where(rb == 1, ozaki.OZ_EXP_NONFINITE, re_))
+        assert np.array_equal(d.cpu().numpy(), rd)
+
+
+def test_split_nonfinite_flag(oz):
+    ozaki, ctx, torch = oz
+    ctx.flags()
+    X = np.ones((5, 7))
+    X[2, 3] = np.nan
+    X[4, 0] = -np.inf
+    d, e = ctx.split(dev(torch, X), 6)
+    e = e.cpu().numpy()
+    assert e[2] == ozaki.OZ_EXP_NONFINITE and e[4] == ozaki.OZ_EXP_NONFINITE and e[0] == 1
+    assert np.all(d.cpu().numpy()[:, [2, 4], :] == 0)
+    assert ctx.flags() & ozaki.OZ_FLAG_NONFINITE
+    assert ctx.flags() == 0
+
+
+@pytest.mark.parametrize("S,G", SG)
+def test_pair_products_bitexact(oz, S, G):
+    ozaki, ctx, torch = oz
+    rng = np.random.default_rng(100 + S * 16 + G)
+    M, N, K = 150, 97, 333
+    A = wl.wide_normal(rng, (M, K), 20)
+    B = wl.wide_normal(rng, (K, N), 20)
+    Ad, _, _ = oracle.split(A, S)
+    Bd, _, _ = oracle.split(B, S, by_columns=True)
+    Q = ctx.pair_products(dev(torch, Ad), dev(torch, np.transpose(Bd, (0, 2, 1))), S, G)
+    ref = oracle.pair_products(Ad, Bd, G)
+    assert np.abs(ref).max() < 2 ** 31
+    assert np.array_equal(Q.cpu().numpy().astype(np.int64), ref)
+
+
+@pytest.mark.parametrize("S,G", SG)
+def test_dgemm_bitexact(oz, S, G):
+    ozaki, ctx, torch = oz
+    rng = np.random.default_rng(200 + S * 16 + G)
+    M, N, K = 200, 131, 300
+    A = wl.wide_normal(rng, (M, K), 10)
+    B = wl.wide_normal(rng, (K, N), 10)
+    C = ctx.dgemm(dev(torch, A), dev(torch, B), slices=S, ndiag=G).cpu().numpy()
+    assert_bitexact(C, oracle.ozaki_dgemm(A, B, S, G), "S=%d G=%d" % (S, G))
+
+
+@pytest.mark.parametrize("transa,transb", [("N", "T"), ("T", "N"), ("T", "T")])
+def test_dgemm_transposes_alpha_beta(oz, transa, transb):
+    ozaki, ctx, torch = oz
+    rng = np.random.default_rng(7)
+    M, N, K = 96, 160, 70
+    A = wl.wide_normal(rng, (M, K), 30)
+    B = wl.wide_normal(rng, (K, N), 30)
+    As = A.T.copy() if transa == "T" else A
+    Bs = B.T.copy() if transb == "T" else B
+    C0 = rng.standard_normal((M, N))
+    for (alpha, beta) in [(1.0, 0.0), (-2.5, 0.75), (0.0, 1.0)]:
+        got = ctx.dgemm(dev(torch, As), dev(torch, Bs), slices=6, alpha=alpha, beta=beta,
+                        C=dev(torch, C0), transa=transa, transb=transb).cpu().numpy()
+        ref = oracle.ozaki_dgemm(As, Bs, 6, 6, alpha=alpha, beta=beta, C=C0, transa=transa,
+                                 transb=transb)
+        assert_bitexact(got, ref, "%s%s a=%g b=%g" % (transa, transb, alpha, beta))
+
+
+def test_dgemm_leading_dimensions(oz):
+    ozaki, ctx, torch = oz
+    rng = np.random.default_rng(8)
+    big = wl.wide_normal(rng, (90, 120), 10)
+    A, B = big[:70, :50], big[5:55, 60:117]
+    Ad, Bd = dev(torch, big)[:70, :50], dev(torch, big)[5:55, 60:117]
+    Cbuf = torch.zeros((70, 80), dtype=torch.float64, device="cuda")
+    ctx.dgemm(Ad, Bd, slices=7, C=Cbuf[:, 10:67])
+    assert_bitexact(Cbuf[:, 10:67].cpu().numpy(), oracle.ozaki_dgemm(A.copy(), B.copy(), 7), "ld")
+    assert np.all(Cbuf[:, :10].cpu().numpy() == 0) and np.all(Cbuf[:, 67:].cpu().numpy() == 0)
+
+
+def test_dgemm_nonfinite_and_degenerate(oz):
+    ozaki, ctx, torch = oz
+    rng = np.random.default_rng(9)
+    A = rng.standard_normal((40, 33))
+    B = rng.standard_normal((33, 50))
+    A[3, 7] = np.nan
+    B[10, 44] = np.inf
+    ctx.flags()
+    got = ctx.dgemm(dev(torch, A), dev(torch, B), slices=5).cpu().numpy()
+    assert_bitexact(got, oracle.ozaki_dgemm(A, B, 5), "nan")
+    assert ctx.flags() & ozaki.OZ_FLAG_NONFINITE
+    C0 = rng.standard_normal((4, 6))
+    got = ctx.dgemm(dev(torch, np.zeros((4, 0))), dev(torch, np.zeros((0, 6))), slices=6,
+                    alpha=3.0, beta=0.5, C=dev(torch, C0)).cpu().numpy()
+    assert_bitexact(got, 0.5 * C0, "K=0")
+    one = ctx.dgemm(dev(torch, np.array([[3.0]])), dev(torch, np.array([[-0.5]])), slices=4)
+    assert one.item() == -1.5
+
+
+def test_dgemm_chunked_inner_dimension(oz):
+    """K above the exact int32 range: chunks carried in int64, same result."""
+    ozaki, ctx, torch = oz
+    S = 8
+    K = 40000
+    assert K > ozaki.max_exact_k(S)
+    rng = np.random.default_rng(10)
+    A = wl.wide_normal(rng, (37, K), 6)
+    B = wl.wide_normal(rng, (K, 29), 6)
+    got = ctx.dgemm(dev(torch, A), dev(torch, B), slices=S).cpu().numpy()
+    assert_bitexact(got, oracle.ozaki_dgemm(A, B, S), "chunked")
+
+
+def test_dgemm_argument_errors(oz):
+    ozaki, ctx, torch = oz
+    A = torch.zeros((4, 4), dtype=torch.float64, device="cuda")
+    with pytest.raises(ozaki.OzakiError):
+        ctx.dgemm(A, A, slices=9)
+    with pytest.raises(ozaki.OzakiError):
+        ctx.dgemm(A, A, slices=6, ndiag=8)
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ozaki.OzakiError) as ei:
+        ctx.dgemm(A, A, slices=6, workspace=small)
+    assert ei.value.status == -2
+
+
+@pytest.mark.parametrize("transa,transb", [("N", "N"), ("N", "T"), ("T", "N"), ("T", "T")])
+def test_fp64_mfma_within_gamma_bound(oz, transa, transb):
+    ozaki, ctx, torch = oz
+    rng = np.random.default_rng(11)
+    M, N, K = 130, 70, 257
+    A = wl.wide_normal(rng, (M, K), 10)
+    B = wl.wide_normal(rng, (K, N), 10)
+    As = A.T.copy() if transa == "T" else A
+    Bs = B.T.copy() if transb == "T" else B
+    got = ctx.dgemm(dev(torch, As), dev(torch, Bs), slices=0, transa=transa,
+                    transb=transb).cpu().numpy()
+    hi, lo = oracle.dgemm_dd(A, B)
+    u = 2.0 ** -53
+    gam = K * u / (1 - K * u)
+    err = np.abs((got - hi) - lo)
+    assert np.all(err <= gam * (np.abs(A) @ np.abs(B)) * (1 + 1e-12))
+
+
+def test_dgemm_full_size_sampled_rows(oz):
+    """n = 8192, S = 6: the launch the benchmark times, checked on sampled rows
+    (exponents are per row of A and per column of B, so rows are independent)."""
+    ozaki, ctx, torch = oz
+    n = 8192
+    A, B = wl.gemm_pair(n, U=10, seed=0)
+    Cd = ctx.dgemm(dev(torch, A), dev(torch, B), slices=6)
+    rows = np.random.default_rng(1).choice(n, size=6, replace=False)
+    got = Cd[torch.from_numpy(rows).cuda()].cpu().numpy()
+    ref = oracle.ozaki_dgemm(A[rows], B, 6)
+    assert_bitexact(got, ref, "n=8192 rows")
