@@ -82,6 +82,21 @@ int ozaki_ctx_destroy(ozaki_ctx ctx);
 /* Read and clear the sticky flags (synchronises the device). */
 int ozaki_ctx_flags(ozaki_ctx ctx, uint32_t *flags_out);
 
+/* Per-phase timing for benchmarks.  With timing enabled, the enqueue calls
+ * record a hipEvent pair on their stream around each phase (at most 4096
+ * phases are kept); ozaki_ctx_phase_times waits for the recorded events and
+ * returns how many phases it wrote, phase[i] = OZ_PHASE_* and ms[i] = the
+ * elapsed milliseconds, then clears the record.  Enabling allocates events
+ * (do not enable during graph capture). */
+#define OZ_PHASE_SLICE 1      /* exponents + int8 slices of GEMM operands     */
+#define OZ_PHASE_PAIR 2       /* int8 pair GEMM + FP64 recombination          */
+#define OZ_PHASE_FP64 3       /* native FP64 MFMA GEMM                        */
+#define OZ_PHASE_HEFF_L 4     /* H_eff.psi first contraction (all operators)  */
+#define OZ_PHASE_HEFF_R 5     /* H_eff.psi second contraction + accumulation  */
+#define OZ_PHASE_HEFF_AUX 6   /* H_eff.psi slicing of psi / T and diagonal    */
+int ozaki_ctx_set_timing(ozaki_ctx ctx, int enable);
+int ozaki_ctx_phase_times(ozaki_ctx ctx, int32_t *phase, double *ms, int32_t max_phases);
+
 /* ---- parameters ------------------------------------------------------ */
 /* S = ceildiv(mantissa_bits + 1, 8) ("Numerical procedure"); OZ_ERR_ARG if
  * bits < 1. */

@@ -1,0 +1,472 @@
+// Davidson iteration for the lowest eigenpair of H_eff (the Krylov solver of
+// the second DMRG subroutine, "Theory of TNS/DMRG"; stopped on the residual
+// norm as in "Numerical procedure").  The matvec is heff_apply (emulated or
+// native); everything else runs in FP64 on the device:
+//
+//   Rayleigh-Ritz   one-workgroup cyclic Jacobi (round-robin ordering, all
+//                   disjoint rotations of a round applied together) on the
+//                   m x m projected matrix, m <= 64;
+//   Ritz vector     x = V^T y, Hx = W^T y, r = Hx - theta x, rho = |r|;
+//   correction      t = r / (diag(H) - theta), |den| >= 1e-8;
+//   orthogonalise   classical Gram-Schmidt twice against V, fall back to r
+//                   when |t| < 1e-10, normalise;
+//   expand          W[m] = H V[m] and the new column of V^T W.
+//
+// All reductions use a fixed partition and a fixed tree, so a run is
+// bit-reproducible.  The host reads (theta, rho) once per step.
+#include <cmath>
+#include <vector>
+
+#include "runtime.h"
+
+using namespace oz;
+
+namespace {
+
+constexpr int kDotThreads = 256;
+
+int dot_blocks(int64_t n) {
+    const int64_t b = ceil_div(n, kDotThreads * 4);
+    return static_cast<int>(b < 1 ? 1 : (b > 512 ? 512 : b));
+}
+
+__device__ inline double block_sum(double v, double *sh) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (t < s) sh[t] += sh[t + s];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// partial[row][blk] = sum over this block's share of A[row][i] * v[i]
+__global__ __launch_bounds__(kDotThreads) void k_dots_partial(const double *__restrict__ A, int64_t lda, const double *__restrict__ v,
+                                                              int64_t n, double *__restrict__ partial, const int *gate) {
+    if (gate && *gate == 0) return;
+    __shared__ double sh[kDotThreads];
+    const int row = blockIdx.y;
+    const double *a = A + row * lda;
+    double acc = 0.0;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        acc = fma(a[i], v[i], acc);
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[static_cast<int64_t>(row) * gridDim.x + blockIdx.x] = s;
+}
+
+// out[row * out_stride] = sum of the row's partials; optional mirror out2.
+__global__ __launch_bounds__(kDotThreads) void k_dots_final(const double *__restrict__ partial, int nblk, double *out, int64_t out_stride,
+                                                            double *out2, int64_t out2_stride, const int *gate) {
+    if (gate && *gate == 0) return;
+    __shared__ double sh[kDotThreads];
+    const int row = blockIdx.x;
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) acc += partial[static_cast<int64_t>(row) * nblk + b];
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) {
+        out[row * out_stride] = s;
+        if (out2) out2[row * out2_stride] = s;
+    }
+}
+
+// Lowest eigenpair of the symmetric m x m matrix G (leading dimension ldg) by
+// cyclic Jacobi with the round-robin pairing; writes theta and y (largest
+// |y_i| made positive).  One workgroup of 256 threads, m <= 64.
+__global__ __launch_bounds__(256) void k_jacobi(const double *__restrict__ G, int ldg, int m, double *__restrict__ y,
+                                                double *__restrict__ theta_out) {
+    __shared__ double A[64][65];
+    __shared__ double Vv[64][65];
+    __shared__ double cs[32], sn[32];
+    __shared__ int pp[32], qq[32];
+    __shared__ double red[256];
+    __shared__ int done;
+    const int t = threadIdx.x;
+    for (int i = t; i < m * m; i += blockDim.x) {
+        const int r = i / m, c = i % m;
+        A[r][c] = G[r * ldg + c];
+        Vv[r][c] = (r == c) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    const int me = (m + 1) & ~1;  // even number of players (one dummy when m is odd)
+    for (int sweep = 0; sweep < 30 && m > 1; ++sweep) {
+        // convergence test: off(A) <= 1e-14 ||A||_F
+        double off = 0.0, tot = 0.0;
+        for (int i = t; i < m * m; i += blockDim.x) {
+            const int r = i / m, c = i % m;
+            const double v = A[r][c] * A[r][c];
+            tot += v;
+            if (r != c) off += v;
+        }
+        const double soff = block_sum(off, red);
+        const double stot = block_sum(tot, red);
+        if (t == 0) done = (sqrt(soff) <= 1e-14 * sqrt(stot)) ? 1 : 0;
+        __syncthreads();
+        if (done) break;
+        for (int round = 0; round < me - 1; ++round) {
+            // round-robin: player me-1 fixed, the others rotate
+            if (t < me / 2) {
+                int a, b;
+                if (t == 0) {
+                    a = me - 1;
+                    b = round;
+                } else {
+                    a = (round + t) % (me - 1);
+                    b = (round - t + (me - 1)) % (me - 1);
+                }
+                const int p = a < b ? a : b, q = a < b ? b : a;
+                double c = 1.0, s = 0.0;
+                if (q < m) {
+                    const double apq = A[p][q];
+                    if (apq != 0.0) {
+                        const double th = (A[q][q] - A[p][p]) / (2.0 * apq);
+                        const double tt = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                        c = 1.0 / sqrt(tt * tt + 1.0);
+                        s = tt * c;
+                    }
+                }
+                cs[t] = c;
+                sn[t] = s;
+                pp[t] = p;
+                qq[t] = q < m ? q : -1;
+            }
+            __syncthreads();
+            // rows: A <- J^T A
+            for (int i = t; i < (me / 2) * m; i += blockDim.x) {
+                const int k = i / m, c = i % m;
+                if (qq[k] < 0) continue;
+                const int p = pp[k], q = qq[k];
+                const double ap = A[p][c], aq = A[q][c];
+                A[p][c] = cs[k] * ap - sn[k] * aq;
+                A[q][c] = sn[k] * ap + cs[k] * aq;
+            }
+            __syncthreads();
+            // columns: A <- A J, eigenvectors V <- V J
+            for (int i = t; i < (me / 2) * m; i += blockDim.x) {
+                const int k = i / m, r = i % m;
+                if (qq[k] < 0) continue;
+                const int p = pp[k], q = qq[k];
+                const double ap = A[r][p], aq = A[r][q];
+                A[r][p] = cs[k] * ap - sn[k] * aq;
+                A[r][q] = sn[k] * ap + cs[k] * aq;
+                const double vp = Vv[r][p], vq = Vv[r][q];
+                Vv[r][p] = cs[k] * vp - sn[k] * vq;
+                Vv[r][q] = sn[k] * vp + cs[k] * vq;
+            }
+            __syncthreads();
+        }
+    }
+    if (t == 0) {
+        int best = 0;
+        for (int i = 1; i < m; ++i)
+            if (A[i][i] < A[best][best]) best = i;
+        int big = 0;
+        for (int i = 1; i < m; ++i)
+            if (fabs(Vv[i][best]) > fabs(Vv[big][best])) big = i;
+        const double sgn = Vv[big][best] < 0 ? -1.0 : 1.0;
+        for (int i = 0; i < m; ++i) y[i] = sgn * Vv[i][best];
+        *theta_out = A[best][best];
+    }
+}
+
+// x = V^T y, hx = W^T y, r = hx - theta x, partial sums of r^2.
+__global__ __launch_bounds__(kDotThreads) void k_ritz(const double *__restrict__ V, const double *__restrict__ W, int64_t n,
+                                                      int m, const double *__restrict__ y, const double *__restrict__ theta,
+                                                      double *__restrict__ x, double *__restrict__ hx, double *__restrict__ r,
+                                                      double *__restrict__ partial) {
+    __shared__ double sh[kDotThreads];
+    const double th = *theta;
+    double acc = 0.0;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        double xi = 0.0, hi = 0.0;
+        for (int j = 0; j < m; ++j) {
+            xi = fma(y[j], V[j * n + i], xi);
+            hi = fma(y[j], W[j * n + i], hi);
+        }
+        const double ri = hi - th * xi;
+        x[i] = xi;
+        hx[i] = hi;
+        r[i] = ri;
+        acc = fma(ri, ri, acc);
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__global__ void k_precond(const double *__restrict__ r, const double *__restrict__ hdiag,
+                          const double *__restrict__ theta, double *__restrict__ t, int64_t n) {
+    const double th = *theta;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        double den = hdiag[i] - th;
+        if (fabs(den) < 1e-8) den = copysign(1e-8, den);
+        t[i] = r[i] / den;
+    }
+}
+
+// t -= V^T c  (c: m projection coefficients)
+__global__ void k_project(const double *__restrict__ V, int64_t n, int m, const double *__restrict__ c,
+                          double *__restrict__ t, const int *gate) {
+    if (gate && *gate == 0) return;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        double s = 0.0;
+        for (int j = 0; j < m; ++j) s = fma(c[j], V[j * n + i], s);
+        t[i] = t[i] - s;
+    }
+}
+
+// when |t|^2 < 1e-20 replace t by r and raise the gate for a second pass
+__global__ void k_fallback(const double *__restrict__ nrm2, const double *__restrict__ r, double *__restrict__ t,
+                           int64_t n, int *gate) {
+    const bool fb = *nrm2 < 1e-20;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *gate = fb ? 1 : 0;
+    if (!fb) return;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        t[i] = r[i];
+}
+
+__global__ void k_scale_into(const double *__restrict__ t, const double *__restrict__ nrm2, double *__restrict__ out,
+                             int64_t n) {
+    const double inv = 1.0 / sqrt(*nrm2);
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        out[i] = t[i] * inv;
+}
+
+// collapse the basis to the Ritz pair: G = [theta], zero elsewhere
+__global__ void k_collapse_g(double *G, int ldg, int mmax, const double *theta) {
+    for (int i = threadIdx.x; i < mmax * mmax; i += blockDim.x) G[(i / mmax) * ldg + i % mmax] = 0.0;
+    __syncthreads();
+    if (threadIdx.x == 0) G[0] = *theta;
+}
+
+unsigned grid_n(int64_t n) {
+    const int64_t g = ceil_div(n, 256);
+    return static_cast<unsigned>(g < 1 ? 1 : (g > 4096 ? 4096 : g));
+}
+
+}  // namespace
+
+struct davidson_s {
+    ozaki_ctx ctx = nullptr;
+    heff_plan H = nullptr;
+    int64_t n = 0;
+    int m_max = 0, max_iter = 0;
+    double tol = 0;
+    std::vector<void *> allocs;
+    double *V = nullptr, *W = nullptr, *G = nullptr, *hdiag = nullptr;
+    double *x = nullptr, *hx = nullptr, *r = nullptr, *t = nullptr;
+    double *y = nullptr, *coef = nullptr, *partial = nullptr, *scal = nullptr;  // scal: theta, rho2, nrm2
+    int *gate = nullptr;
+    double *host = nullptr;  // pinned: theta, rho2
+    int m = 0, iter = 0, status = OZ_OK;
+    std::vector<double> hist;
+};
+
+namespace {
+
+int dalloc(davidson d, size_t bytes, void **p) {
+    hipError_t e = hipMalloc(p, bytes < 8 ? 8 : bytes);
+    if (e != hipSuccess) return fail(OZ_ERR_NOMEM, "davidson_create: %zu bytes: %s", bytes, hipGetErrorString(e));
+    d->allocs.push_back(*p);
+    return OZ_OK;
+}
+
+void dfree(davidson d) {
+    for (void *p : d->allocs) hipFree(p);
+    if (d->host) hipHostFree(d->host);
+    delete d;
+}
+
+// out[i] = row_i(A) . v for i < rows (rows with stride lda), into out[i * out_stride]
+hipError_t dots(davidson d, const double *A, int64_t lda, int rows, const double *v, double *out,
+                int64_t out_stride, double *out2, int64_t out2_stride, const int *gate, hipStream_t s) {
+    const int nb = dot_blocks(d->n);
+    hipLaunchKernelGGL(k_dots_partial, dim3(nb, rows), dim3(kDotThreads), 0, s, A, lda, v, d->n, d->partial, gate);
+    hipLaunchKernelGGL(k_dots_final, dim3(rows), dim3(kDotThreads), 0, s, d->partial, nb, out, out_stride, out2,
+                       out2_stride, gate);
+    return hipGetLastError();
+}
+
+// V[m] := normalised, orthogonalised t; W[m] = H V[m]; new column of G.
+int expand(davidson d, hipStream_t s) {
+    hipError_t e;
+    const int64_t n = d->n;
+    const int m = d->m;
+    double *nrm2 = d->scal + 2;
+    for (int pass = 0; pass < 2; ++pass) {
+        if ((e = dots(d, d->V, n, m, d->t, d->coef, 1, nullptr, 0, nullptr, s)) != hipSuccess) return hip_fail(e, "davidson: projection");
+        hipLaunchKernelGGL(k_project, dim3(grid_n(n)), dim3(256), 0, s, d->V, n, m, d->coef, d->t, nullptr);
+    }
+    if ((e = dots(d, d->t, n, 1, d->t, nrm2, 1, nullptr, 0, nullptr, s)) != hipSuccess) return hip_fail(e, "davidson: norm");
+    hipLaunchKernelGGL(k_fallback, dim3(grid_n(n)), dim3(256), 0, s, nrm2, d->r, d->t, n, d->gate);
+    for (int pass = 0; pass < 2; ++pass) {
+        dots(d, d->V, n, m, d->t, d->coef, 1, nullptr, 0, d->gate, s);
+        hipLaunchKernelGGL(k_project, dim3(grid_n(n)), dim3(256), 0, s, d->V, n, m, d->coef, d->t, d->gate);
+    }
+    dots(d, d->t, n, 1, d->t, nrm2, 1, nullptr, 0, d->gate, s);
+    double *vm = d->V + static_cast<int64_t>(m) * n;
+    double *wm = d->W + static_cast<int64_t>(m) * n;
+    hipLaunchKernelGGL(k_scale_into, dim3(grid_n(n)), dim3(256), 0, s, d->t, nrm2, vm, n);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "davidson: orthogonalisation");
+    int rc = heff_apply(d->H, vm, wm, s);
+    if (rc != OZ_OK) return rc;
+    // G[i][m] = G[m][i] = V[i] . W[m], i <= m
+    if ((e = dots(d, d->V, n, m + 1, wm, d->G + m, d->m_max, d->G + static_cast<int64_t>(m) * d->m_max, 1, nullptr, s)) != hipSuccess)
+        return hip_fail(e, "davidson: projected column");
+    d->m = m + 1;
+    return OZ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int davidson_create(ozaki_ctx ctx, davidson *out, heff_plan H, const double *hdiag, const double *x0,
+                    int m_max, double tol, int max_iter, void *stream) {
+    if (!out) return fail(OZ_ERR_ARG, "davidson_create: out is NULL");
+    *out = nullptr;
+    if (!ctx || !H || !hdiag || !x0) return fail(OZ_ERR_ARG, "davidson_create: NULL argument");
+    if (m_max < 2 || m_max > 64) return fail(OZ_ERR_ARG, "davidson_create: m_max = %d (2..64)", m_max);
+    if (!(tol >= 0) || max_iter < 1) return fail(OZ_ERR_ARG, "davidson_create: tol / max_iter");
+    const int64_t n = heff_vector_length(H);
+    if (n < 1) return fail(OZ_ERR_ARG, "davidson_create: empty operator");
+    hipError_t e;
+    if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    davidson d = new davidson_s();
+    d->ctx = ctx;
+    d->H = H;
+    d->n = n;
+    d->m_max = m_max;
+    d->tol = tol;
+    d->max_iter = max_iter;
+    int rc;
+    void *p;
+#define OZ_DA(field, bytes) \
+    if ((rc = dalloc(d, (bytes), &p)) != OZ_OK) { dfree(d); return rc; } \
+    d->field = static_cast<decltype(d->field)>(p);
+    OZ_DA(V, sizeof(double) * m_max * n)
+    OZ_DA(W, sizeof(double) * m_max * n)
+    OZ_DA(G, sizeof(double) * m_max * m_max)
+    OZ_DA(hdiag, sizeof(double) * n)
+    OZ_DA(x, sizeof(double) * n)
+    OZ_DA(hx, sizeof(double) * n)
+    OZ_DA(r, sizeof(double) * n)
+    OZ_DA(t, sizeof(double) * n)
+    OZ_DA(y, sizeof(double) * 64)
+    OZ_DA(coef, sizeof(double) * 64)
+    OZ_DA(partial, sizeof(double) * 65 * 512)
+    OZ_DA(scal, sizeof(double) * 8)
+    OZ_DA(gate, sizeof(int) * 4)
+#undef OZ_DA
+    if ((e = hipHostMalloc(reinterpret_cast<void **>(&d->host), sizeof(double) * 4, 0)) != hipSuccess) {
+        d->host = nullptr;
+        dfree(d);
+        return hip_fail(e, "davidson_create: pinned buffer");
+    }
+    if ((e = hipMemcpyAsync(d->hdiag, hdiag, sizeof(double) * n, hipMemcpyDeviceToDevice, s)) != hipSuccess ||
+        (e = hipMemsetAsync(d->G, 0, sizeof(double) * m_max * m_max, s)) != hipSuccess) {
+        dfree(d);
+        return hip_fail(e, "davidson_create: copies");
+    }
+    // v0 = x0 / |x0|, W0 = H v0, G00 = v0 . W0
+    double *nrm2 = d->scal + 2;
+    if ((e = dots(d, x0, n, 1, x0, nrm2, 1, nullptr, 0, nullptr, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(d->host, nrm2, sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess) {
+        dfree(d);
+        return hip_fail(e, "davidson_create: start vector");
+    }
+    if (!(d->host[0] > 0) || !std::isfinite(d->host[0])) {
+        dfree(d);
+        return fail(OZ_ERR_ARG, "davidson_create: start vector is zero or not finite");
+    }
+    hipLaunchKernelGGL(k_scale_into, dim3(grid_n(n)), dim3(256), 0, s, x0, nrm2, d->V, n);
+    if ((rc = heff_apply(H, d->V, d->W, s)) != OZ_OK) { dfree(d); return rc; }
+    dots(d, d->V, n, 1, d->W, d->G, 1, nullptr, 0, nullptr, s);
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) { dfree(d); return hip_fail(e, "davidson_create: sync"); }
+    d->m = 1;
+    *out = d;
+    return OZ_OK;
+}
+
+int davidson_step(davidson d, davidson_info *info, void *stream) {
+    if (!d) return fail(OZ_ERR_ARG, "davidson_step: NULL solver");
+    if (d->status != OZ_OK) {
+        if (info) *info = davidson_info{d->host[0], std::sqrt(d->host[1]), d->iter, d->m, d->status};
+        return fail(OZ_ERR_STATE, "davidson_step: the iteration has already ended (%s)", ozaki_status_string(d->status));
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    if ((e = hipSetDevice(d->ctx->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+    const int64_t n = d->n;
+    double *theta = d->scal, *rho2 = d->scal + 1;
+    // Rayleigh-Ritz, Ritz pair and residual
+    hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(256), 0, s, d->G, d->m_max, d->m, d->y, theta);
+    const int nb = dot_blocks(n);
+    hipLaunchKernelGGL(k_ritz, dim3(nb), dim3(kDotThreads), 0, s, d->V, d->W, n, d->m, d->y, theta, d->x, d->hx, d->r,
+                       d->partial);
+    hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(kDotThreads), 0, s, d->partial, nb, rho2, 1, nullptr, 0, nullptr);
+    if ((e = hipMemcpyAsync(d->host, d->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(e, "davidson_step: Rayleigh-Ritz");
+    d->iter += 1;
+    const double rho = std::sqrt(d->host[1]);
+    d->hist.push_back(rho);
+    int status = OZ_OK;
+    const size_t w = 20;
+    if (rho <= d->tol) {
+        status = OZ_CONVERGED;
+    } else if (d->hist.size() > w) {
+        // stagnated: the last w residuals never got below half the best before them
+        const size_t first_recent = d->hist.size() - w;
+        double recent = INFINITY, before = INFINITY;
+        for (size_t i = 0; i < d->hist.size(); ++i) {
+            if (i >= first_recent)
+                recent = std::min(recent, d->hist[i]);
+            else
+                before = std::min(before, d->hist[i]);
+        }
+        if (recent > 0.5 * before) status = OZ_STAGNATED;
+    }
+    if (status == OZ_OK && d->iter >= d->max_iter) status = OZ_MAX_ITER;
+    if (status == OZ_OK) {
+        hipLaunchKernelGGL(k_precond, dim3(grid_n(n)), dim3(256), 0, s, d->r, d->hdiag, theta, d->t, n);
+        if (d->m == d->m_max) {
+            hipMemcpyAsync(d->V, d->x, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
+            hipMemcpyAsync(d->W, d->hx, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
+            hipLaunchKernelGGL(k_collapse_g, dim3(1), dim3(256), 0, s, d->G, d->m_max, d->m_max, theta);
+            d->m = 1;
+        }
+        int rc = expand(d, s);
+        if (rc != OZ_OK) return rc;
+    }
+    d->status = status;
+    if (info) *info = davidson_info{d->host[0], rho, d->iter, d->m, status};
+    return status;
+}
+
+int davidson_get_vector(davidson d, double *x_out, void *stream) {
+    if (!d || !x_out) return fail(OZ_ERR_ARG, "davidson_get_vector: NULL argument");
+    if (d->iter == 0) return fail(OZ_ERR_STATE, "davidson_get_vector: no step taken yet");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(x_out, d->x, sizeof(double) * d->n, hipMemcpyDeviceToDevice, s);
+    return e == hipSuccess ? OZ_OK : hip_fail(e, "davidson_get_vector");
+}
+
+int davidson_destroy(davidson d) {
+    if (!d) return OZ_OK;
+    hipSetDevice(d->ctx->device);
+    hipDeviceSynchronize();
+    dfree(d);
+    return OZ_OK;
+}
+
+}  // extern "C"

@@ -148,9 +148,17 @@ __global__ __launch_bounds__(256) void k_dgemm_grouped(Dgemm64Args a) {
     __shared__ double sB[kBK][kBN + kPad];
     for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
         const TileDesc td = a.tiles[t];
-        const OutDesc od = a.outs[td.out];
-        dgemm_tile<false, TB>(a, [&](int i) { return a.terms[i]; }, td.term_begin, td.term_end,
-                              od, td.m0, td.n0, sA, sB);
+        OutDesc od = a.outs[td.out];
+        if (a.out_base) od.C = a.out_base + reinterpret_cast<intptr_t>(od.C);
+        const Term64 *terms = a.terms;
+        const double *b_base = a.b_base;
+        dgemm_tile<false, TB>(a,
+                              [&](int i) {
+                                  Term64 tm = terms[i];
+                                  if (b_base) tm.B = b_base + reinterpret_cast<intptr_t>(tm.B);
+                                  return tm;
+                              },
+                              td.term_begin, td.term_end, od, td.m0, td.n0, sA, sB);
         __syncthreads();
     }
 }

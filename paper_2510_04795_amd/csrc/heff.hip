@@ -1,0 +1,506 @@
+// Two-site effective-Hamiltonian application sigma = H_eff psi
+// ("Theory of TNS/DMRG": the second subroutine's Krylov solver applies this
+// operator to the two-site tensor of shape (D, d = 4, 4, D)).
+//
+// H_eff is a list of triples (op, lo, li, ri, ro, alpha); triple t adds
+// alpha L[op][lo, li] psi[li, ri] R[op][ro, ri]^T to sigma block (lo, ro).  A
+// dense two-site problem is one left and one right sector with phys = 16.
+//
+// Plan (built once per operator set):
+//  * distinct left products u = (op, lo, li, ri): T_u = L[op][lo, li] Psi[li, ri]
+//    with Psi the left x (phys * right) view of a psi block;
+//  * every sigma block is split into tiles; a tile owns its output and sums
+//    its triples' second products T'_u R^T (T'_u: the (left * phys) x right
+//    view of T_u) in list order, sigma = fma(alpha, c, sigma) from +0, so the
+//    result does not depend on scheduling and needs no atomics;
+//  * emulated mode: the int8 slices of every L and R block are made once here;
+//    psi and T are sliced on every apply (psi by columns, T by rows).
+// Apply = 7 launches whatever the block count: exponents + slices of psi,
+// grouped first product, exponents + slices of T, grouped second product,
+// diagonal term.  Nothing is allocated or synchronised, so it can be captured.
+#include <algorithm>
+#include <map>
+#include <tuple>
+#include <vector>
+
+#include "runtime.h"
+
+using namespace oz;
+
+struct heff_plan_s {
+    ozaki_ctx ctx = nullptr;
+    int S = 0, G = 0;  // S == 0: native FP64 path
+    int64_t n = 0;     // elements of psi / sigma
+    double flops = 0;
+    const double *diag = nullptr;
+    std::vector<void *> allocs;
+    // emulated path
+    SliceBlock *psi_blocks = nullptr;
+    SliceTask *psi_etasks = nullptr, *psi_stasks = nullptr;
+    int n_psi_etasks = 0, n_psi_stasks = 0;
+    int32_t *psi_e = nullptr;
+    int8_t *psi_p = nullptr;
+    double *T = nullptr;
+    SliceBlock *T_blocks = nullptr;
+    SliceTask *T_etasks = nullptr, *T_stasks = nullptr;
+    int n_T_etasks = 0, n_T_stasks = 0;
+    int32_t *T_e = nullptr;
+    int8_t *T_p = nullptr;
+    PairArgs argsL{}, argsR{};
+    // FP64 path
+    Dgemm64Args d64L{}, d64R{};
+};
+
+namespace {
+
+template <typename T>
+int upload(heff_plan p, const std::vector<T> &v, T **out) {
+    *out = nullptr;
+    if (v.empty()) return OZ_OK;
+    void *d = nullptr;
+    hipError_t e = hipMalloc(&d, sizeof(T) * v.size());
+    if (e != hipSuccess) return fail(OZ_ERR_NOMEM, "heff_plan_create: %zu bytes: %s", sizeof(T) * v.size(), hipGetErrorString(e));
+    p->allocs.push_back(d);
+    if ((e = hipMemcpy(d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "heff_plan_create: upload");
+    *out = static_cast<T *>(d);
+    return OZ_OK;
+}
+
+int alloc(heff_plan p, size_t bytes, void **out) {
+    *out = nullptr;
+    if (bytes == 0) return OZ_OK;
+    hipError_t e = hipMalloc(out, bytes);
+    if (e != hipSuccess) return fail(OZ_ERR_NOMEM, "heff_plan_create: %zu bytes: %s", bytes, hipGetErrorString(e));
+    p->allocs.push_back(*out);
+    return OZ_OK;
+}
+
+void free_plan(heff_plan p) {
+    for (void *d : p->allocs) hipFree(d);
+    delete p;
+}
+
+// Slice descriptors for a list of blocks: exponent tasks (4 rows or 256
+// columns each) and slice tasks (32 groups x one 32-wide K block each).
+struct SliceSet {
+    std::vector<SliceBlock> blocks;
+    std::vector<SliceTask> etasks, stasks;
+    int64_t e_total = 0, p_total = 0;
+
+    int64_t add(int64_t x_off, int64_t ld, int64_t R, int64_t K, bool trans, int S, int64_t *e_off,
+                int64_t *p_off) {
+        SliceBlock b{};
+        b.x_off = x_off;
+        b.ld = ld;
+        b.R = static_cast<int32_t>(R);
+        b.K = static_cast<int32_t>(K);
+        b.trans = trans ? 1 : 0;
+        b.Rp = round_up(R, kRowQ);
+        b.e_off = e_total;
+        b.p_off = p_total;
+        *e_off = b.e_off;
+        *p_off = b.p_off;
+        e_total += b.Rp;
+        p_total += align256(static_cast<size_t>(S) * b.Rp * round_up(K, kKB));
+        const int id = static_cast<int>(blocks.size());
+        blocks.push_back(b);
+        const int step = trans ? 256 : 4;
+        for (int64_t g = 0; g < R; g += step) etasks.push_back(SliceTask{id, static_cast<int32_t>(g), 0, 0});
+        for (int64_t kb = 0; kb < ceil_div(K, kKB); ++kb)
+            for (int64_t r0 = 0; r0 < b.Rp; r0 += 32)
+                stasks.push_back(SliceTask{id, static_cast<int32_t>(r0), static_cast<int32_t>(kb), 0});
+        return id;
+    }
+};
+
+// Slice a set of blocks of x_base once (plan creation): grouped exponent and
+// slice launches into freshly allocated exponent / packed buffers.
+int slice_once(heff_plan p, const SliceSet &set, const double *x_base, int S, hipStream_t s,
+               int32_t **e_out, int8_t **p_out) {
+    int rc;
+    SliceBlock *db;
+    SliceTask *de, *ds;
+    void *e_mem, *p_mem;
+    if ((rc = upload(p, set.blocks, &db)) || (rc = upload(p, set.etasks, &de)) ||
+        (rc = upload(p, set.stasks, &ds)))
+        return rc;
+    if ((rc = alloc(p, sizeof(int32_t) * std::max<int64_t>(set.e_total, 1), &e_mem)) ||
+        (rc = alloc(p, std::max<int64_t>(set.p_total, 256), &p_mem)))
+        return rc;
+    hipError_t e;
+    if ((e = launch_exponents_grouped(db, de, static_cast<int>(set.etasks.size()), x_base,
+                                      static_cast<int32_t *>(e_mem), p->ctx->d_flags, s)) != hipSuccess)
+        return hip_fail(e, "heff_plan_create: exponents");
+    if ((e = launch_slice_grouped(S, db, ds, static_cast<int>(set.stasks.size()), x_base,
+                                  static_cast<int32_t *>(e_mem), static_cast<int8_t *>(p_mem), s)) != hipSuccess)
+        return hip_fail(e, "heff_plan_create: slices");
+    *e_out = static_cast<int32_t *>(e_mem);
+    *p_out = static_cast<int8_t *>(p_mem);
+    return OZ_OK;
+}
+
+struct TileWork {
+    TileDesc td;
+    int64_t cost;
+};
+
+void sort_tiles(std::vector<TileWork> &w, std::vector<TileDesc> *out) {
+    std::stable_sort(w.begin(), w.end(), [](const TileWork &a, const TileWork &b) { return a.cost > b.cost; });
+    out->clear();
+    for (auto &x : w) out->push_back(x.td);
+}
+
+}  // namespace
+
+extern "C" {
+
+int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const double *L_data,
+                     const double *R_data, int32_t n_triples, const heff_triple *triples,
+                     const double *diag, int slices, int ndiag, void *stream) {
+    if (!out) return fail(OZ_ERR_ARG, "heff_plan_create: out is NULL");
+    *out = nullptr;
+    if (!ctx || !L) return fail(OZ_ERR_ARG, "heff_plan_create: NULL ctx or layout");
+    if (slices != 0 && (slices < 2 || slices > 8)) return fail(OZ_ERR_ARG, "heff_plan_create: slices = %d", slices);
+    const int S = slices;
+    const int G = S ? resolve_ndiag(S, ndiag) : 0;
+    if (S && !valid_sg(S, G)) return fail(OZ_ERR_ARG, "heff_plan_create: ndiag = %d", ndiag);
+    if (L->n_left < 1 || L->n_right < 1 || L->phys < 1 || !L->left_dim || !L->right_dim)
+        return fail(OZ_ERR_ARG, "heff_plan_create: empty sector list");
+    if (n_triples < 0 || (n_triples > 0 && !triples)) return fail(OZ_ERR_ARG, "heff_plan_create: triples");
+    const int64_t p = L->phys;
+    std::vector<int64_t> ld(L->left_dim, L->left_dim + L->n_left), rd(L->right_dim, L->right_dim + L->n_right);
+    for (auto d : ld) if (d < 1) return fail(OZ_ERR_ARG, "heff_plan_create: left sector size %lld", (long long)d);
+    for (auto d : rd) if (d < 1) return fail(OZ_ERR_ARG, "heff_plan_create: right sector size %lld", (long long)d);
+
+    // psi / sigma blocks
+    std::map<std::pair<int, int>, int> psi_of;
+    std::vector<std::pair<int64_t, int64_t>> extents;
+    int64_t n = 0;
+    for (int b = 0; b < L->n_psi_blocks; ++b) {
+        const int l = L->psi_lr[2 * b], r = L->psi_lr[2 * b + 1];
+        if (l < 0 || l >= L->n_left || r < 0 || r >= L->n_right) return fail(OZ_ERR_ARG, "heff_plan_create: psi block %d sectors", b);
+        if (psi_of.count({l, r})) return fail(OZ_ERR_ARG, "heff_plan_create: psi block (%d, %d) repeated", l, r);
+        if (L->psi_offset[b] < 0) return fail(OZ_ERR_ARG, "heff_plan_create: psi offset");
+        psi_of[{l, r}] = b;
+        const int64_t sz = ld[l] * p * rd[r];
+        extents.push_back({L->psi_offset[b], L->psi_offset[b] + sz});
+        n = std::max(n, L->psi_offset[b] + sz);
+    }
+    std::sort(extents.begin(), extents.end());
+    for (size_t i = 1; i < extents.size(); ++i)
+        if (extents[i].first < extents[i - 1].second) return fail(OZ_ERR_ARG, "heff_plan_create: psi blocks overlap");
+    std::map<std::tuple<int, int, int>, int> L_of, R_of;
+    for (int i = 0; i < L->n_L_blocks; ++i) {
+        auto key = std::make_tuple(L->L_key[3 * i], L->L_key[3 * i + 1], L->L_key[3 * i + 2]);
+        if (std::get<1>(key) < 0 || std::get<1>(key) >= L->n_left || std::get<2>(key) < 0 || std::get<2>(key) >= L->n_left)
+            return fail(OZ_ERR_ARG, "heff_plan_create: L block %d sectors", i);
+        L_of[key] = i;
+    }
+    for (int i = 0; i < L->n_R_blocks; ++i) {
+        auto key = std::make_tuple(L->R_key[3 * i], L->R_key[3 * i + 1], L->R_key[3 * i + 2]);
+        if (std::get<1>(key) < 0 || std::get<1>(key) >= L->n_right || std::get<2>(key) < 0 || std::get<2>(key) >= L->n_right)
+            return fail(OZ_ERR_ARG, "heff_plan_create: R block %d sectors", i);
+        R_of[key] = i;
+    }
+    if ((L->n_L_blocks > 0 && !L_data) || (L->n_R_blocks > 0 && !R_data)) return fail(OZ_ERR_ARG, "heff_plan_create: L_data / R_data NULL");
+
+    // distinct left products and the triples of every sigma block
+    std::map<std::tuple<int, int, int, int>, int> u_of;
+    struct U { int op, lo, li, ri, Lb, psib; int64_t t_off; };
+    std::vector<U> us;
+    std::vector<std::vector<int>> by_sigma(L->n_psi_blocks);
+    std::vector<int> tri_u(n_triples), tri_R(n_triples);
+    int64_t t_total = 0;
+    double flops = 0;
+    for (int t = 0; t < n_triples; ++t) {
+        const heff_triple &tr = triples[t];
+        auto lk = std::make_tuple(tr.op, tr.lo, tr.li);
+        auto rk = std::make_tuple(tr.op, tr.ro, tr.ri);
+        if (!L_of.count(lk)) return fail(OZ_ERR_ARG, "heff_plan_create: triple %d: no L block (%d, %d, %d)", t, tr.op, tr.lo, tr.li);
+        if (!R_of.count(rk)) return fail(OZ_ERR_ARG, "heff_plan_create: triple %d: no R block (%d, %d, %d)", t, tr.op, tr.ro, tr.ri);
+        if (!psi_of.count({tr.li, tr.ri})) return fail(OZ_ERR_ARG, "heff_plan_create: triple %d: no psi block (%d, %d)", t, tr.li, tr.ri);
+        if (!psi_of.count({tr.lo, tr.ro})) return fail(OZ_ERR_ARG, "heff_plan_create: triple %d: no sigma block (%d, %d)", t, tr.lo, tr.ro);
+        auto uk = std::make_tuple(tr.op, tr.lo, tr.li, tr.ri);
+        auto it = u_of.find(uk);
+        if (it == u_of.end()) {
+            U u{tr.op, tr.lo, tr.li, tr.ri, L_of[lk], psi_of[{tr.li, tr.ri}], t_total};
+            t_total += ld[tr.lo] * p * rd[tr.ri];
+            flops += 2.0 * ld[tr.lo] * ld[tr.li] * (p * rd[tr.ri]);
+            it = u_of.emplace(uk, static_cast<int>(us.size())).first;
+            us.push_back(u);
+        }
+        tri_u[t] = it->second;
+        tri_R[t] = R_of[rk];
+        by_sigma[psi_of[{tr.lo, tr.ro}]].push_back(t);
+        flops += 2.0 * (ld[tr.lo] * p) * rd[tr.ri] * rd[tr.ro];
+        if (ld[tr.lo] * p > INT32_MAX / 2 || p * rd[tr.ri] > INT32_MAX / 2)
+            return fail(OZ_ERR_ARG, "heff_plan_create: block too large");
+        if (S && std::max<int64_t>(ld[tr.li], rd[tr.ri]) > max_exact_k(S, G))
+            return fail(OZ_ERR_UNSUPPORTED, "heff_plan_create: inner dimension above the exact int32 range");
+    }
+
+    hipError_t e;
+    if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    heff_plan P = new heff_plan_s();
+    P->ctx = ctx;
+    P->S = S;
+    P->G = G;
+    P->n = n;
+    P->flops = flops;
+    P->diag = diag;
+    int rc = OZ_OK;
+    void *mem = nullptr;
+    if ((rc = alloc(P, sizeof(double) * std::max<int64_t>(t_total, 1), &mem))) { free_plan(P); return rc; }
+    P->T = static_cast<double *>(mem);
+
+    if (S == 0) {
+        const PairShape sh = dgemm_shape();
+        // first product: T_u = L Psi  (op(B) = B, B offsets relative to psi)
+        std::vector<Term64> termsL;
+        std::vector<OutDesc> outsL;
+        std::vector<TileWork> wl;
+        for (size_t u = 0; u < us.size(); ++u) {
+            const U &x = us[u];
+            const int64_t M = ld[x.lo], N = p * rd[x.ri], K = ld[x.li];
+            Term64 tm{};
+            tm.A = L_data + L->L_offset[x.Lb];
+            tm.lda = K;
+            tm.B = reinterpret_cast<const double *>(static_cast<intptr_t>(L->psi_offset[x.psib]));
+            tm.ldb = N;
+            tm.K = static_cast<int32_t>(K);
+            tm.alpha = 1.0;
+            termsL.push_back(tm);
+            outsL.push_back(OutDesc{P->T + x.t_off, N, static_cast<int32_t>(M), static_cast<int32_t>(N)});
+            for (int64_t m0 = 0; m0 < M; m0 += sh.bm)
+                for (int64_t n0 = 0; n0 < N; n0 += sh.bn)
+                    wl.push_back({TileDesc{static_cast<int32_t>(u), static_cast<int32_t>(u + 1), static_cast<int32_t>(m0),
+                                           static_cast<int32_t>(n0), static_cast<int32_t>(u), 0}, K});
+        }
+        // second product: sigma' = sum alpha T'_u R^T  (op(B) = R^T)
+        std::vector<Term64> termsR;
+        std::vector<OutDesc> outsR;
+        std::vector<TileWork> wr;
+        for (int b = 0; b < L->n_psi_blocks; ++b) {
+            const int lo = L->psi_lr[2 * b], ro = L->psi_lr[2 * b + 1];
+            const int64_t M = ld[lo] * p, N = rd[ro];
+            const int tb = static_cast<int>(termsR.size());
+            int64_t cost = 0;
+            for (int t : by_sigma[b]) {
+                const U &x = us[tri_u[t]];
+                Term64 tm{};
+                tm.A = P->T + x.t_off;
+                tm.lda = rd[x.ri];
+                tm.B = R_data + L->R_offset[tri_R[t]];
+                tm.ldb = rd[x.ri];
+                tm.K = static_cast<int32_t>(rd[x.ri]);
+                tm.alpha = triples[t].alpha;
+                termsR.push_back(tm);
+                cost += rd[x.ri];
+            }
+            const int te = static_cast<int>(termsR.size());
+            outsR.push_back(OutDesc{reinterpret_cast<double *>(static_cast<intptr_t>(L->psi_offset[b])), N,
+                                    static_cast<int32_t>(M), static_cast<int32_t>(N)});
+            for (int64_t m0 = 0; m0 < M; m0 += sh.bm)
+                for (int64_t n0 = 0; n0 < N; n0 += sh.bn)
+                    wr.push_back({TileDesc{tb, te, static_cast<int32_t>(m0), static_cast<int32_t>(n0), b, 0}, cost});
+        }
+        std::vector<TileDesc> tl, tr;
+        sort_tiles(wl, &tl);
+        sort_tiles(wr, &tr);
+        TileDesc *dt;
+        Term64 *dm;
+        OutDesc *dout;
+        if ((rc = upload(P, tl, &dt)) || (rc = upload(P, termsL, &dm)) || (rc = upload(P, outsL, &dout))) { free_plan(P); return rc; }
+        P->d64L.tiles = dt; P->d64L.terms = dm; P->d64L.outs = dout;
+        P->d64L.ntiles = static_cast<int32_t>(tl.size());
+        P->d64L.mode = kModeGemm;
+        if ((rc = upload(P, tr, &dt)) || (rc = upload(P, termsR, &dm)) || (rc = upload(P, outsR, &dout))) { free_plan(P); return rc; }
+        P->d64R.tiles = dt; P->d64R.terms = dm; P->d64R.outs = dout;
+        P->d64R.ntiles = static_cast<int32_t>(tr.size());
+        P->d64R.mode = kModeAccum;
+        *out = P;
+        return OZ_OK;
+    }
+
+    // ---- emulated path: slice every L and R block once ----
+    SliceSet Ls, Rs;
+    std::vector<int64_t> L_eoff(L->n_L_blocks), L_poff(L->n_L_blocks), R_eoff(L->n_R_blocks), R_poff(L->n_R_blocks);
+    for (int i = 0; i < L->n_L_blocks; ++i) {
+        const int lo = L->L_key[3 * i + 1], li = L->L_key[3 * i + 2];
+        Ls.add(L->L_offset[i], ld[li], ld[lo], ld[li], false, S, &L_eoff[i], &L_poff[i]);
+    }
+    for (int i = 0; i < L->n_R_blocks; ++i) {
+        const int ro = L->R_key[3 * i + 1], ri = L->R_key[3 * i + 2];
+        Rs.add(L->R_offset[i], rd[ri], rd[ro], rd[ri], false, S, &R_eoff[i], &R_poff[i]);
+    }
+    int32_t *Le, *Re;
+    int8_t *Lp, *Rp;
+    if ((rc = slice_once(P, Ls, L_data, S, s, &Le, &Lp)) || (rc = slice_once(P, Rs, R_data, S, s, &Re, &Rp))) { free_plan(P); return rc; }
+
+    // psi blocks sliced by columns of the left x (phys * right) view, on every apply
+    SliceSet Ps;
+    std::vector<int64_t> P_eoff(L->n_psi_blocks), P_poff(L->n_psi_blocks);
+    for (int b = 0; b < L->n_psi_blocks; ++b) {
+        const int l = L->psi_lr[2 * b], r = L->psi_lr[2 * b + 1];
+        Ps.add(L->psi_offset[b], p * rd[r], p * rd[r], ld[l], true, S, &P_eoff[b], &P_poff[b]);
+    }
+    // T_u sliced by rows of the (left * phys) x right view
+    SliceSet Ts;
+    std::vector<int64_t> T_eoff(us.size()), T_poff(us.size());
+    for (size_t u = 0; u < us.size(); ++u) {
+        const U &x = us[u];
+        Ts.add(x.t_off, rd[x.ri], ld[x.lo] * p, rd[x.ri], false, S, &T_eoff[u], &T_poff[u]);
+    }
+    void *pe, *pp, *te_, *tp;
+    if ((rc = upload(P, Ps.blocks, &P->psi_blocks)) || (rc = upload(P, Ps.etasks, &P->psi_etasks)) ||
+        (rc = upload(P, Ps.stasks, &P->psi_stasks)) || (rc = upload(P, Ts.blocks, &P->T_blocks)) ||
+        (rc = upload(P, Ts.etasks, &P->T_etasks)) || (rc = upload(P, Ts.stasks, &P->T_stasks)) ||
+        (rc = alloc(P, sizeof(int32_t) * std::max<int64_t>(Ps.e_total, 1), &pe)) ||
+        (rc = alloc(P, std::max<int64_t>(Ps.p_total, 256), &pp)) ||
+        (rc = alloc(P, sizeof(int32_t) * std::max<int64_t>(Ts.e_total, 1), &te_)) ||
+        (rc = alloc(P, std::max<int64_t>(Ts.p_total, 256), &tp))) { free_plan(P); return rc; }
+    P->n_psi_etasks = static_cast<int>(Ps.etasks.size());
+    P->n_psi_stasks = static_cast<int>(Ps.stasks.size());
+    P->n_T_etasks = static_cast<int>(Ts.etasks.size());
+    P->n_T_stasks = static_cast<int>(Ts.stasks.size());
+    P->psi_e = static_cast<int32_t *>(pe);
+    P->psi_p = static_cast<int8_t *>(pp);
+    P->T_e = static_cast<int32_t *>(te_);
+    P->T_p = static_cast<int8_t *>(tp);
+
+    const PairShape sh = pair_shape(S, G);
+    // first product tiles: one term each, written to T_u
+    std::vector<TermDesc> termsL;
+    std::vector<OutDesc> outsL;
+    std::vector<TileWork> wl;
+    for (size_t u = 0; u < us.size(); ++u) {
+        const U &x = us[u];
+        const int64_t M = ld[x.lo], N = p * rd[x.ri], K = ld[x.li];
+        TermDesc tm{};
+        tm.A = Lp + L_poff[x.Lb];
+        tm.e = Le + L_eoff[x.Lb];
+        tm.a_rows_p = round_up(M, kRowQ);
+        tm.B = P->psi_p + P_poff[x.psib];
+        tm.f = P->psi_e + P_eoff[x.psib];
+        tm.b_rows_p = round_up(N, kRowQ);
+        tm.kblocks = static_cast<int32_t>(ceil_div(K, kKB));
+        tm.alpha = 1.0;
+        termsL.push_back(tm);
+        outsL.push_back(OutDesc{P->T + x.t_off, N, static_cast<int32_t>(M), static_cast<int32_t>(N)});
+        for (int64_t m0 = 0; m0 < M; m0 += sh.bm)
+            for (int64_t n0 = 0; n0 < N; n0 += sh.bn)
+                wl.push_back({TileDesc{static_cast<int32_t>(u), static_cast<int32_t>(u + 1), static_cast<int32_t>(m0),
+                                       static_cast<int32_t>(n0), static_cast<int32_t>(u), 0}, tm.kblocks});
+    }
+    // second product tiles: each sigma tile sums its triples in list order
+    std::vector<TermDesc> termsR;
+    std::vector<OutDesc> outsR;
+    std::vector<TileWork> wr;
+    for (int b = 0; b < L->n_psi_blocks; ++b) {
+        const int lo = L->psi_lr[2 * b], ro = L->psi_lr[2 * b + 1];
+        const int64_t M = ld[lo] * p, N = rd[ro];
+        const int tb = static_cast<int>(termsR.size());
+        int64_t cost = 0;
+        for (int t : by_sigma[b]) {
+            const int u = tri_u[t];
+            const U &x = us[u];
+            TermDesc tm{};
+            tm.A = P->T_p + T_poff[u];
+            tm.e = P->T_e + T_eoff[u];
+            tm.a_rows_p = round_up(M, kRowQ);
+            tm.B = Rp + R_poff[tri_R[t]];
+            tm.f = Re + R_eoff[tri_R[t]];
+            tm.b_rows_p = round_up(N, kRowQ);
+            tm.kblocks = static_cast<int32_t>(ceil_div(rd[x.ri], kKB));
+            tm.alpha = triples[t].alpha;
+            termsR.push_back(tm);
+            cost += tm.kblocks;
+        }
+        const int te = static_cast<int>(termsR.size());
+        outsR.push_back(OutDesc{reinterpret_cast<double *>(static_cast<intptr_t>(L->psi_offset[b])), N,
+                                static_cast<int32_t>(M), static_cast<int32_t>(N)});
+        for (int64_t m0 = 0; m0 < M; m0 += sh.bm)
+            for (int64_t n0 = 0; n0 < N; n0 += sh.bn)
+                wr.push_back({TileDesc{tb, te, static_cast<int32_t>(m0), static_cast<int32_t>(n0), b, 0}, cost});
+    }
+    std::vector<TileDesc> tl, tr;
+    sort_tiles(wl, &tl);
+    sort_tiles(wr, &tr);
+    TileDesc *dt;
+    TermDesc *dm;
+    OutDesc *dout;
+    if ((rc = upload(P, tl, &dt)) || (rc = upload(P, termsL, &dm)) || (rc = upload(P, outsL, &dout))) { free_plan(P); return rc; }
+    P->argsL.tiles = dt; P->argsL.terms = dm; P->argsL.outs = dout;
+    P->argsL.ntiles = static_cast<int32_t>(tl.size());
+    P->argsL.mode = kModeGemm;
+    if ((rc = upload(P, tr, &dt)) || (rc = upload(P, termsR, &dm)) || (rc = upload(P, outsR, &dout))) { free_plan(P); return rc; }
+    P->argsR.tiles = dt; P->argsR.terms = dm; P->argsR.outs = dout;
+    P->argsR.ntiles = static_cast<int32_t>(tr.size());
+    P->argsR.mode = kModeAccum;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) { free_plan(P); return hip_fail(e, "heff_plan_create: sync"); }
+    *out = P;
+    return OZ_OK;
+}
+
+int heff_apply(heff_plan P, const double *psi, double *sigma, void *stream) {
+    if (!P) return fail(OZ_ERR_ARG, "heff_apply: plan is NULL");
+    if (P->n > 0 && (!psi || !sigma)) return fail(OZ_ERR_ARG, "heff_apply: psi / sigma NULL");
+    if (psi == sigma && P->n > 0) return fail(OZ_ERR_ARG, "heff_apply: psi and sigma overlap");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    ozaki_ctx ctx = P->ctx;
+    hipError_t e;
+    if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+    if (P->S == 0) {
+        hipEvent_t t0 = mark(ctx, s);
+        Dgemm64Args a = P->d64L;
+        a.b_base = psi;
+        if ((e = launch_dgemm_grouped(false, a, a.ntiles, s)) != hipSuccess) return hip_fail(e, "heff_apply: first product");
+        hipEvent_t t1 = mark(ctx, s);
+        phase(ctx, OZ_PHASE_HEFF_L, t0, t1);
+        Dgemm64Args b = P->d64R;
+        b.out_base = sigma;
+        if ((e = launch_dgemm_grouped(true, b, b.ntiles, s)) != hipSuccess) return hip_fail(e, "heff_apply: second product");
+        hipEvent_t t2 = mark(ctx, s);
+        phase(ctx, OZ_PHASE_HEFF_R, t1, t2);
+    } else {
+        hipEvent_t t0 = mark(ctx, s);
+        if ((e = launch_exponents_grouped(P->psi_blocks, P->psi_etasks, P->n_psi_etasks, psi, P->psi_e, ctx->d_flags, s)) != hipSuccess ||
+            (e = launch_slice_grouped(P->S, P->psi_blocks, P->psi_stasks, P->n_psi_stasks, psi, P->psi_e, P->psi_p, s)) != hipSuccess)
+            return hip_fail(e, "heff_apply: slicing psi");
+        hipEvent_t t1 = mark(ctx, s);
+        phase(ctx, OZ_PHASE_HEFF_AUX, t0, t1);
+        if ((e = launch_pair_grouped(P->S, P->G, P->argsL, 0, s)) != hipSuccess) return hip_fail(e, "heff_apply: first product");
+        hipEvent_t t2 = mark(ctx, s);
+        phase(ctx, OZ_PHASE_HEFF_L, t1, t2);
+        if ((e = launch_exponents_grouped(P->T_blocks, P->T_etasks, P->n_T_etasks, P->T, P->T_e, ctx->d_flags, s)) != hipSuccess ||
+            (e = launch_slice_grouped(P->S, P->T_blocks, P->T_stasks, P->n_T_stasks, P->T, P->T_e, P->T_p, s)) != hipSuccess)
+            return hip_fail(e, "heff_apply: slicing T");
+        hipEvent_t t3 = mark(ctx, s);
+        phase(ctx, OZ_PHASE_HEFF_AUX, t2, t3);
+        PairArgs b = P->argsR;
+        b.out_base = sigma;
+        if ((e = launch_pair_grouped(P->S, P->G, b, 0, s)) != hipSuccess) return hip_fail(e, "heff_apply: second product");
+        hipEvent_t t4 = mark(ctx, s);
+        phase(ctx, OZ_PHASE_HEFF_R, t3, t4);
+    }
+    if (P->diag) {
+        if ((e = launch_diag_axpy(P->diag, psi, sigma, P->n, s)) != hipSuccess) return hip_fail(e, "heff_apply: diagonal");
+    }
+    return OZ_OK;
+}
+
+int64_t heff_vector_length(heff_plan P) { return P ? P->n : -1; }
+
+double heff_flops(heff_plan P) { return P ? P->flops : 0.0; }
+
+int heff_plan_destroy(heff_plan P) {
+    if (!P) return OZ_OK;
+    hipSetDevice(P->ctx->device);
+    hipDeviceSynchronize();
+    free_plan(P);
+    return OZ_OK;
+}
+
+}  // extern "C"

@@ -74,6 +74,7 @@ struct PairArgs {
     int32_t qw_first;      // kModeQ64: first chunk stores instead of adding
     double beta;
     int32_t *Q;            // kModeQ output, [G][M][N]
+    double *out_base;      // grouped: when set, OutDesc::C holds an element offset from it
     // int64 partial sums [G][tiles_m*BM][tiles_n*BN] of earlier K chunks when
     // K exceeds the exact int32 range; added in the kModeGemm epilogue if set
     int64_t *Qw;
@@ -102,9 +103,30 @@ struct Dgemm64Args {
     int32_t mode;          // kModeGemm or kModeAccum
     int32_t pad_;
     double beta;
+    double *out_base;      // grouped: when set, OutDesc::C holds an element offset from it
+    const double *b_base;  // grouped: when set, Term64::B holds an element offset from it
 };
 
-// ---- launchers (kernels.hip) -------------------------------------------
+// Grouped slicing: many blocks in one launch.  Offsets are relative to base
+// pointers passed at launch, so the same descriptors serve every call.
+struct SliceBlock {
+    int64_t x_off;   // element offset of the block from the FP64 base
+    int64_t ld;      // leading dimension of the stored block
+    int32_t R, K;    // groups (rows of the packed operand) and inner length
+    int32_t trans;   // 0: stored R x K (groups are rows); 1: stored K x R (groups are columns)
+    int32_t pad_;
+    int64_t e_off;   // int32 offset of the group exponents from the exponent base
+    int64_t p_off;   // byte offset of the packed planes from the packed base
+    int64_t Rp;      // padded group count of the packed planes
+};
+struct SliceTask {
+    int32_t block;
+    int32_t a;       // exponent task: first group; slice task: first group (32-aligned)
+    int32_t b;       // slice task: 32-wide K block index
+    int32_t pad_;
+};
+
+// ---- launchers ---------------------------------------------------------
 // Shared exponents of each row of X (R x K, row-major, ld): e[r], flag on NaN/Inf.
 hipError_t launch_row_exponents(const double *X, int64_t ld, int64_t R, int64_t K, int32_t *e,
                                 uint32_t *flag, hipStream_t s);
@@ -117,6 +139,14 @@ hipError_t launch_col_exponents(const double *X, int64_t ld, int64_t K, int64_t 
 // trans = true: X is K x R (groups are columns).  Pads rows to Rp, K to Kp with 0.
 hipError_t launch_slice(int S, bool trans, const double *X, int64_t ld, int64_t R, int64_t K,
                         const int32_t *e, int8_t *packed, int64_t Rp, hipStream_t s);
+// Grouped exponent pass (tasks of 4 rows or 256 columns) and slice pass
+// (tasks of 32 groups x one 32-wide K block).
+hipError_t launch_exponents_grouped(const SliceBlock *blocks, const SliceTask *tasks, int ntasks,
+                                    const double *x_base, int32_t *e_base, uint32_t *flag,
+                                    hipStream_t s);
+hipError_t launch_slice_grouped(int S, const SliceBlock *blocks, const SliceTask *tasks, int ntasks,
+                                const double *x_base, const int32_t *e_base, int8_t *p_base,
+                                hipStream_t s);
 // Debug conversions between [S][R][K] digits and the packed layout.
 hipError_t launch_pack(int S, const int8_t *canon, int64_t R, int64_t K, int8_t *packed,
                        int64_t Rp, hipStream_t s);

@@ -295,7 +295,8 @@ __global__ __launch_bounds__(256) void k_pair_grouped(PairArgs a) {
     __shared__ uint4 lds0[C::STAGE];
     __shared__ uint4 lds1[C::STAGE];
     const TileDesc td = a.tiles[blockIdx.x];
-    const OutDesc od = a.outs[td.out];
+    OutDesc od = a.outs[td.out];
+    if (a.out_base) od.C = a.out_base + reinterpret_cast<intptr_t>(od.C);
     const TermDesc *terms = a.terms;
     pair_tile<S, G, MB, NB, MODE>(a, [&](int i) { return terms[i]; }, td.term_begin, td.term_end,
                                   od, td.m0, td.n0, lds0, lds1);

@@ -7,12 +7,20 @@
 #include "../../include/ozaki.h"
 #include "internal.h"
 
+#include <vector>
+
 struct ozaki_ctx_s {
     int device = 0;
     int num_cu = 0;
     uint32_t *d_flags = nullptr;  // sticky OZ_FLAG_* bits on the device
     void *scratch = nullptr;      // grow-only scratch of the debug entry points
     size_t scratch_bytes = 0;
+    // phase timing (ozaki_ctx_set_timing)
+    bool timing = false;
+    std::vector<hipEvent_t> events;  // pool
+    size_t next_event = 0;
+    struct Rec { int phase; hipEvent_t a, b; };
+    std::vector<Rec> recs;
 };
 
 namespace oz {
@@ -30,6 +38,11 @@ struct GemmWorkspace {
     size_t a_dig, b_dig, e, f, part, qw, total;
 };
 GemmWorkspace gemm_workspace(int64_t M, int64_t N, int64_t K, int S, int G);
+
+// Phase timing: mark() records an event on s (or returns nullptr when timing
+// is off or the pool is used up); phase() files the pair under a phase id.
+hipEvent_t mark(ozaki_ctx ctx, hipStream_t s);
+void phase(ozaki_ctx ctx, int id, hipEvent_t a, hipEvent_t b);
 
 hipError_t slice_operand(int S, bool by_rows, const double *X, int64_t ld, int64_t R, int64_t K,
                          int32_t *e, int8_t *packed, double *part, uint32_t *flag, hipStream_t s);

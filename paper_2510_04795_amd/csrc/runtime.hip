@@ -75,6 +75,19 @@ hipError_t slice_operand(int S, bool by_rows, const double *X, int64_t ld, int64
     return launch_slice(S, !by_rows, X, ld, R, K, e, packed, round_up(R, kRowQ), s);
 }
 
+constexpr size_t kMaxEvents = 8192;
+
+hipEvent_t mark(ozaki_ctx ctx, hipStream_t s) {
+    if (!ctx || !ctx->timing || ctx->next_event >= ctx->events.size()) return nullptr;
+    hipEvent_t e = ctx->events[ctx->next_event++];
+    if (hipEventRecord(e, s) != hipSuccess) return nullptr;
+    return e;
+}
+
+void phase(ozaki_ctx ctx, int id, hipEvent_t a, hipEvent_t b) {
+    if (a && b) ctx->recs.push_back({id, a, b});
+}
+
 }  // namespace oz
 
 using namespace oz;
@@ -136,6 +149,7 @@ int ozaki_ctx_destroy(ozaki_ctx ctx) {
     hipDeviceSynchronize();
     if (ctx->scratch) hipFree(ctx->scratch);
     if (ctx->d_flags) hipFree(ctx->d_flags);
+    for (auto &ev : ctx->events) hipEventDestroy(ev);
     delete ctx;
     return OZ_OK;
 }
@@ -151,6 +165,38 @@ int ozaki_ctx_flags(ozaki_ctx ctx, uint32_t *flags_out) {
     if ((e = hipMemset(ctx->d_flags, 0, sizeof(uint32_t))) != hipSuccess) return hip_fail(e, "hipMemset");
     *flags_out = v;
     return OZ_OK;
+}
+
+int ozaki_ctx_set_timing(ozaki_ctx ctx, int enable) {
+    if (!ctx) return fail(OZ_ERR_ARG, "ozaki_ctx_set_timing: ctx is NULL");
+    hipError_t e;
+    if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+    if (enable && ctx->events.empty()) {
+        ctx->events.resize(kMaxEvents);
+        for (auto &ev : ctx->events)
+            if ((e = hipEventCreate(&ev)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+    }
+    ctx->timing = enable != 0;
+    return OZ_OK;
+}
+
+int ozaki_ctx_phase_times(ozaki_ctx ctx, int32_t *phase_out, double *ms, int32_t max_phases) {
+    if (!ctx || (max_phases > 0 && (!phase_out || !ms)))
+        return fail(OZ_ERR_ARG, "ozaki_ctx_phase_times: NULL argument");
+    hipError_t e;
+    int n = 0;
+    for (const auto &r : ctx->recs) {
+        if (n >= max_phases) break;
+        if ((e = hipEventSynchronize(r.b)) != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        float t = 0.f;
+        if ((e = hipEventElapsedTime(&t, r.a, r.b)) != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+        phase_out[n] = r.phase;
+        ms[n] = t;
+        ++n;
+    }
+    ctx->recs.clear();
+    ctx->next_event = 0;
+    return n;
 }
 
 int ozaki_slices_for_bits(int mantissa_bits) {
@@ -210,6 +256,7 @@ int ozaki_dgemm(ozaki_ctx ctx, char transa, char transb, int64_t M, int64_t N, i
     if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
 
     if (slices == 0) {
+        hipEvent_t t0 = mark(ctx, s);
         const PairShape sh = dgemm_shape();
         Dgemm64Args a{};
         a.tiles_n = static_cast<int32_t>(ceil_div(N, sh.bn));
@@ -218,6 +265,7 @@ int ozaki_dgemm(ozaki_ctx ctx, char transa, char transb, int64_t M, int64_t N, i
         a.mode = kModeGemm;
         a.beta = beta;
         e = launch_dgemm_single(ta, tb, a, static_cast<int>(ceil_div(M, sh.bm)), s);
+        phase(ctx, OZ_PHASE_FP64, t0, mark(ctx, s));
         return e == hipSuccess ? OZ_OK : hip_fail(e, "ozaki_dgemm (fp64) launch");
     }
 
@@ -235,11 +283,14 @@ int ozaki_dgemm(ozaki_ctx ctx, char transa, char transb, int64_t M, int64_t N, i
     const int64_t Mp = round_up(M, kRowQ), Np = round_up(N, kRowQ), Kp = round_up(K, kKB);
 
     // op(A) rows are stored rows when transa = 'N'; op(B) columns are stored rows when transb = 'T'
+    hipEvent_t t0 = mark(ctx, s);
     if ((e = slice_operand(slices, !ta, A, lda, M, K, ev, adig, part, ctx->d_flags, s)) != hipSuccess)
         return hip_fail(e, "ozaki_dgemm: slicing A");
     if ((e = slice_operand(slices, tb, B, ldb, N, K, fv, bdig, part, ctx->d_flags, s)) != hipSuccess)
         return hip_fail(e, "ozaki_dgemm: slicing B");
 
+    hipEvent_t t1 = mark(ctx, s);
+    phase(ctx, OZ_PHASE_SLICE, t0, t1);
     const PairShape sh = pair_shape(slices, G);
     PairArgs a{};
     a.tiles_n = static_cast<int32_t>(ceil_div(N, sh.bn));
@@ -269,9 +320,11 @@ int ozaki_dgemm(ozaki_ctx ctx, char transa, char transb, int64_t M, int64_t N, i
             if ((e = launch_pair_single(slices, G, c, tiles_m, s)) != hipSuccess)
                 return hip_fail(e, "ozaki_dgemm: pair GEMM launch (chunked)");
         }
+        phase(ctx, OZ_PHASE_PAIR, t1, mark(ctx, s));
         return OZ_OK;
     }
     e = launch_pair_single(slices, G, a, tiles_m, s);
+    phase(ctx, OZ_PHASE_PAIR, t1, mark(ctx, s));
     return e == hipSuccess ? OZ_OK : hip_fail(e, "ozaki_dgemm: pair GEMM launch");
 }
 

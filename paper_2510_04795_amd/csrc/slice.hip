@@ -160,6 +160,83 @@ hipError_t slice_s(bool trans, const double *X, int64_t ld, int64_t R, int64_t K
     return hipGetLastError();
 }
 
+// ---- grouped versions: one launch for a list of blocks -------------------
+__global__ __launch_bounds__(256) void k_exponents_grouped(const SliceBlock *__restrict__ blocks,
+                                                            const SliceTask *__restrict__ tasks,
+                                                            const double *__restrict__ x_base,
+                                                            int32_t *__restrict__ e_base,
+                                                            uint32_t *flag) {
+    const SliceTask tk = tasks[blockIdx.x];
+    const SliceBlock bl = blocks[tk.block];
+    const double *X = x_base + bl.x_off;
+    int32_t *e = e_base + bl.e_off;
+    if (bl.trans == 0) {
+        // four rows, one wave each
+        const int lane = threadIdx.x & 63;
+        const int r = tk.a + (threadIdx.x >> 6);
+        if (r >= bl.R) return;
+        const double *row = X + static_cast<int64_t>(r) * bl.ld;
+        double mu = 0.0;
+        for (int k = lane; k < bl.K; k += 64) mu = combine_max(mu, abs_or_nan(row[k]));
+        for (int off = 32; off >= 1; off >>= 1) mu = combine_max(mu, __shfl_xor(mu, off, 64));
+        if (lane == 0) e[r] = finish_exponent(mu, flag);
+    } else {
+        // 256 columns, one thread each, over all K rows
+        const int c = tk.a + threadIdx.x;
+        if (c >= bl.R) return;
+        double mu = 0.0;
+        for (int k = 0; k < bl.K; ++k) mu = combine_max(mu, abs_or_nan(X[static_cast<int64_t>(k) * bl.ld + c]));
+        e[c] = finish_exponent(mu, flag);
+    }
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void k_slice_grouped(const SliceBlock *__restrict__ blocks,
+                                                        const SliceTask *__restrict__ tasks,
+                                                        const double *__restrict__ x_base,
+                                                        const int32_t *__restrict__ e_base,
+                                                        int8_t *__restrict__ p_base) {
+    __shared__ uint4 tile[S * 2][32];
+    const SliceTask tk = tasks[blockIdx.x];
+    const SliceBlock bl = blocks[tk.block];
+    const double *X = x_base + bl.x_off;
+    const int32_t *e = e_base + bl.e_off;
+    const int t = threadIdx.x;
+    const int64_t r0 = tk.a;
+    const int64_t kb = tk.b;
+    const int64_t k0 = kb * 32;
+    int r, kq;
+    if (bl.trans) {
+        r = t & 31;
+        kq = t >> 5;
+    } else {
+        r = t >> 3;
+        kq = t & 7;
+    }
+    const int64_t gr = r0 + r;
+    double x[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t k = k0 + kq * 4 + q;
+        x[q] = 0.0;
+        if (gr < bl.R && k < bl.K) x[q] = bl.trans ? X[k * bl.ld + gr] : X[gr * bl.ld + k];
+    }
+    const int32_t ee = gr < bl.R ? e[gr] : 0;
+    uint32_t w[S];
+    slice4<S>(x, ee, w);
+    const int c = kq >> 2;
+    const int word = kq & 3;
+#pragma unroll
+    for (int s = 0; s < S; ++s) reinterpret_cast<uint32_t *>(&tile[s * 2 + c][r])[word] = w[s];
+    __syncthreads();
+    uint4 *out = reinterpret_cast<uint4 *>(p_base + bl.p_off);
+    for (int q = t; q < S * 2 * 32; q += 256) {
+        const int sc = q >> 5;
+        const int rr = q & 31;
+        out[(kb * S * 2 + sc) * bl.Rp + r0 + rr] = tile[sc][rr];
+    }
+}
+
 // Debug layout conversions, one byte per thread.
 __global__ void k_pack(int S, const int8_t *__restrict__ canon, int64_t R, int64_t K,
                        int8_t *__restrict__ packed, int64_t Rp, int64_t Kp) {
@@ -242,6 +319,32 @@ hipError_t launch_slice(int S, bool trans, const double *X, int64_t ld, int64_t 
         case 8: return slice_s<8>(trans, X, ld, R, K, e, packed, Rp, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_exponents_grouped(const SliceBlock *blocks, const SliceTask *tasks, int ntasks,
+                                    const double *x_base, int32_t *e_base, uint32_t *flag,
+                                    hipStream_t s) {
+    if (ntasks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_exponents_grouped, dim3(ntasks), dim3(256), 0, s, blocks, tasks, x_base,
+                       e_base, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_slice_grouped(int S, const SliceBlock *blocks, const SliceTask *tasks, int ntasks,
+                                const double *x_base, const int32_t *e_base, int8_t *p_base,
+                                hipStream_t s) {
+    if (ntasks == 0) return hipSuccess;
+#define OZ_SG(S_)                                                                                \
+    case S_:                                                                                     \
+        hipLaunchKernelGGL(k_slice_grouped<S_>, dim3(ntasks), dim3(256), 0, s, blocks, tasks,    \
+                           x_base, e_base, p_base);                                             \
+        break;
+    switch (S) {
+        OZ_SG(2) OZ_SG(3) OZ_SG(4) OZ_SG(5) OZ_SG(6) OZ_SG(7) OZ_SG(8)
+        default: return hipErrorInvalidValue;
+    }
+#undef OZ_SG
+    return hipGetLastError();
 }
 
 hipError_t launch_pack(int S, const int8_t *canon, int64_t R, int64_t K, int8_t *packed,

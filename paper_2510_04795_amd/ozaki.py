@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libozaki.so")
 OZ_OK, OZ_CONVERGED, OZ_STAGNATED, OZ_MAX_ITER = 0, 1, 2, 3
 OZ_FLAG_NONFINITE = 1
 OZ_EXP_NONFINITE = -(2 ** 31)
+PHASES = {1: "slice", 2: "pair", 3: "fp64", 4: "heff_L", 5: "heff_R", 6: "heff_aux"}
 STATUS = {0: "running", 1: "converged", 2: "stagnated", 3: "max_iter"}
 
 if not os.path.exists(LIB_PATH):
@@ -60,6 +61,8 @@ _sig("ozaki_version", _i32, [])
 _sig("ozaki_ctx_create", _i32, [ctypes.POINTER(_ptr), _i32])
 _sig("ozaki_ctx_destroy", _i32, [_ptr])
 _sig("ozaki_ctx_flags", _i32, [_ptr, ctypes.POINTER(ctypes.c_uint32)])
+_sig("ozaki_ctx_set_timing", _i32, [_ptr, _i32])
+_sig("ozaki_ctx_phase_times", _i32, [_ptr, _ptr, _ptr, _i32])
 _sig("ozaki_slices_for_bits", _i32, [_i32])
 _sig("ozaki_pair_count", _i32, [_i32, _i32])
 _sig("ozaki_max_exact_k", _i64, [_i32, _i32])
@@ -81,7 +84,8 @@ _sig("davidson_destroy", _i32, [_ptr])
 
 EXPORTED = [
     "ozaki_status_string", "ozaki_last_error", "ozaki_version", "ozaki_ctx_create",
-    "ozaki_ctx_destroy", "ozaki_ctx_flags", "ozaki_slices_for_bits", "ozaki_pair_count",
+    "ozaki_ctx_destroy", "ozaki_ctx_flags", "ozaki_ctx_set_timing", "ozaki_ctx_phase_times",
+    "ozaki_slices_for_bits", "ozaki_pair_count",
     "ozaki_max_exact_k", "ozaki_dgemm_workspace_bytes", "ozaki_dgemm", "ozaki_split",
     "ozaki_pair_products", "heff_plan_create", "heff_apply", "heff_vector_length", "heff_flops",
     "heff_plan_destroy", "davidson_create", "davidson_step", "davidson_get_vector",
@@ -167,6 +171,18 @@ class Context:
         v = ctypes.c_uint32(0)
         _check(_lib.ozaki_ctx_flags(self.handle, ctypes.byref(v)), "ozaki_ctx_flags")
         return int(v.value)
+
+    def set_timing(self, enable: bool = True):
+        _check(_lib.ozaki_ctx_set_timing(self.handle, int(bool(enable))), "ozaki_ctx_set_timing")
+
+    def phase_times(self, max_phases: int = 8192):
+        """[(phase name, ms)] recorded since the last call (waits for the events)."""
+        import numpy as np
+        ph = np.zeros(max_phases, dtype=np.int32)
+        ms = np.zeros(max_phases, dtype=np.float64)
+        n = _check(_lib.ozaki_ctx_phase_times(self.handle, ph.ctypes.data, ms.ctypes.data,
+                                              max_phases), "ozaki_ctx_phase_times")
+        return [(PHASES.get(int(p), str(int(p))), float(t)) for p, t in zip(ph[:n], ms[:n])]
 
     # ---- GEMM -----------------------------------------------------------
     def workspace(self, M, N, K, slices, ndiag=0) -> torch.Tensor | None:

@@ -218,3 +218,61 @@ def davidson_problem(D: int, kop: int = 32, norm: float = 10.0, well: float = -3
     x0 /= np.linalg.norm(x0)
     return DavidsonProblem(L=L, R=R, delta=delta, hdiag=hdiag,
                            x0=x0.reshape(D, D), scale=s)
+
+
+# ----------------------------------------------------------------------------
+# Flat layouts for the library's H_eff plan (data arrangement only)
+# ----------------------------------------------------------------------------
+def flatten_dense(L: np.ndarray, R: np.ndarray, psi: np.ndarray):
+    """Layout dict, flat L, flat R, flat psi and triples of a dense two-site
+    problem: one left and one right sector of size D, phys = psi.shape[1],
+    triples (k, 0, 0, 0, 0, 1) for every operator pair k."""
+    kop, D, _ = L.shape
+    p = psi.shape[1]
+    layout = {"left_dim": [D], "right_dim": [psi.shape[2]], "phys": p,
+              "psi_lr": [0, 0], "psi_offset": [0],
+              "L_key": [x for k in range(kop) for x in (k, 0, 0)],
+              "L_offset": [k * D * D for k in range(kop)],
+              "R_key": [x for k in range(kop) for x in (k, 0, 0)],
+              "R_offset": [k * R.shape[1] * R.shape[2] for k in range(kop)]}
+    triples = [(k, 0, 0, 0, 0, 1.0) for k in range(kop)]
+    return layout, np.ascontiguousarray(L).ravel(), np.ascontiguousarray(R).ravel(), \
+        np.ascontiguousarray(psi).ravel(), triples
+
+
+def flatten_sparse(prob: "HeffSparse"):
+    """Layout dict, flat L, flat R, flat psi and triples of a block-sparse
+    problem (phys = 1); blocks are stored in sorted key order."""
+    dims = [int(d) for d in prob.dims]
+    psi_off, off = [], 0
+    for (l, r) in prob.psi_blocks:
+        psi_off.append(off)
+        off += dims[l] * dims[r]
+    psi_flat = np.concatenate([prob.psi[b].ravel() for b in prob.psi_blocks]) if prob.psi_blocks else np.zeros(0)
+    Lk = sorted(prob.L)
+    Rk = sorted(prob.R)
+    L_off, o = [], 0
+    for k in Lk:
+        L_off.append(o)
+        o += prob.L[k].size
+    R_off, o = [], 0
+    for k in Rk:
+        R_off.append(o)
+        o += prob.R[k].size
+    layout = {"left_dim": dims, "right_dim": dims, "phys": 1,
+              "psi_lr": [x for b in prob.psi_blocks for x in b], "psi_offset": psi_off,
+              "L_key": [x for k in Lk for x in k], "L_offset": L_off,
+              "R_key": [x for k in Rk for x in k], "R_offset": R_off}
+    L_flat = np.concatenate([prob.L[k].ravel() for k in Lk]) if Lk else np.zeros(0)
+    R_flat = np.concatenate([prob.R[k].ravel() for k in Rk]) if Rk else np.zeros(0)
+    return layout, L_flat, R_flat, psi_flat, list(prob.triples)
+
+
+def unflatten_sparse(prob: "HeffSparse", flat: np.ndarray) -> dict:
+    """Blocks of a flat sigma laid out like flatten_sparse's psi."""
+    out, off = {}, 0
+    for (l, r) in prob.psi_blocks:
+        n = int(prob.dims[l]) * int(prob.dims[r])
+        out[(l, r)] = flat[off:off + n].reshape(int(prob.dims[l]), int(prob.dims[r]))
+        off += n
+    return out

@@ -1,0 +1,176 @@
+"""GPU parity of the two-site H_eff.psi plans against the CPU oracle.
+
+Emulated plans must match the oracle bit for bit (every sigma tile sums its
+triples in list order with the same FP64 steps); native FP64 plans are held
+to a bound derived from gamma_K of the two chained products.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2510_04795_amd import workloads as wl
+from tests.helpers import assert_bitexact
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def oz():
+    import torch
+    from paper_2510_04795_amd import ozaki
+    torch.cuda.init()
+    ctx = ozaki.Context(0)
+    yield ozaki, ctx, torch
+    ctx.close()
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def dense_plan(ozaki, ctx, torch, L, R, psi, S, G=0, diag=None):
+    layout, Lf, Rf, pf, triples = wl.flatten_dense(L, R, psi)
+    dL, dR = dev(torch, Lf), dev(torch, Rf)
+    dd = dev(torch, diag.ravel()) if diag is not None else None
+    plan = ozaki.HeffPlan(ctx, layout, dL, dR, triples, diag=dd, slices=S, ndiag=G)
+    return plan, dev(torch, pf), (dL, dR, dd)
+
+
+def fp64_bound(L, R, psi, K1, K2):
+    """Componentwise bound for two chained FP64 GEMM sums, summed over k."""
+    u = 2.0 ** -53
+    g = (K1 + K2 + 2) * u / (1 - (K1 + K2 + 2) * u)
+    D, p, D2 = psi.shape
+    aP = np.abs(psi).reshape(D, p * D2)
+    tot = np.zeros((D * p, D2))
+    for k in range(L.shape[0]):
+        tot += (np.abs(L[k]) @ aP).reshape(D * p, D2) @ np.abs(R[k]).T
+    return g * tot.reshape(D, p, D2) * (1 + L.shape[0] * u) + 1e-300
+
+
+@pytest.mark.parametrize("S,G", [(6, 6), (4, 5), (8, 9), (7, 13)])
+def test_dense_bitexact(oz, S, G):
+    ozaki, ctx, torch = oz
+    L, R, psi = wl.heff_dense(D=70, kop=3, phys=4, seed=S)
+    plan, dpsi, keep = dense_plan(ozaki, ctx, torch, L, R, psi, S, G)
+    sig = plan.apply(dpsi).cpu().numpy().reshape(psi.shape)
+    ref = oracle.heff_dense(L, R, psi, S=S, G=G)
+    assert_bitexact(sig, ref, "dense S=%d G=%d" % (S, G))
+    assert plan.flops == 64 * 70 ** 3 * 3 * 4 / 16
+
+
+def test_dense_phys16_with_diagonal(oz):
+    ozaki, ctx, torch = oz
+    L, R, psi = wl.heff_dense(D=40, kop=2, phys=16, seed=3)
+    diag = np.random.default_rng(4).standard_normal(psi.shape)
+    plan, dpsi, keep = dense_plan(ozaki, ctx, torch, L, R, psi, 6, 0, diag=diag)
+    sig = plan.apply(dpsi).cpu().numpy().reshape(psi.shape)
+    assert_bitexact(sig, oracle.heff_dense(L, R, psi, S=6, diag=diag), "phys16 diag")
+    # a second apply on the same plan gives the same bits (no state carried over)
+    sig2 = plan.apply(dpsi).cpu().numpy().reshape(psi.shape)
+    assert_bitexact(sig2, sig, "repeat")
+
+
+def test_dense_fp64_within_bound(oz):
+    ozaki, ctx, torch = oz
+    L, R, psi = wl.heff_dense(D=90, kop=3, phys=4, seed=5)
+    plan, dpsi, keep = dense_plan(ozaki, ctx, torch, L, R, psi, 0)
+    sig = plan.apply(dpsi).cpu().numpy().reshape(psi.shape)
+    ref = oracle.heff_dense(L, R, psi, S=0)
+    assert np.all(np.abs(sig - ref) <= 2 * fp64_bound(L, R, psi, 90, 90))
+
+
+def test_dense_d256_full(oz):
+    """D = 256, phys 16: several tiles in every direction, all rows checked."""
+    ozaki, ctx, torch = oz
+    L, R, psi = wl.heff_dense(D=256, kop=4, phys=16, seed=0)
+    plan, dpsi, keep = dense_plan(ozaki, ctx, torch, L, R, psi, 6)
+    sig = plan.apply(dpsi).cpu().numpy().reshape(psi.shape)
+    assert_bitexact(sig, oracle.heff_dense(L, R, psi, S=6), "D=256")
+
+
+def test_dense_d2048_sampled_rows(oz):
+    """D = 2048, phys 16 (the benchmark's shape, fewer operator pairs): rows
+    alpha' computed alone by the oracle, whole second products included."""
+    ozaki, ctx, torch = oz
+    L, R, psi = wl.heff_dense(D=2048, kop=4, phys=16, seed=0)
+    plan, dpsi, keep = dense_plan(ozaki, ctx, torch, L, R, psi, 6)
+    sig = plan.apply(dpsi).reshape(2048, 16, 2048)
+    rows = [5, 2047]
+    got = sig[rows].cpu().numpy()
+    ref = oracle.heff_dense_rows(L, R, psi, rows, S=6)
+    assert_bitexact(got, ref, "D=2048 rows")
+
+
+def small_sparse(seed):
+    return wl.heff_sparse(n_sectors=9, n_triples=80, kop=5, median=60, sigma_log=0.7,
+                          lo_hi=(7, 150), density=0.35, reach=2, U=12, seed=seed)
+
+
+def sparse_plan(ozaki, ctx, torch, prob, S, G=0):
+    layout, Lf, Rf, pf, triples = wl.flatten_sparse(prob)
+    dL, dR = dev(torch, Lf), dev(torch, Rf)
+    plan = ozaki.HeffPlan(ctx, layout, dL, dR, triples, slices=S, ndiag=G)
+    return plan, dev(torch, pf), (dL, dR)
+
+
+@pytest.mark.parametrize("S,G", [(6, 6), (5, 6), (8, 8)])
+def test_sparse_bitexact(oz, S, G):
+    ozaki, ctx, torch = oz
+    prob = small_sparse(10 + S)
+    plan, dpsi, keep = sparse_plan(ozaki, ctx, torch, prob, S, G)
+    sig = wl.unflatten_sparse(prob, plan.apply(dpsi).cpu().numpy())
+    ref = oracle.heff_sparse(prob, S=S, G=G)
+    for b in prob.psi_blocks:
+        assert_bitexact(sig[b], ref[b], "block %s" % (b,))
+
+
+def test_sparse_fp64(oz):
+    ozaki, ctx, torch = oz
+    prob = small_sparse(3)
+    plan, dpsi, keep = sparse_plan(ozaki, ctx, torch, prob, 0)
+    sig = wl.unflatten_sparse(prob, plan.apply(dpsi).cpu().numpy())
+    ref = oracle.heff_sparse(prob, S=0)
+    mag = {b: np.zeros_like(ref[b]) for b in prob.psi_blocks}
+    for (op, lo, li, ri, ro, al) in prob.triples:
+        mag[(lo, ro)] += abs(al) * (np.abs(prob.L[(op, lo, li)]) @ np.abs(prob.psi[(li, ri)])) @ np.abs(prob.R[(op, ro, ri)]).T
+    u = 2.0 ** -53
+    for b in prob.psi_blocks:
+        K = 2 * int(prob.dims.max()) + 2 + len(prob.triples)
+        assert np.all(np.abs(sig[b] - ref[b]) <= 2 * K * u * mag[b] + 1e-300), b
+
+
+def test_sparse_full_size_sampled_blocks(oz):
+    """The 40-sector, 2000-triple batch; sigma blocks depend only on their own
+    triples, so the oracle recomputes a few blocks alone."""
+    ozaki, ctx, torch = oz
+    prob = wl.heff_sparse()
+    plan, dpsi, keep = sparse_plan(ozaki, ctx, torch, prob, 6)
+    sig = wl.unflatten_sparse(prob, plan.apply(dpsi).cpu().numpy())
+    counts = {}
+    for t in prob.triples:
+        counts[(t[1], t[4])] = counts.get((t[1], t[4]), 0) + 1
+    pick = sorted(counts, key=lambda b: counts[b])[:3]
+    for b in pick:
+        sub = wl.HeffSparse(dims=prob.dims, psi_blocks=[b], psi=prob.psi, L=prob.L, R=prob.R,
+                            triples=[t for t in prob.triples if (t[1], t[4]) == b])
+        ref = oracle.heff_sparse(sub, S=6)
+        assert_bitexact(sig[b], ref[b], "cfg4 block %s" % (b,))
+    # sigma blocks no triple reaches are zero
+    for b in prob.psi_blocks:
+        if b not in counts:
+            assert np.all(sig[b] == 0)
+
+
+def test_plan_argument_errors(oz):
+    ozaki, ctx, torch = oz
+    L, R, psi = wl.heff_dense(D=8, kop=2, phys=1, seed=0)
+    layout, Lf, Rf, pf, triples = wl.flatten_dense(L, R, psi)
+    dL, dR = dev(torch, Lf), dev(torch, Rf)
+    with pytest.raises(ozaki.OzakiError):
+        ozaki.HeffPlan(ctx, layout, dL, dR, [(5, 0, 0, 0, 0, 1.0)], slices=6)   # no operator 5
+    with pytest.raises(ozaki.OzakiError):
+        ozaki.HeffPlan(ctx, layout, dL, dR, triples, slices=9)
+    bad = dict(layout, psi_offset=[0, 10], psi_lr=[0, 0, 0, 0])
+    with pytest.raises(ozaki.OzakiError):
+        ozaki.HeffPlan(ctx, bad, dL, dR, triples, slices=6)
