@@ -115,6 +115,93 @@ def gemm_section(args, ozaki, ctx, torch, oracle):
             "rows_for_error": len(rows)}, (A, B)
 
 
+def heff_flat_plan(ozaki, ctx, torch, layout, Lf, Rf, triples, S, G=0, diag=None):
+    dL = torch.from_numpy(Lf).cuda()
+    dR = torch.from_numpy(Rf).cuda()
+    dd = torch.from_numpy(diag).cuda() if diag is not None else None
+    t0 = time.perf_counter()
+    plan = ozaki.HeffPlan(ctx, layout, dL, dR, triples, diag=dd, slices=S, ndiag=G)
+    torch.cuda.synchronize()
+    return plan, time.perf_counter() - t0, (dL, dR, dd)
+
+
+def heff_section(args, ozaki, ctx, torch, name, layout, Lf, Rf, pf, triples, slices_list):
+    """Warm applies/s (operator slices cached) and error against the FP64 plan."""
+    dpsi = torch.from_numpy(pf).cuda()
+    out = {"workload": name, "n": int(pf.size)}
+    plan, tplan, keep = heff_flat_plan(ozaki, ctx, torch, layout, Lf, Rf, triples, 0)
+    sig64 = plan.apply(dpsi)
+    ctx.set_timing(True)
+    ctx.phase_times()
+    t = time_calls(lambda: plan.apply(dpsi, sig64), args.heff_steps, 1, torch)
+    ph = ctx.phase_times()
+    out["flops_per_apply"] = plan.flops
+    out["fp64"] = {"ms": t * 1e3, "applies_per_s": 1.0 / t, "tflops": plan.flops / t / 1e12,
+                   "plan_s": tplan}
+    log("[bench] %s fp64: %.3f ms/apply  %.2f TFLOP/s" % (name, t * 1e3, plan.flops / t / 1e12))
+    nrm = torch.linalg.vector_norm(sig64).item()
+    plan.close()
+    del keep
+    res = []
+    for (S, G) in slices_list:
+        plan, tplan, keep = heff_flat_plan(ozaki, ctx, torch, layout, Lf, Rf, triples, S, G)
+        sig = plan.apply(dpsi)
+        err = torch.linalg.vector_norm(sig - sig64).item() / nrm
+        ctx.phase_times()
+        t = time_calls(lambda: plan.apply(dpsi, sig), args.heff_steps, 1, torch)
+        ph = ctx.phase_times()
+        phs = {}
+        for (nm, ms) in ph:
+            phs.setdefault(nm, []).append(ms)
+        phs = {k: float(np.sum(v)) / args.heff_steps for k, v in phs.items()}
+        P = ozaki.pair_count(S, G)
+        r = {"slices": S, "ndiag": G, "pairs": P, "ms": t * 1e3, "applies_per_s": 1.0 / t,
+             "tflops": plan.flops / t / 1e12, "rel_frobenius_vs_fp64": err, "plan_s": tplan,
+             "cold_ms": (t + tplan) * 1e3, "phase_ms": phs,
+             "int8_frac_pair_phases": (P * plan.flops / ((phs.get("heff_L", 0) + phs.get("heff_R", 0)) * 1e-3)
+                                       / 1e12 / INT8_PEAK_TOPS) if phs else None}
+        res.append(r)
+        log("[bench] %s S=%d G=%d: %.3f ms/apply  %.2f TFLOP/s  err vs fp64 %.2e  phases %s"
+            % (name, S, G, t * 1e3, r["tflops"], err, {k: round(v, 3) for k, v in phs.items()}))
+        plan.close()
+        del keep
+    ctx.set_timing(False)
+    out["emulated"] = res
+    return out
+
+
+def davidson_section(args, ozaki, ctx, torch):
+    from paper_2510_04795_amd import workloads as wl
+    D = args.dav_d
+    log("[bench] Davidson problem D=%d (n=%d), Kop=32" % (D, D * D))
+    prob = wl.davidson_problem(D=D, kop=32)
+    layout, Lf, Rf, _, triples = wl.flatten_dense(prob.L, prob.R, prob.x0[:, None, :])
+    hd = torch.from_numpy(prob.hdiag.ravel().copy()).cuda()
+    x0 = torch.from_numpy(prob.x0.ravel().copy()).cuda()
+    out = {"D": D, "n": D * D, "kop": 32, "tol": 1e-8, "runs": []}
+    e64 = None
+    for S in [0, 4, 5, 6, 7, 8]:
+        plan, tplan, keep = heff_flat_plan(ozaki, ctx, torch, layout, Lf, Rf, triples, S, 0,
+                                           diag=prob.delta.ravel().copy())
+        dav = ozaki.Davidson(ctx, plan, hd, x0, m_max=32, tol=1e-8, max_iter=300)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        theta, status, its, res = dav.run()
+        t = time.perf_counter() - t0
+        if S == 0:
+            e64 = theta
+        r = {"slices": S, "energy": theta, "status": status, "iterations": its, "residual": res,
+             "ms_per_iteration": t / max(its, 1) * 1e3, "matvec_flops": plan.flops,
+             "energy_error_vs_fp64": None if S == 0 else abs(theta - e64)}
+        out["runs"].append(r)
+        log("[bench] Davidson S=%d: E=%.12f  %s in %d it  (%.2f ms/it)  |dE|=%s"
+            % (S, theta, status, its, r["ms_per_iteration"], r["energy_error_vs_fp64"]))
+        dav.close()
+        plan.close()
+        del keep
+    return out
+
+
 def cpu_baseline(oracle, A, B, S, G, rows_count):
     rows = sampled_rows(A.shape[0], rows_count, seed=2)
     n = A.shape[0]
@@ -136,6 +223,12 @@ def main():
     ap.add_argument("--err-rows", type=int, default=16)
     ap.add_argument("--cpu-rows", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--sections", default="gemm,dense,sparse,davidson",
+                    help="comma list of gemm, dense, sparse, davidson")
+    ap.add_argument("--heff-d", type=int, default=2048)
+    ap.add_argument("--heff-kop", type=int, default=64)
+    ap.add_argument("--heff-steps", type=int, default=3)
+    ap.add_argument("--dav-d", type=int, default=1024)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -146,12 +239,34 @@ def main():
     from paper_2510_04795_amd import ozaki
     torch.cuda.init()
     ctx = ozaki.Context(0)
+    sections = set(args.sections.split(","))
+    from paper_2510_04795_amd import workloads as wl
     gemm, (A, B) = gemm_section(args, ozaki, ctx, torch, oracle)
     chosen = gemm["chosen"]
     cpu = None
     if not args.no_cpu:
         log("[bench] CPU oracle sample")
         cpu = cpu_baseline(oracle, A, B, chosen["slices"], chosen["ndiag"], args.cpu_rows)
+    del A, B
+    extra = {}
+    if "dense" in sections:
+        log("[bench] generating dense two-site problem D=%d Kop=%d phys=16" % (args.heff_d, args.heff_kop))
+        L, R, psi = wl.heff_dense(D=args.heff_d, kop=args.heff_kop, phys=16)
+        layout, Lf, Rf, pf, triples = wl.flatten_dense(L, R, psi)
+        del L, R, psi
+        extra["heff_dense"] = heff_section(
+            args, ozaki, ctx, torch, "dense D=%d Kop=%d phys=16" % (args.heff_d, args.heff_kop),
+            layout, Lf, Rf, pf, triples, [(6, 6), (7, 7), (8, 8)])
+        del Lf, Rf, pf
+    if "sparse" in sections:
+        log("[bench] generating block-sparse batch (40 sectors, 2000 triples)")
+        prob = wl.heff_sparse()
+        layout, Lf, Rf, pf, triples = wl.flatten_sparse(prob)
+        extra["heff_sparse"] = heff_section(
+            args, ozaki, ctx, torch, "block-sparse 40 sectors, %d triples" % len(triples),
+            layout, Lf, Rf, pf, triples, [(6, 6), (7, 7), (8, 8)])
+    if "davidson" in sections:
+        extra["davidson"] = davidson_section(args, ozaki, ctx, torch)
     line = {
         "metric": "Emulated-FP64 TFLOP/s vs native FP64 MFMA at equal error; H_eff.psi applies/s",
         "value": chosen["tflops"],
@@ -179,6 +294,7 @@ def main():
         "at_1e-12": gemm["at_1e-12"],
         "cpu_baseline": cpu,
     }
+    line.update(extra)
     print(json.dumps(line), flush=True)
 
 

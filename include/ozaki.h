@@ -133,6 +133,33 @@ int ozaki_dgemm(ozaki_ctx ctx, char transa, char transb, int64_t M, int64_t N, i
                 double beta, double *C, int64_t ldc, int slices, int ndiag,
                 void *workspace, size_t workspace_bytes, void *stream);
 
+/* ---- tile variants and autotuning ------------------------------------ */
+/* The int8 pair GEMM is built in several tile variants per (S, G) (waves of
+ * MB x NB blocks of 32 x 32 outputs).  Every variant gives bit-identical
+ * results; only speed differs.  ozaki_pair_variants writes the tile shape of
+ * variant v to tile_m[v] x tile_n[v] (0 x 0 when v is not built for this G)
+ * and returns the number of variant slots. */
+int ozaki_pair_variants(int slices, int ndiag, int32_t *tile_m, int32_t *tile_n, int32_t max_variants);
+/* Use variant `variant` for (slices, ndiag) in this context (-1: library
+ * default; heff plans then autotune if enabled).  OZ_ERR_ARG for a variant
+ * that is not built. */
+int ozaki_ctx_set_variant(ozaki_ctx ctx, int slices, int ndiag, int variant);
+/* Variant ozaki_dgemm currently uses for (slices, ndiag). */
+int ozaki_ctx_get_variant(ozaki_ctx ctx, int slices, int ndiag);
+/* Whether heff_plan_create times the variants of its two grouped phases and
+ * keeps the fastest (default on; a variant fixed with ozaki_ctx_set_variant
+ * takes precedence). */
+int ozaki_ctx_set_autotune(ozaki_ctx ctx, int enable);
+/* Time every built variant of this GEMM (alpha = 1, beta = 0 into C, one
+ * warm-up and three timed calls each) and fix the fastest for (slices,
+ * ndiag) in the context.  ms_out (host, nullable, one slot per variant) gets
+ * the mean milliseconds or -1.  Returns the chosen variant (>= 0) or an
+ * error; synchronises the stream. */
+int ozaki_dgemm_tune(ozaki_ctx ctx, char transa, char transb, int64_t M, int64_t N, int64_t K,
+                     const double *A, int64_t lda, const double *B, int64_t ldb, double *C,
+                     int64_t ldc, int slices, int ndiag, void *workspace, size_t workspace_bytes,
+                     void *stream, double *ms_out);
+
 /* ---- test and debug surface (steps 1-3 on their own) ---------------- */
 /* Steps 1-2: shared exponents and slices of X (rows x cols, row-major, ld).
  *  by_columns = 0: one exponent per row, digits[S][rows][cols];
@@ -209,6 +236,9 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *layout,
 /* sigma = H_eff psi (sigma overwritten; psi and sigma must not overlap).
  * One grouped launch per phase; enqueue only. */
 int heff_apply(heff_plan plan, const double *psi, double *sigma, void *stream);
+/* Tile variants the plan's two grouped phases use (emulated plans; -1 for
+ * native FP64 plans). */
+int heff_plan_variants(heff_plan plan, int32_t *first, int32_t *second);
 /* Total elements of psi for the plan's layout. */
 int64_t heff_vector_length(heff_plan plan);
 /* FP64-equivalent flops of one heff_apply (2 m n k summed over all GEMMs). */

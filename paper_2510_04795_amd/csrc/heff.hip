@@ -47,6 +47,7 @@ struct heff_plan_s {
     int32_t *T_e = nullptr;
     int8_t *T_p = nullptr;
     PairArgs argsL{}, argsR{};
+    int varL = -1, varR = -1;   // tile variants of the two grouped phases
     // FP64 path
     Dgemm64Args d64L{}, d64R{};
 };
@@ -370,11 +371,11 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
     P->T_e = static_cast<int32_t *>(te_);
     P->T_p = static_cast<int8_t *>(tp);
 
-    const PairShape sh = pair_shape(S, G);
-    // first product tiles: one term each, written to T_u
-    std::vector<TermDesc> termsL;
-    std::vector<OutDesc> outsL;
-    std::vector<TileWork> wl;
+    // terms and outputs (shared by every tile variant)
+    std::vector<TermDesc> termsL, termsR;
+    std::vector<OutDesc> outsL, outsR;
+    std::vector<int> sigma_tb(L->n_psi_blocks), sigma_te(L->n_psi_blocks);
+    std::vector<int64_t> sigma_cost(L->n_psi_blocks, 0);
     for (size_t u = 0; u < us.size(); ++u) {
         const U &x = us[u];
         const int64_t M = ld[x.lo], N = p * rd[x.ri], K = ld[x.li];
@@ -389,20 +390,11 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
         tm.alpha = 1.0;
         termsL.push_back(tm);
         outsL.push_back(OutDesc{P->T + x.t_off, N, static_cast<int32_t>(M), static_cast<int32_t>(N)});
-        for (int64_t m0 = 0; m0 < M; m0 += sh.bm)
-            for (int64_t n0 = 0; n0 < N; n0 += sh.bn)
-                wl.push_back({TileDesc{static_cast<int32_t>(u), static_cast<int32_t>(u + 1), static_cast<int32_t>(m0),
-                                       static_cast<int32_t>(n0), static_cast<int32_t>(u), 0}, tm.kblocks});
     }
-    // second product tiles: each sigma tile sums its triples in list order
-    std::vector<TermDesc> termsR;
-    std::vector<OutDesc> outsR;
-    std::vector<TileWork> wr;
     for (int b = 0; b < L->n_psi_blocks; ++b) {
         const int lo = L->psi_lr[2 * b], ro = L->psi_lr[2 * b + 1];
         const int64_t M = ld[lo] * p, N = rd[ro];
-        const int tb = static_cast<int>(termsR.size());
-        int64_t cost = 0;
+        sigma_tb[b] = static_cast<int>(termsR.size());
         for (int t : by_sigma[b]) {
             const int u = tri_u[t];
             const U &x = us[u];
@@ -416,29 +408,114 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
             tm.kblocks = static_cast<int32_t>(ceil_div(rd[x.ri], kKB));
             tm.alpha = triples[t].alpha;
             termsR.push_back(tm);
-            cost += tm.kblocks;
+            sigma_cost[b] += tm.kblocks;
         }
-        const int te = static_cast<int>(termsR.size());
+        sigma_te[b] = static_cast<int>(termsR.size());
         outsR.push_back(OutDesc{reinterpret_cast<double *>(static_cast<intptr_t>(L->psi_offset[b])), N,
                                 static_cast<int32_t>(M), static_cast<int32_t>(N)});
-        for (int64_t m0 = 0; m0 < M; m0 += sh.bm)
-            for (int64_t n0 = 0; n0 < N; n0 += sh.bn)
-                wr.push_back({TileDesc{tb, te, static_cast<int32_t>(m0), static_cast<int32_t>(n0), b, 0}, cost});
     }
-    std::vector<TileDesc> tl, tr;
-    sort_tiles(wl, &tl);
-    sort_tiles(wr, &tr);
-    TileDesc *dt;
-    TermDesc *dm;
-    OutDesc *dout;
-    if ((rc = upload(P, tl, &dt)) || (rc = upload(P, termsL, &dm)) || (rc = upload(P, outsL, &dout))) { free_plan(P); return rc; }
-    P->argsL.tiles = dt; P->argsL.terms = dm; P->argsL.outs = dout;
-    P->argsL.ntiles = static_cast<int32_t>(tl.size());
-    P->argsL.mode = kModeGemm;
-    if ((rc = upload(P, tr, &dt)) || (rc = upload(P, termsR, &dm)) || (rc = upload(P, outsR, &dout))) { free_plan(P); return rc; }
-    P->argsR.tiles = dt; P->argsR.terms = dm; P->argsR.outs = dout;
-    P->argsR.ntiles = static_cast<int32_t>(tr.size());
-    P->argsR.mode = kModeAccum;
+    // tile lists per variant (longest first)
+    auto tiles_for = [&](int v, std::vector<TileDesc> *tl, std::vector<TileDesc> *tr,
+                         std::vector<int64_t> *cl, std::vector<int64_t> *cr) {
+        const PairShape sh = pair_shape(S, G, v);
+        std::vector<TileWork> wl, wr;
+        for (size_t u = 0; u < us.size(); ++u) {
+            const OutDesc &o = outsL[u];
+            for (int64_t m0 = 0; m0 < o.M; m0 += sh.bm)
+                for (int64_t n0 = 0; n0 < o.N; n0 += sh.bn)
+                    wl.push_back({TileDesc{static_cast<int32_t>(u), static_cast<int32_t>(u + 1), static_cast<int32_t>(m0),
+                                           static_cast<int32_t>(n0), static_cast<int32_t>(u), 0},
+                                  static_cast<int64_t>(termsL[u].kblocks) * sh.bm * sh.bn});
+        }
+        for (int b = 0; b < L->n_psi_blocks; ++b) {
+            const OutDesc &o = outsR[b];
+            for (int64_t m0 = 0; m0 < o.M; m0 += sh.bm)
+                for (int64_t n0 = 0; n0 < o.N; n0 += sh.bn)
+                    wr.push_back({TileDesc{sigma_tb[b], sigma_te[b], static_cast<int32_t>(m0), static_cast<int32_t>(n0), b, 0},
+                                  (sigma_cost[b] + 1) * sh.bm * sh.bn});
+        }
+        sort_tiles(wl, tl);
+        sort_tiles(wr, tr);
+        cl->clear();
+        cr->clear();
+        std::stable_sort(wl.begin(), wl.end(), [](const TileWork &a, const TileWork &b) { return a.cost > b.cost; });
+        std::stable_sort(wr.begin(), wr.end(), [](const TileWork &a, const TileWork &b) { return a.cost > b.cost; });
+        for (auto &w : wl) cl->push_back(w.cost);
+        for (auto &w : wr) cr->push_back(w.cost);
+    };
+    TermDesc *dmL, *dmR;
+    OutDesc *doL, *doR;
+    if ((rc = upload(P, termsL, &dmL)) || (rc = upload(P, outsL, &doL)) || (rc = upload(P, termsR, &dmR)) ||
+        (rc = upload(P, outsR, &doR))) { free_plan(P); return rc; }
+    P->argsL.terms = dmL; P->argsL.outs = doL; P->argsL.mode = kModeGemm;
+    P->argsR.terms = dmR; P->argsR.outs = doR; P->argsR.mode = kModeAccum;
+
+    const int fixed = ctx->variant[S][G];
+    std::vector<int> cands;
+    for (int v = 0; v < pair_num_variants(); ++v)
+        if (pair_variant_ok(G, v) && (fixed < 0 ? (ctx->autotune || v == pair_default_variant(G)) : v == fixed))
+            cands.push_back(v);
+    // Autotuning: time each candidate on a prefix of its (longest-first) tile
+    // list, scaled by the prefix's share of the total cost; inputs are zeroed
+    // scratch (the timing does not depend on the values).
+    double bestL = -1, bestR = -1;
+    void *tmp_sigma = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    const bool tuning = cands.size() > 1;
+    if (tuning) {
+        if ((e = hipMalloc(&tmp_sigma, sizeof(double) * std::max<int64_t>(n, 1))) != hipSuccess) { free_plan(P); return hip_fail(e, "heff_plan_create: tuning buffer"); }
+        hipMemsetAsync(P->psi_p, 0, std::max<int64_t>(Ps.p_total, 256), s);
+        hipMemsetAsync(P->psi_e, 0, sizeof(int32_t) * std::max<int64_t>(Ps.e_total, 1), s);
+        hipMemsetAsync(P->T_p, 0, std::max<int64_t>(Ts.p_total, 256), s);
+        hipMemsetAsync(P->T_e, 0, sizeof(int32_t) * std::max<int64_t>(Ts.e_total, 1), s);
+        hipEventCreate(&ev0);
+        hipEventCreate(&ev1);
+    }
+    for (int v : cands) {
+        std::vector<TileDesc> tl, tr;
+        std::vector<int64_t> cl, cr;
+        tiles_for(v, &tl, &tr, &cl, &cr);
+        TileDesc *dtl, *dtr;
+        if ((rc = upload(P, tl, &dtl)) || (rc = upload(P, tr, &dtr))) { if (tmp_sigma) hipFree(tmp_sigma); free_plan(P); return rc; }
+        if (!tuning) {
+            P->argsL.tiles = dtl; P->argsL.ntiles = static_cast<int32_t>(tl.size()); P->varL = v;
+            P->argsR.tiles = dtr; P->argsR.ntiles = static_cast<int32_t>(tr.size()); P->varR = v;
+            break;
+        }
+        for (int ph = 0; ph < 2; ++ph) {
+            const std::vector<int64_t> &cost = ph == 0 ? cl : cr;
+            int64_t total = 0;
+            for (auto c : cost) total += c;
+            const int prefix = static_cast<int>(std::min<size_t>(cost.size(), static_cast<size_t>(8 * ctx->num_cu)));
+            int64_t part = 0;
+            for (int i = 0; i < prefix; ++i) part += cost[i];
+            PairArgs a = ph == 0 ? P->argsL : P->argsR;
+            a.tiles = ph == 0 ? dtl : dtr;
+            a.ntiles = prefix;
+            if (ph == 1) a.out_base = static_cast<double *>(tmp_sigma);
+            float ms = 0.f;
+            for (int rep = 0; rep < 2; ++rep) {
+                hipEventRecord(ev0, s);
+                if ((e = launch_pair_grouped(S, G, v, a, s)) != hipSuccess) { hipFree(tmp_sigma); free_plan(P); return hip_fail(e, "heff_plan_create: tuning launch"); }
+                hipEventRecord(ev1, s);
+                hipEventSynchronize(ev1);
+                hipEventElapsedTime(&ms, ev0, ev1);
+            }
+            const double est = part > 0 ? ms * static_cast<double>(total) / static_cast<double>(part) : 0.0;
+            double &best = ph == 0 ? bestL : bestR;
+            if (best < 0 || est < best) {
+                best = est;
+                if (ph == 0) { P->argsL.tiles = dtl; P->argsL.ntiles = static_cast<int32_t>(tl.size()); P->varL = v; }
+                else { P->argsR.tiles = dtr; P->argsR.ntiles = static_cast<int32_t>(tr.size()); P->varR = v; }
+            }
+        }
+    }
+    if (tuning) {
+        hipEventDestroy(ev0);
+        hipEventDestroy(ev1);
+        hipStreamSynchronize(s);
+        hipFree(tmp_sigma);
+    }
     if ((e = hipStreamSynchronize(s)) != hipSuccess) { free_plan(P); return hip_fail(e, "heff_plan_create: sync"); }
     *out = P;
     return OZ_OK;
@@ -471,7 +548,7 @@ int heff_apply(heff_plan P, const double *psi, double *sigma, void *stream) {
             return hip_fail(e, "heff_apply: slicing psi");
         hipEvent_t t1 = mark(ctx, s);
         phase(ctx, OZ_PHASE_HEFF_AUX, t0, t1);
-        if ((e = launch_pair_grouped(P->S, P->G, P->argsL, 0, s)) != hipSuccess) return hip_fail(e, "heff_apply: first product");
+        if ((e = launch_pair_grouped(P->S, P->G, P->varL, P->argsL, s)) != hipSuccess) return hip_fail(e, "heff_apply: first product");
         hipEvent_t t2 = mark(ctx, s);
         phase(ctx, OZ_PHASE_HEFF_L, t1, t2);
         if ((e = launch_exponents_grouped(P->T_blocks, P->T_etasks, P->n_T_etasks, P->T, P->T_e, ctx->d_flags, s)) != hipSuccess ||
@@ -481,7 +558,7 @@ int heff_apply(heff_plan P, const double *psi, double *sigma, void *stream) {
         phase(ctx, OZ_PHASE_HEFF_AUX, t2, t3);
         PairArgs b = P->argsR;
         b.out_base = sigma;
-        if ((e = launch_pair_grouped(P->S, P->G, b, 0, s)) != hipSuccess) return hip_fail(e, "heff_apply: second product");
+        if ((e = launch_pair_grouped(P->S, P->G, P->varR, b, s)) != hipSuccess) return hip_fail(e, "heff_apply: second product");
         hipEvent_t t4 = mark(ctx, s);
         phase(ctx, OZ_PHASE_HEFF_R, t3, t4);
     }
@@ -492,6 +569,13 @@ int heff_apply(heff_plan P, const double *psi, double *sigma, void *stream) {
 }
 
 int64_t heff_vector_length(heff_plan P) { return P ? P->n : -1; }
+
+int heff_plan_variants(heff_plan P, int32_t *first, int32_t *second) {
+    if (!P) return fail(OZ_ERR_ARG, "heff_plan_variants: plan is NULL");
+    if (first) *first = P->varL;
+    if (second) *second = P->varR;
+    return OZ_OK;
+}
 
 double heff_flops(heff_plan P) { return P ? P->flops : 0.0; }
 

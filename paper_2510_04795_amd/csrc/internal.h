@@ -153,12 +153,15 @@ hipError_t launch_pack(int S, const int8_t *canon, int64_t R, int64_t K, int8_t 
 hipError_t launch_unpack(int S, const int8_t *packed, int64_t Rp, int64_t R, int64_t K,
                          int8_t *canon, hipStream_t s);
 
-// Tile shape of the int8 pair GEMM for (S, G).
+// Tile variants of the int8 pair GEMM.  v < 0 selects the default variant.
 struct PairShape { int bm, bn; };
-PairShape pair_shape(int S, int G);
 bool pair_supported(int S, int G);
-hipError_t launch_pair_single(int S, int G, const PairArgs &a, int tiles_m, hipStream_t s);
-hipError_t launch_pair_grouped(int S, int G, const PairArgs &a, int grid, hipStream_t s);
+int pair_num_variants();
+bool pair_variant_ok(int G, int v);
+int pair_default_variant(int G);
+PairShape pair_shape(int S, int G, int v);
+hipError_t launch_pair_single(int S, int G, int v, const PairArgs &a, int tiles_m, hipStream_t s);
+hipError_t launch_pair_grouped(int S, int G, int v, const PairArgs &a, hipStream_t s);
 
 // FP64 MFMA GEMM.
 PairShape dgemm_shape();

@@ -1,4 +1,4 @@
-// Dispatch of the pair-GEMM kernels over the slice count.
+// Dispatch of the pair-GEMM kernels over the slice count and tile variant.
 #include "pairgemm_impl.h"
 
 namespace oz {
@@ -8,43 +8,42 @@ bool pair_supported(int S, int G) {
     return G == S || G == S + 1 || G == 2 * S - 1;
 }
 
-PairShape pair_shape(int S, int G) {
-    PairShape sh{0, 0};
-    switch (S) {
-        case 2: pair_shape_s2(G, &sh); break;
-        case 3: pair_shape_s3(G, &sh); break;
-        case 4: pair_shape_s4(G, &sh); break;
-        case 5: pair_shape_s5(G, &sh); break;
-        case 6: pair_shape_s6(G, &sh); break;
-        case 7: pair_shape_s7(G, &sh); break;
-        case 8: pair_shape_s8(G, &sh); break;
-        default: break;
-    }
-    return sh;
+int pair_num_variants() { return pair::kNumVariants; }
+
+bool pair_variant_ok(int G, int v) { return v >= 0 && v < pair::kNumVariants && pair::variant_fits(G, v); }
+
+int pair_default_variant(int G) { return pair::default_variant(G); }
+
+PairShape pair_shape(int S, int G, int v) {
+    (void)S;
+    if (v < 0) v = pair::default_variant(G);
+    return PairShape{2 * pair::variant_mb(v) * 32, 2 * pair::variant_nb(v) * 32};
 }
 
-hipError_t launch_pair_single(int S, int G, const PairArgs &a, int tiles_m, hipStream_t s) {
+hipError_t launch_pair_single(int S, int G, int v, const PairArgs &a, int tiles_m, hipStream_t s) {
+    if (v < 0) v = pair::default_variant(G);
     switch (S) {
-        case 2: return pair_single_s2(G, a, tiles_m, s);
-        case 3: return pair_single_s3(G, a, tiles_m, s);
-        case 4: return pair_single_s4(G, a, tiles_m, s);
-        case 5: return pair_single_s5(G, a, tiles_m, s);
-        case 6: return pair_single_s6(G, a, tiles_m, s);
-        case 7: return pair_single_s7(G, a, tiles_m, s);
-        case 8: return pair_single_s8(G, a, tiles_m, s);
+        case 2: return pair_single_s2(G, v, a, tiles_m, s);
+        case 3: return pair_single_s3(G, v, a, tiles_m, s);
+        case 4: return pair_single_s4(G, v, a, tiles_m, s);
+        case 5: return pair_single_s5(G, v, a, tiles_m, s);
+        case 6: return pair_single_s6(G, v, a, tiles_m, s);
+        case 7: return pair_single_s7(G, v, a, tiles_m, s);
+        case 8: return pair_single_s8(G, v, a, tiles_m, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_pair_grouped(int S, int G, const PairArgs &a, int, hipStream_t s) {
+hipError_t launch_pair_grouped(int S, int G, int v, const PairArgs &a, hipStream_t s) {
+    if (v < 0) v = pair::default_variant(G);
     switch (S) {
-        case 2: return pair_grouped_s2(G, a, s);
-        case 3: return pair_grouped_s3(G, a, s);
-        case 4: return pair_grouped_s4(G, a, s);
-        case 5: return pair_grouped_s5(G, a, s);
-        case 6: return pair_grouped_s6(G, a, s);
-        case 7: return pair_grouped_s7(G, a, s);
-        case 8: return pair_grouped_s8(G, a, s);
+        case 2: return pair_grouped_s2(G, v, a, s);
+        case 3: return pair_grouped_s3(G, v, a, s);
+        case 4: return pair_grouped_s4(G, v, a, s);
+        case 5: return pair_grouped_s5(G, v, a, s);
+        case 6: return pair_grouped_s6(G, v, a, s);
+        case 7: return pair_grouped_s7(G, v, a, s);
+        case 8: return pair_grouped_s8(G, v, a, s);
         default: return hipErrorInvalidValue;
     }
 }

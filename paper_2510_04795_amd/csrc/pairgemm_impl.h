@@ -41,36 +41,55 @@ struct Cfg {
     static constexpr int SEGS = 2 * S * (BM + BN) / 64; // all wave loads per stage
 };
 
-// Issue the direct-to-LDS loads of one packed K block into an LDS stage.
+// Direct-to-LDS loads of one packed K block: the stage holds 2S runs of BM
+// A rows then 2S runs of BN B rows; every wave issues 64-row segments (one
+// 16-byte chunk per lane).  The per-wave segment list is fixed for a term, so
+// it is computed once: a lane address at block 0, the per-block stride and
+// the LDS offset of each segment the wave owns.
 template <int S, int G, int MB, int NB>
-__device__ __forceinline__ void load_stage(uint4 *stage, const uint4 *gA, const uint4 *gB,
-                                           int64_t a_rows_p, int64_t b_rows_p, int m0, int n0,
-                                           int kb, int wave, int lane) {
+struct LoadPlan {
     using C = Cfg<S, G, MB, NB>;
+    static constexpr int NL = (C::SEGS + 3) / 4;
+    const uint4 *src[NL];
+    int64_t stride[NL];
+    int lds_off[NL];
+    bool valid[NL];
+
+    __device__ __forceinline__ void init(const uint4 *gA, const uint4 *gB, int64_t a_rows_p,
+                                         int64_t b_rows_p, int m0, int n0, int wave, int lane) {
 #pragma unroll
-    for (int q = wave; q < C::SEGS; q += 4) {
-        const uint4 *src;
-        int lds_off;
-        if (q < C::A_SEG) {
-            const int run = q / (C::BM / 64);
-            const int seg = q - run * (C::BM / 64);
-            int64_t row = m0 + seg * 64 + lane;
-            row = row < a_rows_p ? row : a_rows_p - 1;
-            src = gA + (static_cast<int64_t>(kb) * 2 * S + run) * a_rows_p + row;
-            lds_off = run * C::BM + seg * 64;
-        } else {
-            const int qb = q - C::A_SEG;
-            const int run = qb / (C::BN / 64);
-            const int seg = qb - run * (C::BN / 64);
-            int64_t row = n0 + seg * 64 + lane;
-            row = row < b_rows_p ? row : b_rows_p - 1;
-            src = gB + (static_cast<int64_t>(kb) * 2 * S + run) * b_rows_p + row;
-            lds_off = 2 * S * C::BM + run * C::BN + seg * 64;
+        for (int i = 0; i < NL; ++i) {
+            const int q = wave + 4 * i;
+            valid[i] = q < C::SEGS;
+            if (q < C::A_SEG) {
+                const int run = q / (C::BM / 64);
+                const int seg = q - run * (C::BM / 64);
+                int64_t row = m0 + seg * 64 + lane;
+                row = row < a_rows_p ? row : a_rows_p - 1;
+                src[i] = gA + run * a_rows_p + row;
+                stride[i] = 2 * S * a_rows_p;
+                lds_off[i] = run * C::BM + seg * 64;
+            } else {
+                const int qb = (q < C::SEGS ? q : C::A_SEG) - C::A_SEG;
+                const int run = qb / (C::BN / 64);
+                const int seg = qb - run * (C::BN / 64);
+                int64_t row = n0 + seg * 64 + lane;
+                row = row < b_rows_p ? row : b_rows_p - 1;
+                src[i] = gB + run * b_rows_p + row;
+                stride[i] = 2 * S * b_rows_p;
+                lds_off[i] = 2 * S * C::BM + run * C::BN + seg * 64;
+            }
         }
-        __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(src),
-                                         (lds_void *)(stage + lds_off), 16, 0, 0);
     }
-}
+
+    __device__ __forceinline__ void issue(uint4 *stage, int kb) const {
+#pragma unroll
+        for (int i = 0; i < NL; ++i)
+            if (valid[i])
+                __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(src[i] + kb * stride[i]),
+                                                 (lds_void *)(stage + lds_off[i]), 16, 0, 0);
+    }
+};
 
 // All kept pair products of one LDS stage (one 32-wide K block).  The B
 // fragments of every kept slice stay in registers; A fragments are streamed
@@ -137,19 +156,27 @@ __device__ __forceinline__ void pair_mainloop(v16i (&acc)[G][MB][NB], uint4 *lds
             for (int nb = 0; nb < NB; ++nb) acc[g][mb][nb] = v16i{};
     if (nkb == 0) return;
 
-    load_stage<S, G, MB, NB>(lds0, gA, gB, T.a_rows_p, T.b_rows_p, m0, n0, 0, wave, lane);
-    for (int kb = 0; kb < nkb; kb += 2) {
+    LoadPlan<S, G, MB, NB> lp;
+    lp.init(gA, gB, T.a_rows_p, T.b_rows_p, m0, n0, wave, lane);
+    lp.issue(lds0, 0);
+    // Blocks are taken two at a time (stage 0, stage 1) so each LDS stage is
+    // its own object; the loop has a single exit and an odd last block is
+    // peeled, which keeps the accumulators in place across iterations.
+    int kb = 0;
+    for (; kb + 2 <= nkb; kb += 2) {
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        if (kb + 1 < nkb)
-            load_stage<S, G, MB, NB>(lds1, gA, gB, T.a_rows_p, T.b_rows_p, m0, n0, kb + 1, wave, lane);
+        lp.issue(lds1, kb + 1);
         multiply_stage<S, G, MB, NB>(acc, lds0, wm, wn, half, l32);
-        if (kb + 1 >= nkb) break;
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        if (kb + 2 < nkb)
-            load_stage<S, G, MB, NB>(lds0, gA, gB, T.a_rows_p, T.b_rows_p, m0, n0, kb + 2, wave, lane);
+        if (kb + 2 < nkb) lp.issue(lds0, kb + 2);
         multiply_stage<S, G, MB, NB>(acc, lds1, wm, wn, half, l32);
+    }
+    if (kb < nkb) {
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        multiply_stage<S, G, MB, NB>(acc, lds0, wm, wn, half, l32);
     }
 }
 
@@ -303,61 +330,93 @@ __global__ __launch_bounds__(256) void k_pair_grouped(PairArgs a) {
 }
 
 // Per-(S, G) tile shape: as wide as the accumulators allow.
-template <int S, int G>
-struct Shape {
-    static constexpr int MB = (G <= 8) ? 2 : 1;
-    static constexpr int NB = (G <= 4) ? 2 : 1;
-};
+// Wave-tile variants (MB x NB blocks of 32 x 32 per wave).  The 1 x 1
+// variant is always built; a wider one only when its G accumulator sets fit
+// in 192 registers (16 G MB NB), leaving the rest of the register file to
+// operands and addresses.
+constexpr int kNumVariants = 4;
+__host__ __device__ constexpr int variant_mb(int v) { return v == 1 || v == 3 ? 2 : 1; }
+__host__ __device__ constexpr int variant_nb(int v) { return v == 2 || v == 3 ? 2 : 1; }
+__host__ __device__ constexpr bool variant_fits(int G, int v) {
+    return v == 0 || 16 * G * variant_mb(v) * variant_nb(v) <= 192;
+}
+// default: the widest tile that fits, preferring 2 x 1
+__host__ __device__ constexpr int default_variant(int G) {
+    return variant_fits(G, 3) ? 3 : (variant_fits(G, 1) ? 1 : 0);
+}
 
-template <int S, int G>
-hipError_t run_single(const PairArgs &a, int tiles_m, hipStream_t s) {
-    constexpr int MB = Shape<S, G>::MB, NB = Shape<S, G>::NB;
-    const unsigned grid = static_cast<unsigned>(tiles_m) * static_cast<unsigned>(a.tiles_n);
-    if (grid == 0) return hipSuccess;
-    switch (a.mode) {
-        case kModeGemm:
-            hipLaunchKernelGGL((k_pair_single<S, G, MB, NB, kModeGemm>), dim3(grid), dim3(256), 0, s, a, tiles_m);
-            break;
-        case kModeQ:
-            hipLaunchKernelGGL((k_pair_single<S, G, MB, NB, kModeQ>), dim3(grid), dim3(256), 0, s, a, tiles_m);
-            break;
-        case kModeQ64:
-            hipLaunchKernelGGL((k_pair_single<S, G, MB, NB, kModeQ64>), dim3(grid), dim3(256), 0, s, a, tiles_m);
-            break;
-        default: return hipErrorInvalidValue;
+template <int S, int G, int V>
+hipError_t run_single_v(const PairArgs &a, int tiles_m, hipStream_t s) {
+    constexpr int MB = variant_mb(V), NB = variant_nb(V);
+    if constexpr (!variant_fits(G, V)) {
+        return hipErrorInvalidValue;
+    } else {
+        const unsigned grid = static_cast<unsigned>(tiles_m) * static_cast<unsigned>(a.tiles_n);
+        if (grid == 0) return hipSuccess;
+        switch (a.mode) {
+            case kModeGemm:
+                hipLaunchKernelGGL((k_pair_single<S, G, MB, NB, kModeGemm>), dim3(grid), dim3(256), 0, s, a, tiles_m);
+                break;
+            case kModeQ:
+                hipLaunchKernelGGL((k_pair_single<S, G, MB, NB, kModeQ>), dim3(grid), dim3(256), 0, s, a, tiles_m);
+                break;
+            case kModeQ64:
+                hipLaunchKernelGGL((k_pair_single<S, G, MB, NB, kModeQ64>), dim3(grid), dim3(256), 0, s, a, tiles_m);
+                break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
     }
-    return hipGetLastError();
+}
+
+template <int S, int G, int V>
+hipError_t run_grouped_v(const PairArgs &a, hipStream_t s) {
+    constexpr int MB = variant_mb(V), NB = variant_nb(V);
+    if constexpr (!variant_fits(G, V)) {
+        return hipErrorInvalidValue;
+    } else {
+        if (a.ntiles == 0) return hipSuccess;
+        switch (a.mode) {
+            case kModeGemm:
+                hipLaunchKernelGGL((k_pair_grouped<S, G, MB, NB, kModeGemm>), dim3(a.ntiles), dim3(256), 0, s, a);
+                break;
+            case kModeAccum:
+                hipLaunchKernelGGL((k_pair_grouped<S, G, MB, NB, kModeAccum>), dim3(a.ntiles), dim3(256), 0, s, a);
+                break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
 }
 
 template <int S, int G>
-hipError_t run_grouped(const PairArgs &a, hipStream_t s) {
-    constexpr int MB = Shape<S, G>::MB, NB = Shape<S, G>::NB;
-    if (a.ntiles == 0) return hipSuccess;
-    switch (a.mode) {
-        case kModeGemm:
-            hipLaunchKernelGGL((k_pair_grouped<S, G, MB, NB, kModeGemm>), dim3(a.ntiles), dim3(256), 0, s, a);
-            break;
-        case kModeAccum:
-            hipLaunchKernelGGL((k_pair_grouped<S, G, MB, NB, kModeAccum>), dim3(a.ntiles), dim3(256), 0, s, a);
-            break;
+hipError_t run_single(int v, const PairArgs &a, int tiles_m, hipStream_t s) {
+    switch (v) {
+        case 0: return run_single_v<S, G, 0>(a, tiles_m, s);
+        case 1: return run_single_v<S, G, 1>(a, tiles_m, s);
+        case 2: return run_single_v<S, G, 2>(a, tiles_m, s);
+        case 3: return run_single_v<S, G, 3>(a, tiles_m, s);
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 template <int S, int G>
-PairShape shape_of() {
-    return PairShape{Cfg<S, G, Shape<S, G>::MB, Shape<S, G>::NB>::BM,
-                     Cfg<S, G, Shape<S, G>::MB, Shape<S, G>::NB>::BN};
+hipError_t run_grouped(int v, const PairArgs &a, hipStream_t s) {
+    switch (v) {
+        case 0: return run_grouped_v<S, G, 0>(a, s);
+        case 1: return run_grouped_v<S, G, 1>(a, s);
+        case 2: return run_grouped_v<S, G, 2>(a, s);
+        case 3: return run_grouped_v<S, G, 3>(a, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace pair
 
 // Per-S entry points (pairgemm_s<S>.hip).
-#define OZ_DECLARE_PAIR_S(S_)                                                             \
-    hipError_t pair_single_s##S_(int G, const PairArgs &a, int tiles_m, hipStream_t s);   \
-    hipError_t pair_grouped_s##S_(int G, const PairArgs &a, hipStream_t s);               \
-    bool pair_shape_s##S_(int G, PairShape *out);
+#define OZ_DECLARE_PAIR_S(S_)                                                                   \
+    hipError_t pair_single_s##S_(int G, int v, const PairArgs &a, int tiles_m, hipStream_t s);  \
+    hipError_t pair_grouped_s##S_(int G, int v, const PairArgs &a, hipStream_t s);
 OZ_DECLARE_PAIR_S(2)
 OZ_DECLARE_PAIR_S(3)
 OZ_DECLARE_PAIR_S(4)
@@ -368,24 +427,18 @@ OZ_DECLARE_PAIR_S(8)
 #undef OZ_DECLARE_PAIR_S
 
 // Instantiate the three diagonal counts G = S, S + 1, 2S - 1 for one S.
-#define OZ_DEFINE_PAIR_S(S_)                                                                  \
-    hipError_t pair_single_s##S_(int G, const PairArgs &a, int tiles_m, hipStream_t s) {      \
-        if (G == S_) return pair::run_single<S_, S_>(a, tiles_m, s);                          \
-        if (G == S_ + 1) return pair::run_single<S_, S_ + 1>(a, tiles_m, s);                  \
-        if (G == 2 * S_ - 1) return pair::run_single<S_, 2 * S_ - 1>(a, tiles_m, s);          \
-        return hipErrorInvalidValue;                                                          \
-    }                                                                                         \
-    hipError_t pair_grouped_s##S_(int G, const PairArgs &a, hipStream_t s) {                  \
-        if (G == S_) return pair::run_grouped<S_, S_>(a, s);                                  \
-        if (G == S_ + 1) return pair::run_grouped<S_, S_ + 1>(a, s);                          \
-        if (G == 2 * S_ - 1) return pair::run_grouped<S_, 2 * S_ - 1>(a, s);                  \
-        return hipErrorInvalidValue;                                                          \
-    }                                                                                         \
-    bool pair_shape_s##S_(int G, PairShape *out) {                                            \
-        if (G == S_) { *out = pair::shape_of<S_, S_>(); return true; }                        \
-        if (G == S_ + 1) { *out = pair::shape_of<S_, S_ + 1>(); return true; }                \
-        if (G == 2 * S_ - 1) { *out = pair::shape_of<S_, 2 * S_ - 1>(); return true; }        \
-        return false;                                                                         \
+#define OZ_DEFINE_PAIR_S(S_)                                                                    \
+    hipError_t pair_single_s##S_(int G, int v, const PairArgs &a, int tiles_m, hipStream_t s) { \
+        if (G == S_) return pair::run_single<S_, S_>(v, a, tiles_m, s);                         \
+        if (G == S_ + 1) return pair::run_single<S_, S_ + 1>(v, a, tiles_m, s);                 \
+        if (G == 2 * S_ - 1) return pair::run_single<S_, 2 * S_ - 1>(v, a, tiles_m, s);         \
+        return hipErrorInvalidValue;                                                            \
+    }                                                                                           \
+    hipError_t pair_grouped_s##S_(int G, int v, const PairArgs &a, hipStream_t s) {             \
+        if (G == S_) return pair::run_grouped<S_, S_>(v, a, s);                                 \
+        if (G == S_ + 1) return pair::run_grouped<S_, S_ + 1>(v, a, s);                         \
+        if (G == 2 * S_ - 1) return pair::run_grouped<S_, 2 * S_ - 1>(v, a, s);                 \
+        return hipErrorInvalidValue;                                                            \
     }
 
 }  // namespace oz

@@ -15,6 +15,9 @@ struct ozaki_ctx_s {
     uint32_t *d_flags = nullptr;  // sticky OZ_FLAG_* bits on the device
     void *scratch = nullptr;      // grow-only scratch of the debug entry points
     size_t scratch_bytes = 0;
+    // tile variant of the pair GEMM per (S, G); -1 = library default
+    int variant[9][16];
+    bool autotune = true;  // heff plans time the variants of their grouped phases
     // phase timing (ozaki_ctx_set_timing)
     bool timing = false;
     std::vector<hipEvent_t> events;  // pool
@@ -43,6 +46,9 @@ GemmWorkspace gemm_workspace(int64_t M, int64_t N, int64_t K, int S, int G);
 // is off or the pool is used up); phase() files the pair under a phase id.
 hipEvent_t mark(ozaki_ctx ctx, hipStream_t s);
 void phase(ozaki_ctx ctx, int id, hipEvent_t a, hipEvent_t b);
+
+// Variant for (S, G) in this context (explicit choice or the default).
+int ctx_variant(ozaki_ctx ctx, int S, int G);
 
 hipError_t slice_operand(int S, bool by_rows, const double *X, int64_t ld, int64_t R, int64_t K,
                          int32_t *e, int8_t *packed, double *part, uint32_t *flag, hipStream_t s);

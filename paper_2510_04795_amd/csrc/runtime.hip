@@ -53,8 +53,8 @@ GemmWorkspace gemm_workspace(int64_t M, int64_t N, int64_t K, int S, int G) {
     w.part = off; off += align256(col_exponent_scratch(K, M > N ? M : N));
     w.qw = off;
     if (K > max_exact_k(S, G)) {
-        const PairShape sh = pair_shape(S, G);
-        const int64_t mt = round_up(M, sh.bm), nt = round_up(N, sh.bn);
+        // sized for the largest tile of any variant
+        const int64_t mt = round_up(M, 128), nt = round_up(N, 128);
         off += align256(sizeof(int64_t) * static_cast<size_t>(G) * mt * nt);
     }
     w.total = off;
@@ -86,6 +86,11 @@ hipEvent_t mark(ozaki_ctx ctx, hipStream_t s) {
 
 void phase(ozaki_ctx ctx, int id, hipEvent_t a, hipEvent_t b) {
     if (a && b) ctx->recs.push_back({id, a, b});
+}
+
+int ctx_variant(ozaki_ctx ctx, int S, int G) {
+    const int v = (S >= 0 && S < 9 && G >= 0 && G < 16) ? ctx->variant[S][G] : -1;
+    return v >= 0 ? v : pair_default_variant(G);
 }
 
 }  // namespace oz
@@ -124,6 +129,8 @@ int ozaki_ctx_create(ozaki_ctx *out, int device) {
     if ((e = hipSetDevice(device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
     auto *c = new ozaki_ctx_s();
     c->device = device;
+    for (auto &row : c->variant)
+        for (auto &v : row) v = -1;
     hipDeviceProp_t prop;
     if ((e = hipGetDeviceProperties(&prop, device)) != hipSuccess) {
         delete c;
@@ -197,6 +204,89 @@ int ozaki_ctx_phase_times(ozaki_ctx ctx, int32_t *phase_out, double *ms, int32_t
     ctx->recs.clear();
     ctx->next_event = 0;
     return n;
+}
+
+int ozaki_pair_variants(int slices, int ndiag, int32_t *tile_m, int32_t *tile_n, int32_t max_variants) {
+    if (slices < 2 || slices > 8) return fail(OZ_ERR_ARG, "ozaki_pair_variants: slices = %d", slices);
+    const int G = resolve_ndiag(slices, ndiag);
+    if (!valid_sg(slices, G)) return fail(OZ_ERR_ARG, "ozaki_pair_variants: ndiag = %d", ndiag);
+    const int nv = pair_num_variants();
+    for (int v = 0; v < nv && v < max_variants; ++v) {
+        const bool ok = pair_variant_ok(G, v);
+        const PairShape sh = pair_shape(slices, G, v);
+        if (tile_m) tile_m[v] = ok ? sh.bm : 0;
+        if (tile_n) tile_n[v] = ok ? sh.bn : 0;
+    }
+    return nv;
+}
+
+int ozaki_ctx_set_variant(ozaki_ctx ctx, int slices, int ndiag, int variant) {
+    if (!ctx) return fail(OZ_ERR_ARG, "ozaki_ctx_set_variant: ctx is NULL");
+    if (slices < 2 || slices > 8) return fail(OZ_ERR_ARG, "ozaki_ctx_set_variant: slices = %d", slices);
+    const int G = resolve_ndiag(slices, ndiag);
+    if (!valid_sg(slices, G)) return fail(OZ_ERR_ARG, "ozaki_ctx_set_variant: ndiag = %d", ndiag);
+    if (variant >= 0 && !pair_variant_ok(G, variant))
+        return fail(OZ_ERR_ARG, "ozaki_ctx_set_variant: variant %d is not built for G = %d", variant, G);
+    ctx->variant[slices][G] = variant < 0 ? -1 : variant;
+    return OZ_OK;
+}
+
+int ozaki_ctx_get_variant(ozaki_ctx ctx, int slices, int ndiag) {
+    if (!ctx) return fail(OZ_ERR_ARG, "ozaki_ctx_get_variant: ctx is NULL");
+    if (slices < 2 || slices > 8) return fail(OZ_ERR_ARG, "ozaki_ctx_get_variant: slices = %d", slices);
+    const int G = resolve_ndiag(slices, ndiag);
+    if (!valid_sg(slices, G)) return fail(OZ_ERR_ARG, "ozaki_ctx_get_variant: ndiag = %d", ndiag);
+    return ctx_variant(ctx, slices, G);
+}
+
+int ozaki_ctx_set_autotune(ozaki_ctx ctx, int enable) {
+    if (!ctx) return fail(OZ_ERR_ARG, "ozaki_ctx_set_autotune: ctx is NULL");
+    ctx->autotune = enable != 0;
+    return OZ_OK;
+}
+
+int ozaki_dgemm_tune(ozaki_ctx ctx, char transa, char transb, int64_t M, int64_t N, int64_t K,
+                     const double *A, int64_t lda, const double *B, int64_t ldb, double *C,
+                     int64_t ldc, int slices, int ndiag, void *workspace, size_t workspace_bytes,
+                     void *stream, double *ms_out) {
+    if (!ctx) return fail(OZ_ERR_ARG, "ozaki_dgemm_tune: ctx is NULL");
+    if (slices < 2 || slices > 8) return fail(OZ_ERR_ARG, "ozaki_dgemm_tune: slices = %d", slices);
+    const int G = resolve_ndiag(slices, ndiag);
+    if (!valid_sg(slices, G)) return fail(OZ_ERR_ARG, "ozaki_dgemm_tune: ndiag = %d", ndiag);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    hipEvent_t ev0, ev1;
+    if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+    if ((e = hipEventCreate(&ev0)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+    if ((e = hipEventCreate(&ev1)) != hipSuccess) { hipEventDestroy(ev0); return hip_fail(e, "hipEventCreate"); }
+    const int saved = ctx->variant[slices][G];
+    int best = -1;
+    float best_ms = 0.f;
+    int rc = OZ_OK;
+    for (int v = 0; v < pair_num_variants(); ++v) {
+        if (ms_out) ms_out[v] = -1.0;
+        if (!pair_variant_ok(G, v)) continue;
+        ctx->variant[slices][G] = v;
+        rc = ozaki_dgemm(ctx, transa, transb, M, N, K, 1.0, A, lda, B, ldb, 0.0, C, ldc, slices, G,
+                         workspace, workspace_bytes, stream);
+        if (rc != OZ_OK) break;
+        hipEventRecord(ev0, s);
+        for (int rep = 0; rep < 3 && rc == OZ_OK; ++rep)
+            rc = ozaki_dgemm(ctx, transa, transb, M, N, K, 1.0, A, lda, B, ldb, 0.0, C, ldc, slices, G,
+                             workspace, workspace_bytes, stream);
+        hipEventRecord(ev1, s);
+        if (rc != OZ_OK) break;
+        if ((e = hipEventSynchronize(ev1)) != hipSuccess) { rc = hip_fail(e, "ozaki_dgemm_tune: sync"); break; }
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, ev0, ev1);
+        ms /= 3.f;
+        if (ms_out) ms_out[v] = ms;
+        if (best < 0 || ms < best_ms) { best = v; best_ms = ms; }
+    }
+    hipEventDestroy(ev0);
+    hipEventDestroy(ev1);
+    ctx->variant[slices][G] = (rc == OZ_OK && best >= 0) ? best : saved;
+    return rc == OZ_OK ? best : rc;
 }
 
 int ozaki_slices_for_bits(int mantissa_bits) {
@@ -291,7 +381,8 @@ int ozaki_dgemm(ozaki_ctx ctx, char transa, char transb, int64_t M, int64_t N, i
 
     hipEvent_t t1 = mark(ctx, s);
     phase(ctx, OZ_PHASE_SLICE, t0, t1);
-    const PairShape sh = pair_shape(slices, G);
+    const int var = ctx_variant(ctx, slices, G);
+    const PairShape sh = pair_shape(slices, G, var);
     PairArgs a{};
     a.tiles_n = static_cast<int32_t>(ceil_div(N, sh.bn));
     const int tiles_m = static_cast<int>(ceil_div(M, sh.bm));
@@ -317,13 +408,13 @@ int ozaki_dgemm(ozaki_ctx ctx, char transa, char transb, int64_t M, int64_t N, i
             c.mode = last ? kModeGemm : kModeQ64;
             c.qw_first = kb0 == 0;
             c.Qw = qw;
-            if ((e = launch_pair_single(slices, G, c, tiles_m, s)) != hipSuccess)
+            if ((e = launch_pair_single(slices, G, var, c, tiles_m, s)) != hipSuccess)
                 return hip_fail(e, "ozaki_dgemm: pair GEMM launch (chunked)");
         }
         phase(ctx, OZ_PHASE_PAIR, t1, mark(ctx, s));
         return OZ_OK;
     }
-    e = launch_pair_single(slices, G, a, tiles_m, s);
+    e = launch_pair_single(slices, G, var, a, tiles_m, s);
     phase(ctx, OZ_PHASE_PAIR, t1, mark(ctx, s));
     return e == hipSuccess ? OZ_OK : hip_fail(e, "ozaki_dgemm: pair GEMM launch");
 }
@@ -379,14 +470,15 @@ int ozaki_pair_products(ozaki_ctx ctx, int64_t M, int64_t N, int64_t K, int slic
     hipStream_t s = static_cast<hipStream_t>(stream);
     if ((e = launch_pack(slices, Adig, M, K, pa, Mp, s)) != hipSuccess) return hip_fail(e, "pack A");
     if ((e = launch_pack(slices, BTdig, N, K, pb, Np, s)) != hipSuccess) return hip_fail(e, "pack B");
-    const PairShape sh = pair_shape(slices, G);
+    const int var = ctx_variant(ctx, slices, G);
+    const PairShape sh = pair_shape(slices, G, var);
     PairArgs a{};
     a.tiles_n = static_cast<int32_t>(ceil_div(N, sh.bn));
     a.term = TermDesc{pa, nullptr, pb, nullptr, Mp, Np, static_cast<int32_t>(Kp / kKB), 0, 1.0};
     a.out = OutDesc{nullptr, 0, static_cast<int32_t>(M), static_cast<int32_t>(N)};
     a.mode = kModeQ;
     a.Q = Q;
-    if ((e = launch_pair_single(slices, G, a, static_cast<int>(ceil_div(M, sh.bm)), s)) != hipSuccess)
+    if ((e = launch_pair_single(slices, G, var, a, static_cast<int>(ceil_div(M, sh.bm)), s)) != hipSuccess)
         return hip_fail(e, "ozaki_pair_products: launch");
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "ozaki_pair_products: sync");
     return OZ_OK;

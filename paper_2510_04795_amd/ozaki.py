@@ -63,6 +63,13 @@ _sig("ozaki_ctx_destroy", _i32, [_ptr])
 _sig("ozaki_ctx_flags", _i32, [_ptr, ctypes.POINTER(ctypes.c_uint32)])
 _sig("ozaki_ctx_set_timing", _i32, [_ptr, _i32])
 _sig("ozaki_ctx_phase_times", _i32, [_ptr, _ptr, _ptr, _i32])
+_sig("ozaki_pair_variants", _i32, [_i32, _i32, _ptr, _ptr, _i32])
+_sig("ozaki_ctx_set_variant", _i32, [_ptr, _i32, _i32, _i32])
+_sig("ozaki_ctx_get_variant", _i32, [_ptr, _i32, _i32])
+_sig("ozaki_ctx_set_autotune", _i32, [_ptr, _i32])
+_sig("ozaki_dgemm_tune", _i32, [_ptr, ctypes.c_char, ctypes.c_char, _i64, _i64, _i64, _ptr, _i64, _ptr,
+                                _i64, _ptr, _i64, _i32, _i32, _ptr, _sz, _ptr, _ptr])
+_sig("heff_plan_variants", _i32, [_ptr, _ptr, _ptr])
 _sig("ozaki_slices_for_bits", _i32, [_i32])
 _sig("ozaki_pair_count", _i32, [_i32, _i32])
 _sig("ozaki_max_exact_k", _i64, [_i32, _i32])
@@ -85,7 +92,8 @@ _sig("davidson_destroy", _i32, [_ptr])
 EXPORTED = [
     "ozaki_status_string", "ozaki_last_error", "ozaki_version", "ozaki_ctx_create",
     "ozaki_ctx_destroy", "ozaki_ctx_flags", "ozaki_ctx_set_timing", "ozaki_ctx_phase_times",
-    "ozaki_slices_for_bits", "ozaki_pair_count",
+    "ozaki_pair_variants", "ozaki_ctx_set_variant", "ozaki_ctx_get_variant",
+    "ozaki_ctx_set_autotune", "ozaki_dgemm_tune", "heff_plan_variants", "ozaki_slices_for_bits", "ozaki_pair_count",
     "ozaki_max_exact_k", "ozaki_dgemm_workspace_bytes", "ozaki_dgemm", "ozaki_split",
     "ozaki_pair_products", "heff_plan_create", "heff_apply", "heff_vector_length", "heff_flops",
     "heff_plan_destroy", "davidson_create", "davidson_step", "davidson_get_vector",
@@ -127,6 +135,16 @@ def _ld(t: torch.Tensor, name: str) -> int:
     if t.size(1) > 1 and t.stride(1) != 1:
         raise ValueError("%s must be a row-major 2-D tensor with unit column stride" % name)
     return max(t.stride(0), t.size(1), 1)
+
+
+def pair_variants(slices: int, ndiag: int = 0):
+    """[(variant, tile_m, tile_n)] of the built tile variants for (slices, ndiag)."""
+    import numpy as np
+    tm = np.zeros(16, dtype=np.int32)
+    tn = np.zeros(16, dtype=np.int32)
+    n = _check(_lib.ozaki_pair_variants(slices, ndiag, tm.ctypes.data, tn.ctypes.data, 16),
+               "ozaki_pair_variants")
+    return [(v, int(tm[v]), int(tn[v])) for v in range(n) if tm[v] > 0]
 
 
 def slices_for_bits(bits: int) -> int:
@@ -183,6 +201,37 @@ class Context:
         n = _check(_lib.ozaki_ctx_phase_times(self.handle, ph.ctypes.data, ms.ctypes.data,
                                               max_phases), "ozaki_ctx_phase_times")
         return [(PHASES.get(int(p), str(int(p))), float(t)) for p, t in zip(ph[:n], ms[:n])]
+
+    def set_variant(self, slices: int, ndiag: int = 0, variant: int = -1):
+        _check(_lib.ozaki_ctx_set_variant(self.handle, slices, ndiag, variant), "ozaki_ctx_set_variant")
+
+    def get_variant(self, slices: int, ndiag: int = 0) -> int:
+        return _check(_lib.ozaki_ctx_get_variant(self.handle, slices, ndiag), "ozaki_ctx_get_variant")
+
+    def set_autotune(self, enable: bool = True):
+        _check(_lib.ozaki_ctx_set_autotune(self.handle, int(bool(enable))), "ozaki_ctx_set_autotune")
+
+    def tune(self, A, B, slices: int, ndiag: int = 0, C=None, transa="N", transb="N",
+             workspace=None, stream=None):
+        """Time every tile variant on this GEMM and keep the fastest; returns
+        (variant, {variant: ms})."""
+        import numpy as np
+        ta, tb = transa.upper() == "T", transb.upper() == "T"
+        M = A.size(1) if ta else A.size(0)
+        K = A.size(0) if ta else A.size(1)
+        N = B.size(0) if tb else B.size(1)
+        if C is None:
+            C = torch.empty((M, N), dtype=torch.float64, device=A.device)
+        if workspace is None:
+            workspace = self.workspace(M, N, K, slices, ndiag)
+        ms = np.zeros(16, dtype=np.float64)
+        v = _check(_lib.ozaki_dgemm_tune(self.handle, transa.upper().encode(), transb.upper().encode(),
+                                         M, N, K, A.data_ptr(), _ld(A, "A"), B.data_ptr(), _ld(B, "B"),
+                                         C.data_ptr(), _ld(C, "C"), slices, ndiag,
+                                         workspace.data_ptr(),
+                                         workspace.numel() * workspace.element_size(),
+                                         _stream(stream), ms.ctypes.data), "ozaki_dgemm_tune")
+        return v, {i: float(t) for i, t in enumerate(ms[:4]) if t >= 0}
 
     # ---- GEMM -----------------------------------------------------------
     def workspace(self, M, N, K, slices, ndiag=0) -> torch.Tensor | None:
@@ -290,6 +339,9 @@ class HeffPlan:
         self.handle = h
         self.n = int(_lib.heff_vector_length(h))
         self.flops = float(_lib.heff_flops(h))
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        _check(_lib.heff_plan_variants(h, ctypes.byref(a), ctypes.byref(b)), "heff_plan_variants")
+        self.variants = (a.value, b.value)
 
     def apply(self, psi, sigma=None, stream=None):
         _dev_f64(psi, "psi")

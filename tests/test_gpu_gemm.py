@@ -200,3 +200,37 @@ def test_dgemm_full_size_sampled_rows(oz):
     got = Cd[torch.from_numpy(rows).cuda()].cpu().numpy()
     ref = oracle.ozaki_dgemm(A[rows], B, 6)
     assert_bitexact(got, ref, "n=8192 rows")
+
+
+@pytest.mark.parametrize("S,G", [(2, 3), (4, 4), (5, 6), (6, 6), (8, 8), (7, 13)])
+def test_every_tile_variant_bitexact(oz, S, G):
+    """Tile variants change only the schedule: all give the oracle's bits."""
+    ozaki, ctx, torch = oz
+    rng = np.random.default_rng(300 + S * 16 + G)
+    A = wl.wide_normal(rng, (150, 270), 12)
+    B = wl.wide_normal(rng, (270, 199), 12)
+    ref = oracle.ozaki_dgemm(A, B, S, G)
+    variants = ozaki.pair_variants(S, G)
+    assert variants and all(tm % 64 == 0 and tn % 64 == 0 for (_, tm, tn) in variants)
+    try:
+        for (v, tm, tn) in variants:
+            ctx.set_variant(S, G, v)
+            assert ctx.get_variant(S, G) == v
+            got = ctx.dgemm(dev(torch, A), dev(torch, B), slices=S, ndiag=G).cpu().numpy()
+            assert_bitexact(got, ref, "variant %d (%dx%d)" % (v, tm, tn))
+    finally:
+        ctx.set_variant(S, G, -1)
+
+
+def test_tune_picks_a_built_variant(oz):
+    ozaki, ctx, torch = oz
+    rng = np.random.default_rng(12)
+    A = dev(torch, wl.wide_normal(rng, (512, 512), 10))
+    B = dev(torch, wl.wide_normal(rng, (512, 512), 10))
+    v, times = ctx.tune(A, B, slices=6)
+    assert v in [x[0] for x in ozaki.pair_variants(6)]
+    assert set(times) == set(x[0] for x in ozaki.pair_variants(6))
+    assert ctx.get_variant(6) == v
+    ctx.set_variant(6, 0, -1)
+    with pytest.raises(ozaki.OzakiError):
+        ctx.set_variant(8, 15, 3)   # 2x2 blocks of 15 accumulator sets are not built

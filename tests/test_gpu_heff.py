@@ -174,3 +174,23 @@ def test_plan_argument_errors(oz):
     bad = dict(layout, psi_offset=[0, 10], psi_lr=[0, 0, 0, 0])
     with pytest.raises(ozaki.OzakiError):
         ozaki.HeffPlan(ctx, bad, dL, dR, triples, slices=6)
+
+
+def test_plan_variants_bitexact(oz):
+    """Each fixed tile variant and the autotuned choice give the oracle's bits."""
+    ozaki, ctx, torch = oz
+    prob = small_sparse(21)
+    ref = oracle.heff_sparse(prob, S=6)
+    try:
+        for (v, tm, tn) in ozaki.pair_variants(6):
+            ctx.set_variant(6, 0, v)
+            plan, dpsi, keep = sparse_plan(ozaki, ctx, torch, prob, 6)
+            assert plan.variants == (v, v)
+            sig = wl.unflatten_sparse(prob, plan.apply(dpsi).cpu().numpy())
+            for b in prob.psi_blocks:
+                assert_bitexact(sig[b], ref[b], "variant %d block %s" % (v, b))
+    finally:
+        ctx.set_variant(6, 0, -1)
+    plan, dpsi, keep = sparse_plan(ozaki, ctx, torch, prob, 6)
+    built = [x[0] for x in ozaki.pair_variants(6)]
+    assert plan.variants[0] in built and plan.variants[1] in built
