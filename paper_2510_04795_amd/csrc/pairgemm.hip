@@ -17,7 +17,7 @@ int pair_default_variant(int G) { return pair::default_variant(G); }
 PairShape pair_shape(int S, int G, int v) {
     (void)S;
     if (v < 0) v = pair::default_variant(G);
-    return PairShape{2 * pair::variant_mb(v) * 32, 2 * pair::variant_nb(v) * 32};
+    return PairShape{pair::variant_bm(v), pair::variant_bn(v)};
 }
 
 hipError_t launch_pair_single(int S, int G, int v, const PairArgs &a, int tiles_m, hipStream_t s) {

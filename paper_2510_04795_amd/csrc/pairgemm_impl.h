@@ -32,10 +32,13 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 typedef __attribute__((address_space(3))) void lds_void;
 
-template <int S, int G, int MB, int NB>
+// WM x WN waves per block, each owning MB x NB blocks of 32 x 32 outputs.
+template <int S, int G, int WM, int WN, int MB, int NB>
 struct Cfg {
-    static constexpr int BM = 2 * MB * 32;
-    static constexpr int BN = 2 * NB * 32;
+    static constexpr int NW = WM * WN;                  // waves per block
+    static constexpr int NT = 64 * NW;                  // threads per block
+    static constexpr int BM = WM * MB * 32;
+    static constexpr int BN = WN * NB * 32;
     static constexpr int STAGE = 2 * S * (BM + BN);     // uint4 per LDS stage
     static constexpr int A_SEG = 2 * S * BM / 64;       // 64-row wave loads for A
     static constexpr int SEGS = 2 * S * (BM + BN) / 64; // all wave loads per stage
@@ -46,10 +49,10 @@ struct Cfg {
 // 16-byte chunk per lane).  The per-wave segment list is fixed for a term, so
 // it is computed once: a lane address at block 0, the per-block stride and
 // the LDS offset of each segment the wave owns.
-template <int S, int G, int MB, int NB>
+template <int S, int G, int WM, int WN, int MB, int NB>
 struct LoadPlan {
-    using C = Cfg<S, G, MB, NB>;
-    static constexpr int NL = (C::SEGS + 3) / 4;
+    using C = Cfg<S, G, WM, WN, MB, NB>;
+    static constexpr int NL = (C::SEGS + C::NW - 1) / C::NW;
     const uint4 *src[NL];
     int64_t stride[NL];
     int lds_off[NL];
@@ -59,7 +62,7 @@ struct LoadPlan {
                                          int64_t b_rows_p, int m0, int n0, int wave, int lane) {
 #pragma unroll
         for (int i = 0; i < NL; ++i) {
-            const int q = wave + 4 * i;
+            const int q = wave + C::NW * i;
             valid[i] = q < C::SEGS;
             if (q < C::A_SEG) {
                 const int run = q / (C::BM / 64);
@@ -93,12 +96,14 @@ struct LoadPlan {
 
 // All kept pair products of one LDS stage (one 32-wide K block).  The B
 // fragments of every kept slice stay in registers; A fragments are streamed
-// one slice at a time, so operands cost 4 S NB + 4 MB registers.
-template <int S, int G, int MB, int NB>
+// one slice at a time, the next slice's read issued before the current
+// slice's MFMAs so the LDS latency hides behind them.
+template <int S, int G, int WM, int WN, int MB, int NB>
 __device__ __forceinline__ void multiply_stage(v16i (&acc)[G][MB][NB], const uint4 *stage, int wm,
                                                int wn, int half, int l32) {
-    using C = Cfg<S, G, MB, NB>;
+    using C = Cfg<S, G, WM, WN, MB, NB>;
     constexpr int TB = S < G ? S : G;  // B slices that meet at least one kept pair
+    constexpr int SA = S < G ? S : G;  // A slices that meet at least one kept pair
     const uint4 *sA = stage;
     const uint4 *sB = stage + 2 * S * C::BM;
     v4i bf[TB][NB];
@@ -110,15 +115,22 @@ __device__ __forceinline__ void multiply_stage(v16i (&acc)[G][MB][NB], const uin
             bf[t][nb] = v4i{static_cast<int>(v.x), static_cast<int>(v.y), static_cast<int>(v.z),
                             static_cast<int>(v.w)};
         }
+    v4i af[2][MB];
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-        if (s >= G) continue;
-        v4i af[MB];
+    for (int mb = 0; mb < MB; ++mb) {
+        const uint4 v = sA[half * C::BM + (wm * MB + mb) * 32 + l32];
+        af[0][mb] = v4i{static_cast<int>(v.x), static_cast<int>(v.y), static_cast<int>(v.z),
+                        static_cast<int>(v.w)};
+    }
 #pragma unroll
-        for (int mb = 0; mb < MB; ++mb) {
-            const uint4 v = sA[(s * 2 + half) * C::BM + (wm * MB + mb) * 32 + l32];
-            af[mb] = v4i{static_cast<int>(v.x), static_cast<int>(v.y), static_cast<int>(v.z),
-                         static_cast<int>(v.w)};
+    for (int s = 0; s < SA; ++s) {
+        if (s + 1 < SA) {
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb) {
+                const uint4 v = sA[((s + 1) * 2 + half) * C::BM + (wm * MB + mb) * 32 + l32];
+                af[(s + 1) & 1][mb] = v4i{static_cast<int>(v.x), static_cast<int>(v.y),
+                                          static_cast<int>(v.z), static_cast<int>(v.w)};
+            }
         }
 #pragma unroll
         for (int t = 0; t < TB; ++t) {
@@ -128,20 +140,20 @@ __device__ __forceinline__ void multiply_stage(v16i (&acc)[G][MB][NB], const uin
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb)
                     acc[s + t][mb][nb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
-                        af[mb], bf[t][nb], acc[s + t][mb][nb], 0, 0, 0);
+                        af[s & 1][mb], bf[t][nb], acc[s + t][mb][nb], 0, 0, 0);
         }
     }
 }
 
 // Exact diagonal sums of one tile for one term, accumulated over all K blocks.
-template <int S, int G, int MB, int NB>
+template <int S, int G, int WM, int WN, int MB, int NB>
 __device__ __forceinline__ void pair_mainloop(v16i (&acc)[G][MB][NB], uint4 *lds0, uint4 *lds1,
                                               const TermDesc &T, int m0, int n0) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform per wave
-    const int wm = wave >> 1;
-    const int wn = wave & 1;
+    const int wm = wave / WN;
+    const int wn = wave % WN;
     const int half = lane >> 5;
     const int l32 = lane & 31;
     const uint4 *gA = reinterpret_cast<const uint4 *>(T.A);
@@ -156,7 +168,7 @@ __device__ __forceinline__ void pair_mainloop(v16i (&acc)[G][MB][NB], uint4 *lds
             for (int nb = 0; nb < NB; ++nb) acc[g][mb][nb] = v16i{};
     if (nkb == 0) return;
 
-    LoadPlan<S, G, MB, NB> lp;
+    LoadPlan<S, G, WM, WN, MB, NB> lp;
     lp.init(gA, gB, T.a_rows_p, T.b_rows_p, m0, n0, wave, lane);
     lp.issue(lds0, 0);
     // Blocks are taken two at a time (stage 0, stage 1) so each LDS stage is
@@ -167,16 +179,16 @@ __device__ __forceinline__ void pair_mainloop(v16i (&acc)[G][MB][NB], uint4 *lds
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         lp.issue(lds1, kb + 1);
-        multiply_stage<S, G, MB, NB>(acc, lds0, wm, wn, half, l32);
+        multiply_stage<S, G, WM, WN, MB, NB>(acc, lds0, wm, wn, half, l32);
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         if (kb + 2 < nkb) lp.issue(lds0, kb + 2);
-        multiply_stage<S, G, MB, NB>(acc, lds1, wm, wn, half, l32);
+        multiply_stage<S, G, WM, WN, MB, NB>(acc, lds1, wm, wn, half, l32);
     }
     if (kb < nkb) {
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        multiply_stage<S, G, MB, NB>(acc, lds0, wm, wn, half, l32);
+        multiply_stage<S, G, WM, WN, MB, NB>(acc, lds0, wm, wn, half, l32);
     }
 }
 
@@ -190,14 +202,14 @@ __device__ __forceinline__ double horner(const long long (&q)[G], int32_t ei, in
     return ldexp(h, ei + fj - 14);
 }
 
-template <int S, int G, int MB, int NB, int MODE, typename GetTerm>
+template <int S, int G, int WM, int WN, int MB, int NB, int MODE, typename GetTerm>
 __device__ __forceinline__ void pair_tile(const PairArgs &a, GetTerm get_term, int tb, int te,
                                           const OutDesc &out, int m0, int n0, uint4 *lds0,
                                           uint4 *lds1) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int wm = wave >> 1;
-    const int wn = wave & 1;
+    const int wm = wave / WN;
+    const int wn = wave % WN;
     const int half = lane >> 5;
     const int l32 = lane & 31;
 
@@ -215,7 +227,7 @@ __device__ __forceinline__ void pair_tile(const PairArgs &a, GetTerm get_term, i
     for (int ti = tb; ti < tend; ++ti) {
         const TermDesc T = get_term(ti);
         v16i acc[G][MB][NB];
-        pair_mainloop<S, G, MB, NB>(acc, lds0, lds1, T, m0, n0);
+        pair_mainloop<S, G, WM, WN, MB, NB>(acc, lds0, lds1, T, m0, n0);
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
             const int j = n0 + (wn * NB + nb) * 32 + l32;
@@ -283,9 +295,12 @@ __device__ __forceinline__ void pair_tile(const PairArgs &a, GetTerm get_term, i
 }
 
 // Tile index -> (tm, tn).  Blocks are dispatched to the 8 XCDs round robin;
-// give every XCD a contiguous range of tiles, walked in groups of 8 tile rows,
-// so the blocks sharing an L2 also share A and B panels.
-__device__ __forceinline__ void tile_coords(int b, int tiles_m, int tiles_n, int &tm, int &tn) {
+// give every XCD a contiguous range of tiles, walked in groups of `group`
+// tile rows, so the blocks that run together on one L2 share A and B panels.
+// With ~32 blocks in flight per XCD as a x b tiles, each K block fetches
+// a A slabs and b B slabs: for a BM x BN tile the fetch per tile is
+// proportional to BM / b + BN / a, smallest at a / b = BN / BM.
+__device__ __forceinline__ void tile_coords(int b, int tiles_m, int tiles_n, int group, int &tm, int &tn) {
     const int T = tiles_m * tiles_n;
     const int nx = 8;
     const int q = T / nx;
@@ -293,7 +308,6 @@ __device__ __forceinline__ void tile_coords(int b, int tiles_m, int tiles_n, int
     const int x = b % nx;
     const int idx = b / nx;
     const int lin = x * q + (x < rem ? x : rem) + idx;
-    const int group = 8;
     const int per_group = group * tiles_n;
     const int gid = lin / per_group;
     const int first = gid * group;
@@ -303,51 +317,69 @@ __device__ __forceinline__ void tile_coords(int b, int tiles_m, int tiles_n, int
     tn = w / rows;
 }
 
-template <int S, int G, int MB, int NB, int MODE>
-__global__ __launch_bounds__(256) void k_pair_single(PairArgs a, int tiles_m) {
-    using C = Cfg<S, G, MB, NB>;
+template <int S, int G, int WM, int WN, int MB, int NB, int MODE>
+__global__ __launch_bounds__(64 * WM * WN) void k_pair_single(PairArgs a, int tiles_m) {
+    using C = Cfg<S, G, WM, WN, MB, NB>;
     __shared__ uint4 lds0[C::STAGE];
     __shared__ uint4 lds1[C::STAGE];
     int tm, tn;
-    tile_coords(blockIdx.x, tiles_m, a.tiles_n, tm, tn);
+    constexpr int group = C::BM >= 2 * C::BN ? 4 : 8;
+    tile_coords(blockIdx.x, tiles_m, a.tiles_n, group, tm, tn);
     const TermDesc term = a.term;
-    pair_tile<S, G, MB, NB, MODE>(a, [&](int) { return term; }, 0, 1, a.out, tm * C::BM,
-                                  tn * C::BN, lds0, lds1);
+    pair_tile<S, G, WM, WN, MB, NB, MODE>(a, [&](int) { return term; }, 0, 1, a.out, tm * C::BM,
+                                          tn * C::BN, lds0, lds1);
 }
 
 // One block per listed tile (tiles are listed longest first).
-template <int S, int G, int MB, int NB, int MODE>
-__global__ __launch_bounds__(256) void k_pair_grouped(PairArgs a) {
-    using C = Cfg<S, G, MB, NB>;
+template <int S, int G, int WM, int WN, int MB, int NB, int MODE>
+__global__ __launch_bounds__(64 * WM * WN) void k_pair_grouped(PairArgs a) {
+    using C = Cfg<S, G, WM, WN, MB, NB>;
     __shared__ uint4 lds0[C::STAGE];
     __shared__ uint4 lds1[C::STAGE];
     const TileDesc td = a.tiles[blockIdx.x];
     OutDesc od = a.outs[td.out];
     if (a.out_base) od.C = a.out_base + reinterpret_cast<intptr_t>(od.C);
     const TermDesc *terms = a.terms;
-    pair_tile<S, G, MB, NB, MODE>(a, [&](int i) { return terms[i]; }, td.term_begin, td.term_end,
-                                  od, td.m0, td.n0, lds0, lds1);
+    pair_tile<S, G, WM, WN, MB, NB, MODE>(a, [&](int i) { return terms[i]; }, td.term_begin,
+                                          td.term_end, od, td.m0, td.n0, lds0, lds1);
 }
 
 // Per-(S, G) tile shape: as wide as the accumulators allow.
-// Wave-tile variants (MB x NB blocks of 32 x 32 per wave).  The 1 x 1
-// variant is always built; a wider one only when its G accumulator sets fit
-// in 192 registers (16 G MB NB), leaving the rest of the register file to
-// operands and addresses.
-constexpr int kNumVariants = 4;
-__host__ __device__ constexpr int variant_mb(int v) { return v == 1 || v == 3 ? 2 : 1; }
-__host__ __device__ constexpr int variant_nb(int v) { return v == 2 || v == 3 ? 2 : 1; }
+// Tile variants: WM x WN waves of MB x NB blocks of 32 x 32 outputs.
+//   v  waves  wave tile  block tile  built when (registers per wave)
+//   0  2x2    1x1        64 x 64     always
+//   1  2x2    2x1        128 x 64    32 G <= 192
+//   2  2x2    2x2        128 x 128   64 G <= 192
+//   3  4x2    1x1        128 x 64    16 G <= 128 (two waves per SIMD)
+//   4  2x4    1x1        64 x 128    16 G <= 128
+//   5  2x4    2x1        128 x 128   32 G <= 160
+//   6  4x4    1x1        128 x 128   16 G <= 64  (four waves per SIMD)
+// Accumulators take 16 G MB NB registers; the budget leaves room for the
+// operands, addresses and, with several waves per SIMD, their share of the
+// register file.
+constexpr int kNumVariants = 7;
+__host__ __device__ constexpr int variant_wm(int v) { return v == 3 || v == 6 ? 4 : 2; }
+__host__ __device__ constexpr int variant_wn(int v) { return v == 4 || v == 5 || v == 6 ? 4 : 2; }
+__host__ __device__ constexpr int variant_mb(int v) { return v == 1 || v == 2 || v == 5 ? 2 : 1; }
+__host__ __device__ constexpr int variant_nb(int v) { return v == 2 ? 2 : 1; }
 __host__ __device__ constexpr bool variant_fits(int G, int v) {
-    return v == 0 || 16 * G * variant_mb(v) * variant_nb(v) <= 192;
+    return v == 0 ? true
+         : v == 1 ? 32 * G <= 192
+         : v == 2 ? 64 * G <= 192
+         : v == 3 || v == 4 ? 16 * G <= 128
+         : v == 5 ? 32 * G <= 160
+         : v == 6 ? 16 * G <= 64
+         : false;
 }
-// default: the widest tile that fits, preferring 2 x 1
-__host__ __device__ constexpr int default_variant(int G) {
-    return variant_fits(G, 3) ? 3 : (variant_fits(G, 1) ? 1 : 0);
-}
+__host__ __device__ constexpr int variant_bm(int v) { return variant_wm(v) * variant_mb(v) * 32; }
+__host__ __device__ constexpr int variant_bn(int v) { return variant_wn(v) * variant_nb(v) * 32; }
+// default before tuning: the 128 x 64 four-wave tile where it fits
+__host__ __device__ constexpr int default_variant(int G) { return variant_fits(G, 1) ? 1 : 0; }
 
 template <int S, int G, int V>
 hipError_t run_single_v(const PairArgs &a, int tiles_m, hipStream_t s) {
-    constexpr int MB = variant_mb(V), NB = variant_nb(V);
+    constexpr int WM = variant_wm(V), WN = variant_wn(V), MB = variant_mb(V), NB = variant_nb(V);
+    constexpr int NT = 64 * WM * WN;
     if constexpr (!variant_fits(G, V)) {
         return hipErrorInvalidValue;
     } else {
@@ -355,13 +387,21 @@ hipError_t run_single_v(const PairArgs &a, int tiles_m, hipStream_t s) {
         if (grid == 0) return hipSuccess;
         switch (a.mode) {
             case kModeGemm:
-                hipLaunchKernelGGL((k_pair_single<S, G, MB, NB, kModeGemm>), dim3(grid), dim3(256), 0, s, a, tiles_m);
+                hipLaunchKernelGGL((k_pair_single<S, G, WM, WN, MB, NB, kModeGemm>), dim3(grid), dim3(NT), 0, s, a, tiles_m);
                 break;
             case kModeQ:
-                hipLaunchKernelGGL((k_pair_single<S, G, MB, NB, kModeQ>), dim3(grid), dim3(256), 0, s, a, tiles_m);
+                if constexpr (V == 0) {
+                    hipLaunchKernelGGL((k_pair_single<S, G, WM, WN, MB, NB, kModeQ>), dim3(grid), dim3(NT), 0, s, a, tiles_m);
+                } else {
+                    return hipErrorInvalidValue;
+                }
                 break;
             case kModeQ64:
-                hipLaunchKernelGGL((k_pair_single<S, G, MB, NB, kModeQ64>), dim3(grid), dim3(256), 0, s, a, tiles_m);
+                if constexpr (V == 0) {
+                    hipLaunchKernelGGL((k_pair_single<S, G, WM, WN, MB, NB, kModeQ64>), dim3(grid), dim3(NT), 0, s, a, tiles_m);
+                } else {
+                    return hipErrorInvalidValue;
+                }
                 break;
             default: return hipErrorInvalidValue;
         }
@@ -371,17 +411,18 @@ hipError_t run_single_v(const PairArgs &a, int tiles_m, hipStream_t s) {
 
 template <int S, int G, int V>
 hipError_t run_grouped_v(const PairArgs &a, hipStream_t s) {
-    constexpr int MB = variant_mb(V), NB = variant_nb(V);
+    constexpr int WM = variant_wm(V), WN = variant_wn(V), MB = variant_mb(V), NB = variant_nb(V);
+    constexpr int NT = 64 * WM * WN;
     if constexpr (!variant_fits(G, V)) {
         return hipErrorInvalidValue;
     } else {
         if (a.ntiles == 0) return hipSuccess;
         switch (a.mode) {
             case kModeGemm:
-                hipLaunchKernelGGL((k_pair_grouped<S, G, MB, NB, kModeGemm>), dim3(a.ntiles), dim3(256), 0, s, a);
+                hipLaunchKernelGGL((k_pair_grouped<S, G, WM, WN, MB, NB, kModeGemm>), dim3(a.ntiles), dim3(NT), 0, s, a);
                 break;
             case kModeAccum:
-                hipLaunchKernelGGL((k_pair_grouped<S, G, MB, NB, kModeAccum>), dim3(a.ntiles), dim3(256), 0, s, a);
+                hipLaunchKernelGGL((k_pair_grouped<S, G, WM, WN, MB, NB, kModeAccum>), dim3(a.ntiles), dim3(NT), 0, s, a);
                 break;
             default: return hipErrorInvalidValue;
         }
@@ -396,6 +437,9 @@ hipError_t run_single(int v, const PairArgs &a, int tiles_m, hipStream_t s) {
         case 1: return run_single_v<S, G, 1>(a, tiles_m, s);
         case 2: return run_single_v<S, G, 2>(a, tiles_m, s);
         case 3: return run_single_v<S, G, 3>(a, tiles_m, s);
+        case 4: return run_single_v<S, G, 4>(a, tiles_m, s);
+        case 5: return run_single_v<S, G, 5>(a, tiles_m, s);
+        case 6: return run_single_v<S, G, 6>(a, tiles_m, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -407,6 +451,9 @@ hipError_t run_grouped(int v, const PairArgs &a, hipStream_t s) {
         case 1: return run_grouped_v<S, G, 1>(a, s);
         case 2: return run_grouped_v<S, G, 2>(a, s);
         case 3: return run_grouped_v<S, G, 3>(a, s);
+        case 4: return run_grouped_v<S, G, 4>(a, s);
+        case 5: return run_grouped_v<S, G, 5>(a, s);
+        case 6: return run_grouped_v<S, G, 6>(a, s);
         default: return hipErrorInvalidValue;
     }
 }

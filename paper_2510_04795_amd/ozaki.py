@@ -224,14 +224,14 @@ class Context:
             C = torch.empty((M, N), dtype=torch.float64, device=A.device)
         if workspace is None:
             workspace = self.workspace(M, N, K, slices, ndiag)
-        ms = np.zeros(16, dtype=np.float64)
+        ms = np.full(16, -1.0, dtype=np.float64)
         v = _check(_lib.ozaki_dgemm_tune(self.handle, transa.upper().encode(), transb.upper().encode(),
                                          M, N, K, A.data_ptr(), _ld(A, "A"), B.data_ptr(), _ld(B, "B"),
                                          C.data_ptr(), _ld(C, "C"), slices, ndiag,
                                          workspace.data_ptr(),
                                          workspace.numel() * workspace.element_size(),
                                          _stream(stream), ms.ctypes.data), "ozaki_dgemm_tune")
-        return v, {i: float(t) for i, t in enumerate(ms[:4]) if t >= 0}
+        return v, {i: float(t) for i, t in enumerate(ms) if t >= 0}
 
     # ---- GEMM -----------------------------------------------------------
     def workspace(self, M, N, K, slices, ndiag=0) -> torch.Tensor | None:
