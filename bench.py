@@ -102,6 +102,8 @@ def gemm_section(args, ozaki, ctx, torch, oracle):
     configs = [(S, G) for S in range(4, 9) for G in (S, S + 1)]
     ws = ctx.workspace(n, n, n, 8, 9)
     for (S, G) in configs:
+        # pick the tile variant by timing them all on this GEMM (outside the timed region)
+        variant, tune_ms = ctx.tune(dA, dB, slices=S, ndiag=G, C=C, workspace=ws)
         ctx.dgemm(dA, dB, slices=S, ndiag=G, C=C, workspace=ws)
         err = oracle.rel_frobenius(C[idx].cpu().numpy(), hi, lo)
         ctx.phase_times()
@@ -111,7 +113,9 @@ def gemm_section(args, ozaki, ctx, torch, oracle):
         P = ozaki.pair_count(S, G)
         pair_ms = ph["pair"][0]
         slice_ms = ph["slice"][0]
-        r = {"slices": S, "ndiag": G, "pairs": P, "ms": t * 1e3, "tflops": flops / t / 1e12,
+        r = {"slices": S, "ndiag": G, "pairs": P, "variant": variant,
+             "tune_ms": {str(k): round(v, 4) for k, v in tune_ms.items()},
+             "ms": t * 1e3, "tflops": flops / t / 1e12,
              "rel_frobenius": err, "pair_kernel_ms": pair_ms, "slice_ms": slice_ms,
              "int8_tops": P * flops / (pair_ms * 1e-3) / 1e12 if pair_ms else None}
         r["int8_frac"] = r["int8_tops"] / INT8_PEAK_TOPS if r["int8_tops"] else None
@@ -119,8 +123,8 @@ def gemm_section(args, ozaki, ctx, torch, oracle):
         # write S bytes per element of each
         r["slice_gbs"] = (2 * n * n * (16 + S)) / (slice_ms * 1e-3) / 1e9 if slice_ms else None
         results.append(r)
-        log("[bench] S=%d G=%d P=%2d: %.3f ms  %.2f TFLOP/s  relF %.2e  pair %.3f ms (%.1f%% int8 peak)"
-            " slice %.3f ms" % (S, G, P, t * 1e3, r["tflops"], err, pair_ms or 0,
+        log("[bench] S=%d G=%d P=%2d v%d: %.3f ms  %.2f TFLOP/s  relF %.2e  pair %.3f ms (%.1f%% int8 peak)"
+            " slice %.3f ms" % (S, G, P, variant, t * 1e3, r["tflops"], err, pair_ms or 0,
                                 100 * (r["int8_frac"] or 0), slice_ms or 0))
     ctx.set_timing(False)
     eq = [r for r in results if r["rel_frobenius"] <= err64]
@@ -129,6 +133,56 @@ def gemm_section(args, ozaki, ctx, torch, oracle):
     at_1e12 = min(tol, key=lambda r: r["ms"]) if tol else None
     return {"n": n, "fp64": fp64, "vendor_fp64": vendor, "emulated": results, "chosen": chosen,
             "at_1e-12": at_1e12, "rows_for_error": len(rows)}, (A, B)
+
+
+PAIR_SOURCES = ["internal.h", "pairgemm_impl.h", "pairgemm.hip"] + ["pairgemm_s%d.hip" % s for s in range(2, 9)]
+COUNTERS_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                             "pair_gemm_n8192_hbm_counters.txt")
+
+
+def pair_bytes(n, S):
+    """Algorithmic HBM bytes of one pair-GEMM launch on square n: both packed
+    operands read once (S bytes per element), exponents read, C written."""
+    return 2 * S * n * n + 2 * 4 * n + 8 * n * n
+
+
+def pair_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2510_04795_amd", "csrc")
+    for f in PAIR_SOURCES:
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def pair_traffic(n, S, G, variant):
+    """HBM bytes per pair-GEMM launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by the plain-copy calibration),
+    or None when there is none for this case or the kernel sources changed
+    since the counters were taken."""
+    if not os.path.exists(COUNTERS_FILE):
+        return None
+    meta, rows = {}, {}
+    with open(COUNTERS_FILE) as fh:
+        for line in fh:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            if "=" in line:
+                k, v = line.split("=", 1)
+                meta[k.strip()] = v.strip()
+                continue
+            f = line.split()
+            if f[0].isdigit():
+                rows[(int(f[0]), int(f[1]), int(f[2]), int(f[3]))] = (float(f[5]), float(f[6]))
+    if meta.get("source_sha256") != pair_source_hash():
+        return None
+    got = rows.get((n, S, G, variant))
+    if got is None:
+        return None
+    fetch_kib, write_kib = got
+    return (fetch_kib * float(meta["fetch_factor"]) + write_kib * float(meta["write_factor"])) * 1024.0
 
 
 def heff_flat_plan(ozaki, ctx, torch, layout, Lf, Rf, triples, S, G=0, diag=None):
@@ -238,7 +292,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--err-rows", type=int, default=16)
-    ap.add_argument("--cpu-rows", type=int, default=8)
+    ap.add_argument("--cpu-rows", type=int, default=96)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--sections", default="gemm,dense,sparse,davidson",
                     help="comma list of gemm, dense, sparse, davidson")
@@ -302,8 +356,11 @@ def main():
                                % (gemm["n"], chosen["slices"], chosen["ndiag"]),
                    "n": gemm["n"], "slices": chosen["slices"], "ndiag": chosen["ndiag"]},
         "roofline": {"bound": "mfma", "achieved": chosen["int8_tops"], "peak": INT8_PEAK_TOPS,
-                     "unit": "TFLOP/s", "frac": chosen["int8_frac"], "traffic": None,
-                     "kernel": "int8 pair GEMM (k_pair_single)",
+                     "unit": "TFLOP/s", "frac": chosen["int8_frac"],
+                     "traffic": pair_traffic(gemm["n"], chosen["slices"], chosen["ndiag"], chosen["variant"]),
+                     "kernel": "int8 pair GEMM k_pair_single (variant %d); achieved = pairs * 2n^3 int8 "
+                               "ops / mean kernel time (HIP events on its stream)" % chosen["variant"],
+                     "algorithmic_bytes": pair_bytes(gemm["n"], chosen["slices"]),
                      "kernel_ms": chosen["pair_kernel_ms"]},
         "fp64_mfma": gemm["fp64"],
         "vendor_fp64": gemm["vendor_fp64"],

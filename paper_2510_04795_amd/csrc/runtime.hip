@@ -381,7 +381,9 @@ int ozaki_dgemm(ozaki_ctx ctx, char transa, char transb, int64_t M, int64_t N, i
 
     hipEvent_t t1 = mark(ctx, s);
     phase(ctx, OZ_PHASE_SLICE, t0, t1);
-    const int var = ctx_variant(ctx, slices, G);
+    const int64_t kmax = max_exact_k(slices, G);
+    // the int64 carries between K chunks are built for the 64 x 64 tile only
+    const int var = K > kmax ? 0 : ctx_variant(ctx, slices, G);
     const PairShape sh = pair_shape(slices, G, var);
     PairArgs a{};
     a.tiles_n = static_cast<int32_t>(ceil_div(N, sh.bn));
@@ -390,7 +392,6 @@ int ozaki_dgemm(ozaki_ctx ctx, char transa, char transb, int64_t M, int64_t N, i
     a.out = OutDesc{C, ldc, static_cast<int32_t>(M), static_cast<int32_t>(N)};
     a.mode = kModeGemm;
     a.beta = beta;
-    const int64_t kmax = max_exact_k(slices, G);
     if (K > kmax) {
         // exact int32 sums per K chunk, carried between chunk launches in int64
         const int64_t chunk = kmax / kKB;
@@ -470,7 +471,7 @@ int ozaki_pair_products(ozaki_ctx ctx, int64_t M, int64_t N, int64_t K, int slic
     hipStream_t s = static_cast<hipStream_t>(stream);
     if ((e = launch_pack(slices, Adig, M, K, pa, Mp, s)) != hipSuccess) return hip_fail(e, "pack A");
     if ((e = launch_pack(slices, BTdig, N, K, pb, Np, s)) != hipSuccess) return hip_fail(e, "pack B");
-    const int var = ctx_variant(ctx, slices, G);
+    const int var = 0;  // the int32 diagonal-sum output is built for the 64 x 64 tile only
     const PairShape sh = pair_shape(slices, G, var);
     PairArgs a{};
     a.tiles_n = static_cast<int32_t>(ceil_div(N, sh.bn));
