@@ -234,8 +234,20 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *layout,
                      const heff_triple *triples, const double *diag, int slices, int ndiag,
                      void *stream);
 /* sigma = H_eff psi (sigma overwritten; psi and sigma must not overlap).
- * One grouped launch per phase; enqueue only. */
+ * One grouped launch per phase; enqueue only.
+ * Replay: the first apply with a given (psi, sigma) pair captures the
+ * plan's launch sequence into a HIP graph (on a private stream; this creates
+ * the graph, which takes host and driver resources) and later applies with
+ * the same pair launch that graph on `stream`.  At most 96 graphs are kept
+ * per plan; evicting the least recently used one synchronises `stream`.
+ * The launches are issued directly instead when phase timing is on, when
+ * `stream` is being captured by the caller, or after
+ * heff_plan_set_graphs(plan, 0).  Results are identical either way. */
 int heff_apply(heff_plan plan, const double *psi, double *sigma, void *stream);
+/* Enable (default) or disable graph replay in heff_apply. */
+int heff_plan_set_graphs(heff_plan plan, int enable);
+/* Number of graphs the plan currently holds. */
+int heff_plan_graph_count(heff_plan plan);
 /* Tile variants the plan's two grouped phases use (emulated plans; -1 for
  * native FP64 plans). */
 int heff_plan_variants(heff_plan plan, int32_t *first, int32_t *second);

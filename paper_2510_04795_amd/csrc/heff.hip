@@ -50,6 +50,18 @@ struct heff_plan_s {
     int varL = -1, varR = -1;   // tile variants of the two grouped phases
     // FP64 path
     Dgemm64Args d64L{}, d64R{};
+    // Replay: one instantiated graph of the apply sequence per (psi, sigma)
+    // pair, captured on a private stream the first time the pair is seen.
+    struct GraphSlot {
+        const double *psi;
+        double *sigma;
+        hipGraphExec_t exec;
+        uint64_t used;
+    };
+    bool use_graphs = true;
+    hipStream_t cap = nullptr;
+    std::vector<GraphSlot> graphs;
+    uint64_t clock = 0;
 };
 
 namespace {
@@ -78,6 +90,8 @@ int alloc(heff_plan p, size_t bytes, void **out) {
 }
 
 void free_plan(heff_plan p) {
+    for (auto &g : p->graphs) hipGraphExecDestroy(g.exec);
+    if (p->cap) hipStreamDestroy(p->cap);
     for (void *d : p->allocs) hipFree(d);
     delete p;
 }
@@ -521,14 +535,12 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
     return OZ_OK;
 }
 
-int heff_apply(heff_plan P, const double *psi, double *sigma, void *stream) {
-    if (!P) return fail(OZ_ERR_ARG, "heff_apply: plan is NULL");
-    if (P->n > 0 && (!psi || !sigma)) return fail(OZ_ERR_ARG, "heff_apply: psi / sigma NULL");
-    if (psi == sigma && P->n > 0) return fail(OZ_ERR_ARG, "heff_apply: psi and sigma overlap");
-    hipStream_t s = static_cast<hipStream_t>(stream);
+namespace {
+
+// The launches of one apply, in order, on stream s.
+int enqueue_apply(heff_plan P, const double *psi, double *sigma, hipStream_t s) {
     ozaki_ctx ctx = P->ctx;
     hipError_t e;
-    if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
     if (P->S == 0) {
         hipEvent_t t0 = mark(ctx, s);
         Dgemm64Args a = P->d64L;
@@ -566,6 +578,82 @@ int heff_apply(heff_plan P, const double *psi, double *sigma, void *stream) {
         if ((e = launch_diag_axpy(P->diag, psi, sigma, P->n, s)) != hipSuccess) return hip_fail(e, "heff_apply: diagonal");
     }
     return OZ_OK;
+}
+
+constexpr size_t kMaxGraphs = 96;
+
+// Capture the apply sequence for (psi, sigma) and instantiate it; evicts the
+// least recently used graph when the cache is full.
+int capture_apply(heff_plan P, const double *psi, double *sigma, hipStream_t s,
+                  heff_plan_s::GraphSlot **out) {
+    hipError_t e;
+    if (!P->cap && (e = hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking)) != hipSuccess)
+        return hip_fail(e, "heff_apply: capture stream");
+    if (P->graphs.size() >= kMaxGraphs) {
+        size_t lru = 0;
+        for (size_t i = 1; i < P->graphs.size(); ++i)
+            if (P->graphs[i].used < P->graphs[lru].used) lru = i;
+        // the evicted graph may still run on the caller's stream
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "heff_apply: sync before eviction");
+        hipGraphExecDestroy(P->graphs[lru].exec);
+        P->graphs.erase(P->graphs.begin() + static_cast<std::ptrdiff_t>(lru));
+    }
+    if ((e = hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+        return hip_fail(e, "heff_apply: begin capture");
+    const int rc = enqueue_apply(P, psi, sigma, P->cap);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(P->cap, &graph);
+    if (rc != OZ_OK) {
+        if (graph) hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "heff_apply: end capture");
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(e, "heff_apply: instantiate");
+    P->graphs.push_back({psi, sigma, exec, 0});
+    *out = &P->graphs.back();
+    return OZ_OK;
+}
+
+}  // namespace
+
+int heff_apply(heff_plan P, const double *psi, double *sigma, void *stream) {
+    if (!P) return fail(OZ_ERR_ARG, "heff_apply: plan is NULL");
+    if (P->n > 0 && (!psi || !sigma)) return fail(OZ_ERR_ARG, "heff_apply: psi / sigma NULL");
+    if (psi == sigma && P->n > 0) return fail(OZ_ERR_ARG, "heff_apply: psi and sigma overlap");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    ozaki_ctx ctx = P->ctx;
+    hipError_t e;
+    if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+    if (P->n == 0) return OZ_OK;
+    // replay a captured graph unless phases are being timed or the caller's
+    // stream is itself being captured (then the launches go into that graph)
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if ((e = hipStreamIsCapturing(s, &cs)) != hipSuccess) return hip_fail(e, "heff_apply: capture status");
+    if (!P->use_graphs || ctx->timing || cs != hipStreamCaptureStatusNone) return enqueue_apply(P, psi, sigma, s);
+    heff_plan_s::GraphSlot *g = nullptr;
+    for (auto &x : P->graphs)
+        if (x.psi == psi && x.sigma == sigma) g = &x;
+    if (!g) {
+        const int rc = capture_apply(P, psi, sigma, s, &g);
+        if (rc != OZ_OK) return rc;
+    }
+    g->used = ++P->clock;
+    if ((e = hipGraphLaunch(g->exec, s)) != hipSuccess) return hip_fail(e, "heff_apply: graph launch");
+    return OZ_OK;
+}
+
+int heff_plan_set_graphs(heff_plan P, int enable) {
+    if (!P) return fail(OZ_ERR_ARG, "heff_plan_set_graphs: plan is NULL");
+    P->use_graphs = enable != 0;
+    return OZ_OK;
+}
+
+int heff_plan_graph_count(heff_plan P) {
+    if (!P) return fail(OZ_ERR_ARG, "heff_plan_graph_count: plan is NULL");
+    return static_cast<int>(P->graphs.size());
 }
 
 int64_t heff_vector_length(heff_plan P) { return P ? P->n : -1; }

@@ -81,6 +81,8 @@ _sig("ozaki_pair_products", _i32, [_ptr, _i64, _i64, _i64, _i32, _i32, _ptr, _pt
 _sig("heff_plan_create", _i32, [_ptr, ctypes.POINTER(_ptr), ctypes.POINTER(HeffLayout), _ptr, _ptr,
                                 _i32, ctypes.POINTER(HeffTriple), _ptr, _i32, _i32, _ptr])
 _sig("heff_apply", _i32, [_ptr, _ptr, _ptr, _ptr])
+_sig("heff_plan_set_graphs", _i32, [_ptr, _i32])
+_sig("heff_plan_graph_count", _i32, [_ptr])
 _sig("heff_vector_length", _i64, [_ptr])
 _sig("heff_flops", _dbl, [_ptr])
 _sig("heff_plan_destroy", _i32, [_ptr])
@@ -95,7 +97,8 @@ EXPORTED = [
     "ozaki_pair_variants", "ozaki_ctx_set_variant", "ozaki_ctx_get_variant",
     "ozaki_ctx_set_autotune", "ozaki_dgemm_tune", "heff_plan_variants", "ozaki_slices_for_bits", "ozaki_pair_count",
     "ozaki_max_exact_k", "ozaki_dgemm_workspace_bytes", "ozaki_dgemm", "ozaki_split",
-    "ozaki_pair_products", "heff_plan_create", "heff_apply", "heff_vector_length", "heff_flops",
+    "ozaki_pair_products", "heff_plan_create", "heff_apply", "heff_plan_set_graphs",
+    "heff_plan_graph_count", "heff_vector_length", "heff_flops",
     "heff_plan_destroy", "davidson_create", "davidson_step", "davidson_get_vector",
     "davidson_destroy",
 ]
@@ -352,6 +355,14 @@ class HeffPlan:
         _check(_lib.heff_apply(self.handle, psi.data_ptr(), sigma.data_ptr(), _stream(stream)),
                "heff_apply")
         return sigma
+
+    def set_graphs(self, enable: bool = True):
+        """Replay captured HIP graphs in apply (default) or issue the launches directly."""
+        _check(_lib.heff_plan_set_graphs(self.handle, int(bool(enable))), "heff_plan_set_graphs")
+
+    @property
+    def graph_count(self) -> int:
+        return _check(_lib.heff_plan_graph_count(self.handle), "heff_plan_graph_count")
 
     def close(self):
         if getattr(self, "handle", None):

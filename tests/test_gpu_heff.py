@@ -194,3 +194,67 @@ def test_plan_variants_bitexact(oz):
     plan, dpsi, keep = sparse_plan(ozaki, ctx, torch, prob, 6)
     built = [x[0] for x in ozaki.pair_variants(6)]
     assert plan.variants[0] in built and plan.variants[1] in built
+
+
+@pytest.mark.parametrize("kind", ["dense", "sparse", "fp64"])
+def test_graph_replay_matches_eager(oz, kind):
+    """Applies replayed from captured graphs give the eager launches' bits on
+    every replay, with other work and synchronisations in between, and read
+    the buffers' current contents."""
+    ozaki, ctx, torch = oz
+    S = 0 if kind == "fp64" else 6
+    if kind == "sparse":
+        prob = small_sparse(31)
+        plan, dpsi, keep = sparse_plan(ozaki, ctx, torch, prob, S)
+    else:
+        L, R, psi = wl.heff_dense(D=72, kop=3, phys=4, seed=8)
+        diag = np.random.default_rng(9).standard_normal(psi.shape)
+        plan, dpsi, keep = dense_plan(ozaki, ctx, torch, L, R, psi, S, diag=diag)
+    plan.set_graphs(False)
+    ref = plan.apply(dpsi).cpu().numpy()
+    assert plan.graph_count == 0
+    plan.set_graphs(True)
+    sig = torch.empty_like(dpsi)
+    other = torch.empty_like(dpsi)
+    psi2 = dpsi * 0.5 - 1.0
+    plan.set_graphs(False)
+    ref2 = plan.apply(psi2).cpu().numpy()
+    plan.set_graphs(True)
+    for rep in range(4):
+        sig.fill_(float("nan"))
+        plan.apply(dpsi, sig)
+        torch.cuda.synchronize()
+        assert_bitexact(sig.cpu().numpy(), ref, "%s replay %d" % (kind, rep))
+        plan.apply(psi2, other)                       # a second graph, interleaved
+        (other * 2.0).sum().item()                    # eager work and a host sync between replays
+        assert_bitexact(other.cpu().numpy(), ref2, "%s second pair replay %d" % (kind, rep))
+    assert plan.graph_count == 2
+    # the graph reads whatever psi holds now
+    dpsi.copy_(psi2)
+    plan.apply(dpsi, sig)
+    assert_bitexact(sig.cpu().numpy(), ref2, "%s new contents" % kind)
+    assert plan.graph_count == 2
+    if kind == "dense" and S:
+        want = oracle.heff_dense(L, R, psi * 0.5 - 1.0, S=S, diag=diag).ravel()
+        assert_bitexact(sig.cpu().numpy(), want, "dense oracle")
+
+
+def test_graph_cache_eviction(oz):
+    """More distinct (psi, sigma) pairs than the cache holds: evicted pairs are
+    captured again and every result stays exact."""
+    ozaki, ctx, torch = oz
+    L, R, psi = wl.heff_dense(D=24, kop=2, phys=1, seed=12)
+    plan, dpsi, keep = dense_plan(ozaki, ctx, torch, L, R, psi, 5)
+    plan.set_graphs(False)
+    ref = plan.apply(dpsi).cpu().numpy()
+    plan.set_graphs(True)
+    outs = [torch.empty_like(dpsi) for _ in range(100)]
+    for o in outs:
+        plan.apply(dpsi, o)
+    assert plan.graph_count == 96
+    for o in outs[:3]:
+        o.zero_()
+        plan.apply(dpsi, o)
+    torch.cuda.synchronize()
+    for i, o in enumerate(outs):
+        assert_bitexact(o.cpu().numpy(), ref, "pair %d" % i)
