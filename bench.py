@@ -99,11 +99,18 @@ def gemm_section(args, ozaki, ctx, torch, oracle):
     log("[bench] vendor fp64 (torch.mm): %.3f ms  %.2f TFLOP/s  relF %.2e" % (t * 1e3, vendor["tflops"], err_t))
     del Ct
 
-    configs = [(S, G) for S in range(4, 9) for G in (S, S + 1)]
+    if args.gemm_configs:
+        configs = [tuple(int(v) for v in c.split(":")) for c in args.gemm_configs.split(",")]
+    else:
+        configs = [(S, G) for S in range(4, 9) for G in (S, S + 1)]
     ws = ctx.workspace(n, n, n, 8, 9)
     for (S, G) in configs:
-        # pick the tile variant by timing them all on this GEMM (outside the timed region)
-        variant, tune_ms = ctx.tune(dA, dB, slices=S, ndiag=G, C=C, workspace=ws)
+        if args.variant >= 0:
+            ctx.set_variant(S, G, args.variant)
+            variant, tune_ms = args.variant, {}
+        else:
+            # pick the tile variant by timing them all on this GEMM (outside the timed region)
+            variant, tune_ms = ctx.tune(dA, dB, slices=S, ndiag=G, C=C, workspace=ws)
         ctx.dgemm(dA, dB, slices=S, ndiag=G, C=C, workspace=ws)
         err = oracle.rel_frobenius(C[idx].cpu().numpy(), hi, lo)
         ctx.phase_times()
@@ -363,6 +370,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--sections", default="gemm,dense,sparse,davidson,sweep",
                     help="comma list of gemm, dense, sparse, davidson, sweep (the GEMM section always runs)")
+    ap.add_argument("--gemm-configs", default="",
+                    help="comma list of S:G for the GEMM section (default: S = 4..8, G in {S, S+1})")
+    ap.add_argument("--variant", type=int, default=-1,
+                    help="fixed pair-GEMM tile variant for the GEMM section (default: tuned per S, G)")
     ap.add_argument("--heff-d", type=int, default=2048)
     ap.add_argument("--heff-kop", type=int, default=64)
     ap.add_argument("--heff-steps", type=int, default=3)

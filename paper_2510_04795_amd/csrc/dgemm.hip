@@ -148,6 +148,7 @@ __global__ __launch_bounds__(256) void k_dgemm_grouped(Dgemm64Args a) {
     __shared__ double sB[kBK][kBN + kPad];
     for (int t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
         const TileDesc td = a.tiles[t];
+        if (td.out < 0) continue;  // padding of the XCD order
         OutDesc od = a.outs[td.out];
         if (a.out_base) od.C = a.out_base + reinterpret_cast<intptr_t>(od.C);
         const Term64 *terms = a.terms;

@@ -160,10 +160,78 @@ struct TileWork {
     int64_t cost;
 };
 
-void sort_tiles(std::vector<TileWork> &w, std::vector<TileDesc> *out) {
-    std::stable_sort(w.begin(), w.end(), [](const TileWork &a, const TileWork &b) { return a.cost > b.cost; });
+// The tiles of one output of M x N in a walk that keeps the blocks running
+// together on one XCD close in both operands: groups of tile rows (fewer for
+// tall tiles), column by column inside a group.
+template <typename Make>
+void walk_output(int64_t M, int64_t N, const PairShape &sh, Make make, std::vector<TileWork> *w) {
+    const int64_t tm_n = ceil_div(M, sh.bm), tn_n = ceil_div(N, sh.bn);
+    const int64_t group = sh.bm >= 2 * sh.bn ? 4 : 8;
+    for (int64_t first = 0; first < tm_n; first += group) {
+        const int64_t rows = std::min(group, tm_n - first);
+        for (int64_t q = 0; q < rows * tn_n; ++q)
+            w->push_back(make((first + q % rows) * sh.bm, (q / rows) * sh.bn));
+    }
+}
+
+constexpr int kXcds = 8;
+
+// Workgroup b of a launch runs on XCD b % 8.  Outputs are taken longest
+// tile first (each output's tiles stay together in their walk), the list is
+// cut into 8 contiguous parts of about equal cost and interleaved, so every
+// XCD walks its own part in order; shorter parts are padded with empty tiles
+// (output -1), which exit at once.
+// Longest tile first over all outputs: for tiles of very different cost the
+// hardware's own balancing over the XCDs does better than fixed parts.
+void longest_first(const std::vector<std::vector<TileWork>> &outputs, std::vector<TileDesc> *out,
+                   std::vector<int64_t> *cost) {
+    std::vector<TileWork> all;
+    for (auto &o : outputs) all.insert(all.end(), o.begin(), o.end());
+    std::stable_sort(all.begin(), all.end(), [](const TileWork &a, const TileWork &b) { return a.cost > b.cost; });
     out->clear();
-    for (auto &x : w) out->push_back(x.td);
+    cost->clear();
+    for (auto &t : all) {
+        out->push_back(t.td);
+        cost->push_back(t.cost);
+    }
+}
+
+void xcd_order(std::vector<std::vector<TileWork>> &outputs, std::vector<TileDesc> *out,
+               std::vector<int64_t> *cost) {
+    std::stable_sort(outputs.begin(), outputs.end(), [](const std::vector<TileWork> &a, const std::vector<TileWork> &b) {
+        const int64_t ca = a.empty() ? 0 : a.front().cost, cb = b.empty() ? 0 : b.front().cost;
+        return ca > cb;
+    });
+    std::vector<TileWork> all;
+    int64_t total = 0;
+    for (auto &o : outputs)
+        for (auto &t : o) {
+            all.push_back(t);
+            total += t.cost;
+        }
+    std::vector<std::vector<TileWork>> part(kXcds);
+    int64_t run = 0;
+    size_t x = 0;
+    for (auto &t : all) {
+        // the part whose share of the cost this tile starts in
+        while (x + 1 < part.size() && run * kXcds >= total * static_cast<int64_t>(x + 1)) ++x;
+        part[x].push_back(t);
+        run += t.cost;
+    }
+    size_t longest = 0;
+    for (auto &p : part) longest = std::max(longest, p.size());
+    out->clear();
+    cost->clear();
+    for (size_t i = 0; i < longest; ++i)
+        for (auto &p : part) {
+            if (i < p.size()) {
+                out->push_back(p[i].td);
+                cost->push_back(p[i].cost);
+            } else {
+                out->push_back(TileDesc{0, 0, 0, 0, -1, 0});
+                cost->push_back(0);
+            }
+        }
 }
 
 }  // namespace
@@ -187,6 +255,14 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
     std::vector<int64_t> ld(L->left_dim, L->left_dim + L->n_left), rd(L->right_dim, L->right_dim + L->n_right);
     for (auto d : ld) if (d < 1) return fail(OZ_ERR_ARG, "heff_plan_create: left sector size %lld", (long long)d);
     for (auto d : rd) if (d < 1) return fail(OZ_ERR_ARG, "heff_plan_create: right sector size %lld", (long long)d);
+    // every operand of the two products has at most phys * (largest sector) rows
+    {
+        int64_t big = 1;
+        for (auto d : ld) big = std::max(big, d);
+        for (auto d : rd) big = std::max(big, d);
+        if (round_up(big * std::max<int64_t>(L->phys, 1), kRowQ) > kMaxPackedRows)
+            return fail(OZ_ERR_ARG, "heff_plan_create: phys * sector size above %lld", (long long)kMaxPackedRows);
+    }
 
     // psi / sigma blocks
     std::map<std::pair<int, int>, int> psi_of;
@@ -275,7 +351,7 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
         // first product: T_u = L Psi  (op(B) = B, B offsets relative to psi)
         std::vector<Term64> termsL;
         std::vector<OutDesc> outsL;
-        std::vector<TileWork> wl;
+        std::vector<std::vector<TileWork>> wl(us.size());
         for (size_t u = 0; u < us.size(); ++u) {
             const U &x = us[u];
             const int64_t M = ld[x.lo], N = p * rd[x.ri], K = ld[x.li];
@@ -288,15 +364,15 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
             tm.alpha = 1.0;
             termsL.push_back(tm);
             outsL.push_back(OutDesc{P->T + x.t_off, N, static_cast<int32_t>(M), static_cast<int32_t>(N)});
-            for (int64_t m0 = 0; m0 < M; m0 += sh.bm)
-                for (int64_t n0 = 0; n0 < N; n0 += sh.bn)
-                    wl.push_back({TileDesc{static_cast<int32_t>(u), static_cast<int32_t>(u + 1), static_cast<int32_t>(m0),
-                                           static_cast<int32_t>(n0), static_cast<int32_t>(u), 0}, K});
+            walk_output(M, N, sh, [&](int64_t m0, int64_t n0) {
+                return TileWork{TileDesc{static_cast<int32_t>(u), static_cast<int32_t>(u + 1), static_cast<int32_t>(m0),
+                                         static_cast<int32_t>(n0), static_cast<int32_t>(u), 0}, K};
+            }, &wl[u]);
         }
         // second product: sigma' = sum alpha T'_u R^T  (op(B) = R^T)
         std::vector<Term64> termsR;
         std::vector<OutDesc> outsR;
-        std::vector<TileWork> wr;
+        std::vector<std::vector<TileWork>> wr(L->n_psi_blocks);
         for (int b = 0; b < L->n_psi_blocks; ++b) {
             const int lo = L->psi_lr[2 * b], ro = L->psi_lr[2 * b + 1];
             const int64_t M = ld[lo] * p, N = rd[ro];
@@ -317,13 +393,14 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
             const int te = static_cast<int>(termsR.size());
             outsR.push_back(OutDesc{reinterpret_cast<double *>(static_cast<intptr_t>(L->psi_offset[b])), N,
                                     static_cast<int32_t>(M), static_cast<int32_t>(N)});
-            for (int64_t m0 = 0; m0 < M; m0 += sh.bm)
-                for (int64_t n0 = 0; n0 < N; n0 += sh.bn)
-                    wr.push_back({TileDesc{tb, te, static_cast<int32_t>(m0), static_cast<int32_t>(n0), b, 0}, cost});
+            walk_output(M, N, sh, [&](int64_t m0, int64_t n0) {
+                return TileWork{TileDesc{tb, te, static_cast<int32_t>(m0), static_cast<int32_t>(n0), b, 0}, cost + 1};
+            }, &wr[b]);
         }
         std::vector<TileDesc> tl, tr;
-        sort_tiles(wl, &tl);
-        sort_tiles(wr, &tr);
+        std::vector<int64_t> cl, cr;
+        xcd_order(wl, &tl, &cl);
+        xcd_order(wr, &tr, &cr);
         TileDesc *dt;
         Term64 *dm;
         OutDesc *dout;
@@ -428,34 +505,33 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
         outsR.push_back(OutDesc{reinterpret_cast<double *>(static_cast<intptr_t>(L->psi_offset[b])), N,
                                 static_cast<int32_t>(M), static_cast<int32_t>(N)});
     }
-    // tile lists per variant (longest first)
-    auto tiles_for = [&](int v, std::vector<TileDesc> *tl, std::vector<TileDesc> *tr,
+    // tile lists per variant, in XCD order (xcd) or longest tile first
+    auto tiles_for = [&](int v, bool xcd, std::vector<TileDesc> *tl, std::vector<TileDesc> *tr,
                          std::vector<int64_t> *cl, std::vector<int64_t> *cr) {
         const PairShape sh = pair_shape(S, G, v);
-        std::vector<TileWork> wl, wr;
+        std::vector<std::vector<TileWork>> wl(us.size()), wr(L->n_psi_blocks);
         for (size_t u = 0; u < us.size(); ++u) {
             const OutDesc &o = outsL[u];
-            for (int64_t m0 = 0; m0 < o.M; m0 += sh.bm)
-                for (int64_t n0 = 0; n0 < o.N; n0 += sh.bn)
-                    wl.push_back({TileDesc{static_cast<int32_t>(u), static_cast<int32_t>(u + 1), static_cast<int32_t>(m0),
-                                           static_cast<int32_t>(n0), static_cast<int32_t>(u), 0},
-                                  static_cast<int64_t>(termsL[u].kblocks) * sh.bm * sh.bn});
+            const int64_t c = static_cast<int64_t>(termsL[u].kblocks) * sh.bm * sh.bn;
+            walk_output(o.M, o.N, sh, [&](int64_t m0, int64_t n0) {
+                return TileWork{TileDesc{static_cast<int32_t>(u), static_cast<int32_t>(u + 1), static_cast<int32_t>(m0),
+                                         static_cast<int32_t>(n0), static_cast<int32_t>(u), 0}, c};
+            }, &wl[u]);
         }
         for (int b = 0; b < L->n_psi_blocks; ++b) {
             const OutDesc &o = outsR[b];
-            for (int64_t m0 = 0; m0 < o.M; m0 += sh.bm)
-                for (int64_t n0 = 0; n0 < o.N; n0 += sh.bn)
-                    wr.push_back({TileDesc{sigma_tb[b], sigma_te[b], static_cast<int32_t>(m0), static_cast<int32_t>(n0), b, 0},
-                                  (sigma_cost[b] + 1) * sh.bm * sh.bn});
+            const int64_t c = (sigma_cost[b] + 1) * sh.bm * sh.bn;
+            walk_output(o.M, o.N, sh, [&](int64_t m0, int64_t n0) {
+                return TileWork{TileDesc{sigma_tb[b], sigma_te[b], static_cast<int32_t>(m0), static_cast<int32_t>(n0), b, 0}, c};
+            }, &wr[b]);
         }
-        sort_tiles(wl, tl);
-        sort_tiles(wr, tr);
-        cl->clear();
-        cr->clear();
-        std::stable_sort(wl.begin(), wl.end(), [](const TileWork &a, const TileWork &b) { return a.cost > b.cost; });
-        std::stable_sort(wr.begin(), wr.end(), [](const TileWork &a, const TileWork &b) { return a.cost > b.cost; });
-        for (auto &w : wl) cl->push_back(w.cost);
-        for (auto &w : wr) cr->push_back(w.cost);
+        if (xcd) {
+            xcd_order(wl, tl, cl);
+            xcd_order(wr, tr, cr);
+        } else {
+            longest_first(wl, tl, cl);
+            longest_first(wr, tr, cr);
+        }
     };
     TermDesc *dmL, *dmR;
     OutDesc *doL, *doR;
@@ -469,13 +545,14 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
     for (int v = 0; v < pair_num_variants(); ++v)
         if (pair_variant_ok(G, v) && (fixed < 0 ? (ctx->autotune || v == pair_default_variant(G)) : v == fixed))
             cands.push_back(v);
-    // Autotuning: time each candidate on a prefix of its (longest-first) tile
-    // list, scaled by the prefix's share of the total cost; inputs are zeroed
-    // scratch (the timing does not depend on the values).
+    // Autotuning: time each candidate (tile variant and tile order) on a
+    // prefix of its tile list, scaled by the prefix's share of the total
+    // cost; inputs are zeroed scratch (the timing does not depend on the
+    // values).
     double bestL = -1, bestR = -1;
     void *tmp_sigma = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    const bool tuning = cands.size() > 1;
+    const bool tuning = cands.size() > 1 || ctx->autotune;
     if (tuning) {
         if ((e = hipMalloc(&tmp_sigma, sizeof(double) * std::max<int64_t>(n, 1))) != hipSuccess) { free_plan(P); return hip_fail(e, "heff_plan_create: tuning buffer"); }
         hipMemsetAsync(P->psi_p, 0, std::max<int64_t>(Ps.p_total, 256), s);
@@ -485,10 +562,16 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
         hipEventCreate(&ev0);
         hipEventCreate(&ev1);
     }
+    // candidates: tile variant x tile order (the XCD order first, the default)
+    std::vector<std::pair<int, bool>> runs;
     for (int v : cands) {
+        runs.push_back({v, true});
+        if (tuning) runs.push_back({v, false});
+    }
+    for (auto [v, xcd] : runs) {
         std::vector<TileDesc> tl, tr;
         std::vector<int64_t> cl, cr;
-        tiles_for(v, &tl, &tr, &cl, &cr);
+        tiles_for(v, xcd, &tl, &tr, &cl, &cr);
         TileDesc *dtl, *dtr;
         if ((rc = upload(P, tl, &dtl)) || (rc = upload(P, tr, &dtr))) { if (tmp_sigma) hipFree(tmp_sigma); free_plan(P); return rc; }
         if (!tuning) {

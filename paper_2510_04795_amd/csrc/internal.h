@@ -21,6 +21,10 @@ namespace oz {
 
 constexpr int kKB = 32;      // inner-dimension block of the packed layout
 constexpr int kRowQ = 32;    // row granularity of the packed layout
+// The pair kernels address one packed K block of an operand (2S runs of
+// rows_p 16-byte chunks) with 32-bit buffer offsets: rows_p is bounded so
+// that 2 * 8 * rows_p * 16 stays below 2^31.
+constexpr int64_t kMaxPackedRows = (INT32_MAX / (2 * 8 * 16)) / kRowQ * kRowQ;
 constexpr int32_t kExpBad = INT32_MIN;
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }

@@ -46,31 +46,39 @@ struct Cfg {
 
 // Direct-to-LDS loads of one packed K block: the stage holds 2S runs of BM
 // A rows then 2S runs of BN B rows; every wave issues 64-row segments (one
-// 16-byte chunk per lane).  The per-wave segment list is fixed for a term, so
-// it is computed once: a lane address at block 0, the per-block stride and
-// the LDS offset of each segment the wave owns.
+// 16-byte chunk per lane).  The loads are buffer loads with an LDS
+// destination: one buffer descriptor per operand and K block (scalar), and
+// per segment a fixed lane offset within the K block, so the per-lane
+// registers stay the same for the whole loop.
+constexpr int kBufferDword3 = 0x00020000;  // raw buffer, 32-bit data format
+
 template <int S, int G, int WM, int WN, int MB, int NB>
 struct LoadPlan {
     using C = Cfg<S, G, WM, WN, MB, NB>;
     static constexpr int NL = (C::SEGS + C::NW - 1) / C::NW;
-    const uint4 *src[NL];
-    int64_t stride[NL];
-    int lds_off[NL];
-    bool valid[NL];
+    const char *A, *B;
+    int a_kb_bytes, b_kb_bytes;  // bytes of one packed K block of each operand
+    int voff[NL];                // lane byte offset within the K block
+    int lds_off[NL];             // uint4 offset of the segment in a stage
+    bool valid[NL], isA[NL];     // uniform per wave
 
-    __device__ __forceinline__ void init(const uint4 *gA, const uint4 *gB, int64_t a_rows_p,
+    __device__ __forceinline__ void init(const void *gA, const void *gB, int64_t a_rows_p,
                                          int64_t b_rows_p, int m0, int n0, int wave, int lane) {
+        A = static_cast<const char *>(gA);
+        B = static_cast<const char *>(gB);
+        a_kb_bytes = static_cast<int>(2 * S * a_rows_p * 16);
+        b_kb_bytes = static_cast<int>(2 * S * b_rows_p * 16);
 #pragma unroll
         for (int i = 0; i < NL; ++i) {
             const int q = wave + C::NW * i;
             valid[i] = q < C::SEGS;
+            isA[i] = q < C::A_SEG;
             if (q < C::A_SEG) {
                 const int run = q / (C::BM / 64);
                 const int seg = q - run * (C::BM / 64);
                 int64_t row = m0 + seg * 64 + lane;
                 row = row < a_rows_p ? row : a_rows_p - 1;
-                src[i] = gA + run * a_rows_p + row;
-                stride[i] = 2 * S * a_rows_p;
+                voff[i] = static_cast<int>((run * a_rows_p + row) * 16);
                 lds_off[i] = run * C::BM + seg * 64;
             } else {
                 const int qb = (q < C::SEGS ? q : C::A_SEG) - C::A_SEG;
@@ -78,71 +86,121 @@ struct LoadPlan {
                 const int seg = qb - run * (C::BN / 64);
                 int64_t row = n0 + seg * 64 + lane;
                 row = row < b_rows_p ? row : b_rows_p - 1;
-                src[i] = gB + run * b_rows_p + row;
-                stride[i] = 2 * S * b_rows_p;
+                voff[i] = static_cast<int>((run * b_rows_p + row) * 16);
                 lds_off[i] = 2 * S * C::BM + run * C::BN + seg * 64;
             }
         }
     }
 
     __device__ __forceinline__ void issue(uint4 *stage, int kb) const {
+        const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<char *>(A + static_cast<int64_t>(kb) * a_kb_bytes), 0, a_kb_bytes, kBufferDword3);
+        const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<char *>(B + static_cast<int64_t>(kb) * b_kb_bytes), 0, b_kb_bytes, kBufferDword3);
 #pragma unroll
         for (int i = 0; i < NL; ++i)
             if (valid[i])
-                __builtin_amdgcn_global_load_lds(reinterpret_cast<const void *>(src[i] + kb * stride[i]),
-                                                 (lds_void *)(stage + lds_off[i]), 16, 0, 0);
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(isA[i] ? ra : rb, (lds_void *)(stage + lds_off[i]), 16,
+                                                         voff[i], 0, 0, 0);
     }
 };
 
-// All kept pair products of one LDS stage (one 32-wide K block).  The B
-// fragments of every kept slice stay in registers; A fragments are streamed
-// one slice at a time, the next slice's read issued before the current
-// slice's MFMAs so the LDS latency hides behind them.
-template <int S, int G, int WM, int WN, int MB, int NB>
-__device__ __forceinline__ void multiply_stage(v16i (&acc)[G][MB][NB], const uint4 *stage, int wm,
-                                               int wn, int half, int l32) {
+// Operand fragments of one stage for one wave: every slice that meets a
+// kept pair, for the wave's MB row blocks (A) and NB column blocks (B).
+// Each fragment is one 16-byte LDS read per lane (a 1 KiB run).
+template <int S, int G, int MB, int NB>
+struct Frags {
+    static constexpr int T = S < G ? S : G;  // slices that meet at least one kept pair
+    v4i a[T][MB];
+    v4i b[T][NB];
+};
+
+__device__ __forceinline__ v4i lds_frag(const uint4 *p) {
+    const uint4 v = *p;
+    return v4i{static_cast<int>(v.x), static_cast<int>(v.y), static_cast<int>(v.z), static_cast<int>(v.w)};
+}
+
+// All fragments of one stage, in the order the MFMAs consume them (A slice
+// 0 and every B slice, then A slices 1, 2, ...), so each MFMA waits only for
+// its own operands.
+template <int S, int G, int WM, int WN, int MB, int NB, typename F>
+__device__ __forceinline__ void read_stage(F &f, const uint4 *stage, int wm, int wn, int half, int l32) {
     using C = Cfg<S, G, WM, WN, MB, NB>;
-    constexpr int TB = S < G ? S : G;  // B slices that meet at least one kept pair
-    constexpr int SA = S < G ? S : G;  // A slices that meet at least one kept pair
     const uint4 *sA = stage;
     const uint4 *sB = stage + 2 * S * C::BM;
-    v4i bf[TB][NB];
 #pragma unroll
-    for (int t = 0; t < TB; ++t)
+    for (int mb = 0; mb < MB; ++mb) f.a[0][mb] = lds_frag(sA + half * C::BM + (wm * MB + mb) * 32 + l32);
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-            const uint4 v = sB[(t * 2 + half) * C::BN + (wn * NB + nb) * 32 + l32];
-            bf[t][nb] = v4i{static_cast<int>(v.x), static_cast<int>(v.y), static_cast<int>(v.z),
-                            static_cast<int>(v.w)};
-        }
-    v4i af[2][MB];
+    for (int t = 0; t < F::T; ++t)
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb) {
-        const uint4 v = sA[half * C::BM + (wm * MB + mb) * 32 + l32];
-        af[0][mb] = v4i{static_cast<int>(v.x), static_cast<int>(v.y), static_cast<int>(v.z),
-                        static_cast<int>(v.w)};
-    }
+        for (int nb = 0; nb < NB; ++nb)
+            f.b[t][nb] = lds_frag(sB + (t * 2 + half) * C::BN + (wn * NB + nb) * 32 + l32);
 #pragma unroll
-    for (int s = 0; s < SA; ++s) {
-        if (s + 1 < SA) {
+    for (int s = 1; s < F::T; ++s)
 #pragma unroll
-            for (int mb = 0; mb < MB; ++mb) {
-                const uint4 v = sA[((s + 1) * 2 + half) * C::BM + (wm * MB + mb) * 32 + l32];
-                af[(s + 1) & 1][mb] = v4i{static_cast<int>(v.x), static_cast<int>(v.y),
-                                          static_cast<int>(v.z), static_cast<int>(v.w)};
-            }
-        }
+        for (int mb = 0; mb < MB; ++mb)
+            f.a[s][mb] = lds_frag(sA + (s * 2 + half) * C::BM + (wm * MB + mb) * 32 + l32);
+}
+
+// Number of kept pairs (s, t), s + t < G, both below min(S, G).
+template <int S, int G>
+constexpr int kept_pairs() {
+    int n = 0;
+    for (int s = 0; s < S && s < G; ++s)
+        for (int t = 0; t < S && t < G; ++t)
+            if (s + t < G) ++n;
+    return n;
+}
+
+// Pairs of a stage deferred to the next one: they run while the next
+// stage's fragments are on their way from LDS.  A 2 x 2 block of pairs
+// ((0,0), (0,1), (1,0), (1,1)) needs only four fragments kept across the
+// stage boundary.
+template <int S, int G>
+__host__ __device__ constexpr bool deferred_pair(int s, int t) {
+    return kept_pairs<S, G>() >= 8 ? (s < 2 && t < 2) : (s == 0 && t == 0);
+}
+
+// The MFMAs of the kept pairs that are (DEFERRED) or are not (!DEFERRED)
+// deferred, slice-major ((0,0), (0,1), ..., (1,0), ...): consecutive MFMAs
+// feed different diagonals, and slice s of A is needed only once slice
+// s - 1 is done.
+template <bool DEFERRED, int S, int G, int MB, int NB, typename F>
+__device__ __forceinline__ void mfma_pairs(v16i (&acc)[G][MB][NB], const F &f) {
 #pragma unroll
-        for (int t = 0; t < TB; ++t) {
-            if (s + t >= G) continue;
+    for (int s = 0; s < F::T; ++s)
+#pragma unroll
+        for (int t = 0; t < F::T; ++t) {
+            if (s + t >= G || deferred_pair<S, G>(s, t) != DEFERRED) continue;
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb)
-                    acc[s + t][mb][nb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(
-                        af[s & 1][mb], bf[t][nb], acc[s + t][mb][nb], 0, 0, 0);
+                    acc[s + t][mb][nb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(f.a[s][mb], f.b[t][nb],
+                                                                               acc[s + t][mb][nb], 0, 0, 0);
         }
-    }
+}
+
+// One K block in LDS stage `cur`.  After the barrier (block kb complete in
+// `cur`, every wave done with `nxt`), all of its fragments are read, then
+// the loads of block kb + 1 into `nxt` are started, so no LDS read of this
+// wave is ever issued while a load into LDS is pending.  The deferred pairs
+// of block kb - 1 (fragments in f) run first, then this block's other
+// pairs; f then holds this block's fragments.
+template <int S, int G, int WM, int WN, int MB, int NB, typename F, typename LP>
+__device__ __forceinline__ void stage_step(v16i (&acc)[G][MB][NB], F &f, const uint4 *cur, uint4 *nxt,
+                                           const LP &lp, int kb, int nkb, int wm, int wn, int half,
+                                           int l32) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    F g;
+    read_stage<S, G, WM, WN, MB, NB>(g, cur, wm, wn, half, l32);
+    if (kb + 1 < nkb) lp.issue(nxt, kb + 1);
+    __builtin_amdgcn_sched_barrier(0);
+    mfma_pairs<true, S, G, MB, NB>(acc, f);
+    mfma_pairs<false, S, G, MB, NB>(acc, g);
+    __builtin_amdgcn_sched_barrier(0);
+    f = g;
 }
 
 // Exact diagonal sums of one tile for one term, accumulated over all K blocks.
@@ -156,8 +214,6 @@ __device__ __forceinline__ void pair_mainloop(v16i (&acc)[G][MB][NB], uint4 *lds
     const int wn = wave % WN;
     const int half = lane >> 5;
     const int l32 = lane & 31;
-    const uint4 *gA = reinterpret_cast<const uint4 *>(T.A);
-    const uint4 *gB = reinterpret_cast<const uint4 *>(T.B);
     const int nkb = T.kblocks;
 
 #pragma unroll
@@ -169,27 +225,30 @@ __device__ __forceinline__ void pair_mainloop(v16i (&acc)[G][MB][NB], uint4 *lds
     if (nkb == 0) return;
 
     LoadPlan<S, G, WM, WN, MB, NB> lp;
-    lp.init(gA, gB, T.a_rows_p, T.b_rows_p, m0, n0, wave, lane);
+    lp.init(T.A, T.B, T.a_rows_p, T.b_rows_p, m0, n0, wave, lane);
+    // a previous term of this block (accumulating mode) may still read the stages
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
     lp.issue(lds0, 0);
+    // no block before the first: its deferred pairs multiply zeros
+    Frags<S, G, MB, NB> f;
+#pragma unroll
+    for (int s = 0; s < Frags<S, G, MB, NB>::T; ++s) {
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) f.a[s][mb] = v4i{};
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) f.b[s][nb] = v4i{};
+    }
     // Blocks are taken two at a time (stage 0, stage 1) so each LDS stage is
     // its own object; the loop has a single exit and an odd last block is
     // peeled, which keeps the accumulators in place across iterations.
     int kb = 0;
     for (; kb + 2 <= nkb; kb += 2) {
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-        lp.issue(lds1, kb + 1);
-        multiply_stage<S, G, WM, WN, MB, NB>(acc, lds0, wm, wn, half, l32);
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-        if (kb + 2 < nkb) lp.issue(lds0, kb + 2);
-        multiply_stage<S, G, WM, WN, MB, NB>(acc, lds1, wm, wn, half, l32);
+        stage_step<S, G, WM, WN, MB, NB>(acc, f, lds0, lds1, lp, kb, nkb, wm, wn, half, l32);
+        stage_step<S, G, WM, WN, MB, NB>(acc, f, lds1, lds0, lp, kb + 1, nkb, wm, wn, half, l32);
     }
-    if (kb < nkb) {
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-        multiply_stage<S, G, WM, WN, MB, NB>(acc, lds0, wm, wn, half, l32);
-    }
+    if (kb < nkb) stage_step<S, G, WM, WN, MB, NB>(acc, f, lds0, lds1, lp, kb, nkb, wm, wn, half, l32);
+    mfma_pairs<true, S, G, MB, NB>(acc, f);
 }
 
 // FP64 value of one output element from its diagonal sums (plus int64 carries).
@@ -330,13 +389,14 @@ __global__ __launch_bounds__(64 * WM * WN) void k_pair_single(PairArgs a, int ti
                                           tn * C::BN, lds0, lds1);
 }
 
-// One block per listed tile (tiles are listed longest first).
+// One block per listed tile (the list is in the XCD order the plan builds).
 template <int S, int G, int WM, int WN, int MB, int NB, int MODE>
 __global__ __launch_bounds__(64 * WM * WN) void k_pair_grouped(PairArgs a) {
     using C = Cfg<S, G, WM, WN, MB, NB>;
     __shared__ uint4 lds0[C::STAGE];
     __shared__ uint4 lds1[C::STAGE];
     const TileDesc td = a.tiles[blockIdx.x];
+    if (td.out < 0) return;  // padding of the XCD order
     OutDesc od = a.outs[td.out];
     if (a.out_base) od.C = a.out_base + reinterpret_cast<intptr_t>(od.C);
     const TermDesc *terms = a.terms;

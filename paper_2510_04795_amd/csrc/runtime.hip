@@ -338,6 +338,8 @@ int ozaki_dgemm(ozaki_ctx ctx, char transa, char transb, int64_t M, int64_t N, i
     const int G = slices ? resolve_ndiag(slices, ndiag) : 0;
     if (slices && !valid_sg(slices, G))
         return fail(OZ_ERR_ARG, "ozaki_dgemm: ndiag = %d for slices = %d (use S, S+1 or 2S-1)", ndiag, slices);
+    if (slices && (round_up(M, kRowQ) > kMaxPackedRows || round_up(N, kRowQ) > kMaxPackedRows))
+        return fail(OZ_ERR_ARG, "ozaki_dgemm: M or N above %lld for the emulated path", (long long)kMaxPackedRows);
     if (M == 0 || N == 0) return OZ_OK;
     if (!C) return fail(OZ_ERR_ARG, "ozaki_dgemm: C is NULL");
     if (K > 0 && (!A || !B)) return fail(OZ_ERR_ARG, "ozaki_dgemm: A or B is NULL");
@@ -457,6 +459,8 @@ int ozaki_pair_products(ozaki_ctx ctx, int64_t M, int64_t N, int64_t K, int slic
     if (K > max_exact_k(slices, G))
         return fail(OZ_ERR_ARG, "ozaki_pair_products: K = %lld exceeds the exact int32 range %lld",
                     (long long)K, (long long)max_exact_k(slices, G));
+    if (round_up(M, kRowQ) > kMaxPackedRows || round_up(N, kRowQ) > kMaxPackedRows)
+        return fail(OZ_ERR_ARG, "ozaki_pair_products: M or N above %lld", (long long)kMaxPackedRows);
     if (M == 0 || N == 0) return OZ_OK;
     if (!Q || (K > 0 && (!Adig || !BTdig))) return fail(OZ_ERR_ARG, "ozaki_pair_products: NULL pointer");
     const int64_t Mp = round_up(M, kRowQ), Np = round_up(N, kRowQ), Kp = round_up(K, kKB);
