@@ -366,7 +366,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--err-rows", type=int, default=16)
-    ap.add_argument("--cpu-rows", type=int, default=96)
+    ap.add_argument("--cpu-rows", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--sections", default="gemm,dense,sparse,davidson,sweep",
                     help="comma list of gemm, dense, sparse, davidson, sweep (the GEMM section always runs)")
