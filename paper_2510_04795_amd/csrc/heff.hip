@@ -96,8 +96,9 @@ void free_plan(heff_plan p) {
     delete p;
 }
 
-// Slice descriptors for a list of blocks: exponent tasks (4 rows or 256
-// columns each) and slice tasks (32 groups x one 32-wide K block each).
+// Slice descriptors for a list of blocks: exponent tasks (kExpTaskRows rows
+// or kExpTaskCols columns each) and slice tasks (32 groups x kSliceTaskKB
+// 32-wide K blocks each).
 struct SliceSet {
     std::vector<SliceBlock> blocks;
     std::vector<SliceTask> etasks, stasks;
@@ -120,9 +121,9 @@ struct SliceSet {
         p_total += align256(static_cast<size_t>(S) * b.Rp * round_up(K, kKB));
         const int id = static_cast<int>(blocks.size());
         blocks.push_back(b);
-        const int step = trans ? 256 : 4;
+        const int step = trans ? kExpTaskCols : kExpTaskRows;
         for (int64_t g = 0; g < R; g += step) etasks.push_back(SliceTask{id, static_cast<int32_t>(g), 0, 0});
-        for (int64_t kb = 0; kb < ceil_div(K, kKB); ++kb)
+        for (int64_t kb = 0; kb < ceil_div(K, kKB); kb += kSliceTaskKB)
             for (int64_t r0 = 0; r0 < b.Rp; r0 += 32)
                 stasks.push_back(SliceTask{id, static_cast<int32_t>(r0), static_cast<int32_t>(kb), 0});
         return id;

@@ -123,6 +123,12 @@ struct SliceBlock {
     int64_t p_off;   // byte offset of the packed planes from the packed base
     int64_t Rp;      // padded group count of the packed planes
 };
+// Work per task of the grouped exponent and slice launches: 16 rows or 64
+// columns per exponent task, 32 groups x 8 K blocks per slice task.
+constexpr int kExpTaskRows = 16;
+constexpr int kExpTaskCols = 64;
+constexpr int kSliceTaskKB = 8;
+
 struct SliceTask {
     int32_t block;
     int32_t a;       // exponent task: first group; slice task: first group (32-aligned)

@@ -161,34 +161,70 @@ hipError_t slice_s(bool trans, const double *X, int64_t ld, int64_t R, int64_t K
 }
 
 // ---- grouped versions: one launch for a list of blocks -------------------
+// Row groups (trans = 0): 16 rows per task, four per wave, the loads of the
+// four rows interleaved so each lane keeps several in flight.
+// Column groups (trans = 1): 64 columns per task, one per lane; the four
+// waves take every fourth row of the block, eight loads in flight per lane,
+// and combine their maxima through LDS.  The maximum is order independent
+// (NaN wins), so the split does not change the exponents.
+
 __global__ __launch_bounds__(256) void k_exponents_grouped(const SliceBlock *__restrict__ blocks,
                                                             const SliceTask *__restrict__ tasks,
                                                             const double *__restrict__ x_base,
                                                             int32_t *__restrict__ e_base,
                                                             uint32_t *flag) {
+    __shared__ double part[4][kExpTaskCols];
     const SliceTask tk = tasks[blockIdx.x];
     const SliceBlock bl = blocks[tk.block];
     const double *X = x_base + bl.x_off;
     int32_t *e = e_base + bl.e_off;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
     if (bl.trans == 0) {
-        // four rows, one wave each
-        const int lane = threadIdx.x & 63;
-        const int r = tk.a + (threadIdx.x >> 6);
-        if (r >= bl.R) return;
-        const double *row = X + static_cast<int64_t>(r) * bl.ld;
-        double mu = 0.0;
-        for (int k = lane; k < bl.K; k += 64) mu = combine_max(mu, abs_or_nan(row[k]));
-        for (int off = 32; off >= 1; off >>= 1) mu = combine_max(mu, __shfl_xor(mu, off, 64));
-        if (lane == 0) e[r] = finish_exponent(mu, flag);
+        const int r0 = tk.a + wave * 4;
+        double mu[4] = {0.0, 0.0, 0.0, 0.0};
+        const double *row[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) row[j] = X + static_cast<int64_t>(r0 + j < bl.R ? r0 + j : 0) * bl.ld;
+        for (int k = lane; k < bl.K; k += 64) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (r0 + j < bl.R) mu[j] = combine_max(mu[j], abs_or_nan(row[j][k]));
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            double m = mu[j];
+            for (int off = 32; off >= 1; off >>= 1) m = combine_max(m, __shfl_xor(m, off, 64));
+            if (lane == 0 && r0 + j < bl.R) e[r0 + j] = finish_exponent(m, flag);
+        }
     } else {
-        // 256 columns, one thread each, over all K rows
-        const int c = tk.a + threadIdx.x;
-        if (c >= bl.R) return;
-        double mu = 0.0;
-        for (int k = 0; k < bl.K; ++k) mu = combine_max(mu, abs_or_nan(X[static_cast<int64_t>(k) * bl.ld + c]));
-        e[c] = finish_exponent(mu, flag);
+        const int c = tk.a + lane;
+        const bool cok = c < bl.R;
+        const double *col = X + (cok ? c : 0);
+        double m8[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) m8[u] = 0.0;
+        int k = wave;
+        for (; k + 28 < bl.K; k += 32) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                m8[u] = combine_max(m8[u], cok ? abs_or_nan(col[static_cast<int64_t>(k + 4 * u) * bl.ld]) : 0.0);
+        }
+        for (; k < bl.K; k += 4) m8[0] = combine_max(m8[0], cok ? abs_or_nan(col[static_cast<int64_t>(k) * bl.ld]) : 0.0);
+        double mu = m8[0];
+#pragma unroll
+        for (int u = 1; u < 8; ++u) mu = combine_max(mu, m8[u]);
+        part[wave][lane] = mu;
+        __syncthreads();
+        if (wave == 0) {
+            mu = combine_max(combine_max(part[0][lane], part[1][lane]), combine_max(part[2][lane], part[3][lane]));
+            if (cok) e[c] = finish_exponent(mu, flag);
+        }
     }
 }
+
+// One task: 32 groups x up to kSliceTaskKB consecutive 32-wide K blocks; the
+// elements of the next K block are loaded while the current one is sliced.
 
 template <int S>
 __global__ __launch_bounds__(256) void k_slice_grouped(const SliceBlock *__restrict__ blocks,
@@ -203,8 +239,6 @@ __global__ __launch_bounds__(256) void k_slice_grouped(const SliceBlock *__restr
     const int32_t *e = e_base + bl.e_off;
     const int t = threadIdx.x;
     const int64_t r0 = tk.a;
-    const int64_t kb = tk.b;
-    const int64_t k0 = kb * 32;
     int r, kq;
     if (bl.trans) {
         r = t & 31;
@@ -214,26 +248,37 @@ __global__ __launch_bounds__(256) void k_slice_grouped(const SliceBlock *__restr
         kq = t & 7;
     }
     const int64_t gr = r0 + r;
-    double x[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int64_t k = k0 + kq * 4 + q;
-        x[q] = 0.0;
-        if (gr < bl.R && k < bl.K) x[q] = bl.trans ? X[k * bl.ld + gr] : X[gr * bl.ld + k];
-    }
     const int32_t ee = gr < bl.R ? e[gr] : 0;
-    uint32_t w[S];
-    slice4<S>(x, ee, w);
+    const int nkb = (bl.K + kKB - 1) / kKB;
+    const int kb_end = tk.b + kSliceTaskKB < nkb ? tk.b + kSliceTaskKB : nkb;
+    auto load = [&](int kb, double (&x)[4]) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t k = static_cast<int64_t>(kb) * 32 + kq * 4 + q;
+            x[q] = 0.0;
+            if (gr < bl.R && k < bl.K) x[q] = bl.trans ? X[k * bl.ld + gr] : X[gr * bl.ld + k];
+        }
+    };
+    double x[4], nx[4];
+    load(tk.b, x);
+    uint4 *out = reinterpret_cast<uint4 *>(p_base + bl.p_off);
     const int c = kq >> 2;
     const int word = kq & 3;
+    for (int kb = tk.b; kb < kb_end; ++kb) {
+        if (kb + 1 < kb_end) load(kb + 1, nx);
+        uint32_t w[S];
+        slice4<S>(x, ee, w);
 #pragma unroll
-    for (int s = 0; s < S; ++s) reinterpret_cast<uint32_t *>(&tile[s * 2 + c][r])[word] = w[s];
-    __syncthreads();
-    uint4 *out = reinterpret_cast<uint4 *>(p_base + bl.p_off);
-    for (int q = t; q < S * 2 * 32; q += 256) {
-        const int sc = q >> 5;
-        const int rr = q & 31;
-        out[(kb * S * 2 + sc) * bl.Rp + r0 + rr] = tile[sc][rr];
+        for (int s = 0; s < S; ++s) reinterpret_cast<uint32_t *>(&tile[s * 2 + c][r])[word] = w[s];
+        __syncthreads();
+        for (int q = t; q < S * 2 * 32; q += 256) {
+            const int sc = q >> 5;
+            const int rr = q & 31;
+            out[(static_cast<int64_t>(kb) * S * 2 + sc) * bl.Rp + r0 + rr] = tile[sc][rr];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) x[q] = nx[q];
     }
 }
 
