@@ -348,7 +348,15 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
     P->T = static_cast<double *>(mem);
 
     if (S == 0) {
-        const PairShape sh = dgemm_shape();
+        // tile edge per phase: 128, or 64 when the 128 tiles would not give
+        // every compute unit two workgroups
+        int64_t nL = 0, nR = 0;
+        for (size_t u = 0; u < us.size(); ++u)
+            nL += ceil_div(ld[us[u].lo], 128) * ceil_div(p * rd[us[u].ri], 128);
+        for (int b = 0; b < L->n_psi_blocks; ++b)
+            nR += ceil_div(ld[L->psi_lr[2 * b]] * p, 128) * ceil_div(rd[L->psi_lr[2 * b + 1]], 128);
+        const int bmL = dgemm_tile_for(nL, ctx->num_cu), bmR = dgemm_tile_for(nR, ctx->num_cu);
+        const PairShape sh{bmL, bmL}, shR{bmR, bmR};
         // first product: T_u = L Psi  (op(B) = B, B offsets relative to psi)
         std::vector<Term64> termsL;
         std::vector<OutDesc> outsL;
@@ -394,7 +402,7 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
             const int te = static_cast<int>(termsR.size());
             outsR.push_back(OutDesc{reinterpret_cast<double *>(static_cast<intptr_t>(L->psi_offset[b])), N,
                                     static_cast<int32_t>(M), static_cast<int32_t>(N)});
-            walk_output(M, N, sh, [&](int64_t m0, int64_t n0) {
+            walk_output(M, N, shR, [&](int64_t m0, int64_t n0) {
                 return TileWork{TileDesc{tb, te, static_cast<int32_t>(m0), static_cast<int32_t>(n0), b, 0}, cost + 1};
             }, &wr[b]);
         }
@@ -409,10 +417,12 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
         P->d64L.tiles = dt; P->d64L.terms = dm; P->d64L.outs = dout;
         P->d64L.ntiles = static_cast<int32_t>(tl.size());
         P->d64L.mode = kModeGemm;
+        P->d64L.tile = bmL;
         if ((rc = upload(P, tr, &dt)) || (rc = upload(P, termsR, &dm)) || (rc = upload(P, outsR, &dout))) { free_plan(P); return rc; }
         P->d64R.tiles = dt; P->d64R.terms = dm; P->d64R.outs = dout;
         P->d64R.ntiles = static_cast<int32_t>(tr.size());
         P->d64R.mode = kModeAccum;
+        P->d64R.tile = bmR;
         *out = P;
         return OZ_OK;
     }
@@ -629,12 +639,12 @@ int enqueue_apply(heff_plan P, const double *psi, double *sigma, hipStream_t s) 
         hipEvent_t t0 = mark(ctx, s);
         Dgemm64Args a = P->d64L;
         a.b_base = psi;
-        if ((e = launch_dgemm_grouped(false, a, a.ntiles, s)) != hipSuccess) return hip_fail(e, "heff_apply: first product");
+        if ((e = launch_dgemm_grouped(false, a, s)) != hipSuccess) return hip_fail(e, "heff_apply: first product");
         hipEvent_t t1 = mark(ctx, s);
         phase(ctx, OZ_PHASE_HEFF_L, t0, t1);
         Dgemm64Args b = P->d64R;
         b.out_base = sigma;
-        if ((e = launch_dgemm_grouped(true, b, b.ntiles, s)) != hipSuccess) return hip_fail(e, "heff_apply: second product");
+        if ((e = launch_dgemm_grouped(true, b, s)) != hipSuccess) return hip_fail(e, "heff_apply: second product");
         hipEvent_t t2 = mark(ctx, s);
         phase(ctx, OZ_PHASE_HEFF_R, t1, t2);
     } else {

@@ -105,7 +105,7 @@ struct Dgemm64Args {
     Term64 term;
     OutDesc out;
     int32_t mode;          // kModeGemm or kModeAccum
-    int32_t pad_;
+    int32_t tile;          // grouped: edge of the listed tiles (64 or 128, see dgemm_tile_for)
     double beta;
     double *out_base;      // grouped: when set, OutDesc::C holds an element offset from it
     const double *b_base;  // grouped: when set, Term64::B holds an element offset from it
@@ -149,8 +149,8 @@ hipError_t launch_col_exponents(const double *X, int64_t ld, int64_t K, int64_t 
 // trans = true: X is K x R (groups are columns).  Pads rows to Rp, K to Kp with 0.
 hipError_t launch_slice(int S, bool trans, const double *X, int64_t ld, int64_t R, int64_t K,
                         const int32_t *e, int8_t *packed, int64_t Rp, hipStream_t s);
-// Grouped exponent pass (tasks of 4 rows or 256 columns) and slice pass
-// (tasks of 32 groups x one 32-wide K block).
+// Grouped exponent pass (tasks of kExpTaskRows rows or kExpTaskCols columns)
+// and slice pass (tasks of 32 groups x kSliceTaskKB 32-wide K blocks).
 hipError_t launch_exponents_grouped(const SliceBlock *blocks, const SliceTask *tasks, int ntasks,
                                     const double *x_base, int32_t *e_base, uint32_t *flag,
                                     hipStream_t s);
@@ -173,11 +173,13 @@ PairShape pair_shape(int S, int G, int v);
 hipError_t launch_pair_single(int S, int G, int v, const PairArgs &a, int tiles_m, hipStream_t s);
 hipError_t launch_pair_grouped(int S, int G, int v, const PairArgs &a, hipStream_t s);
 
-// FP64 MFMA GEMM.
-PairShape dgemm_shape();
-hipError_t launch_dgemm_single(bool ta, bool tb, const Dgemm64Args &a, int tiles_m,
-                               hipStream_t s);
-hipError_t launch_dgemm_grouped(bool tb, const Dgemm64Args &a, int grid, hipStream_t s);
+// FP64 MFMA GEMM.  The single launch picks its tile size from the output
+// extent (a.out) and the compute-unit count; the grouped launch takes tiles
+// of edge a.tile (64 or 128), one workgroup per listed tile.
+// dgemm_tile_for: the edge for a set of outputs with `tiles128` tiles of 128.
+int dgemm_tile_for(int64_t tiles128, int num_cu);
+hipError_t launch_dgemm_single(bool ta, bool tb, const Dgemm64Args &a, int num_cu, hipStream_t s);
+hipError_t launch_dgemm_grouped(bool tb, const Dgemm64Args &a, hipStream_t s);
 
 // sigma[i] = sigma[i] + diag[i] * psi[i] (two roundings), i < n.
 hipError_t launch_diag_axpy(const double *diag, const double *psi, double *sigma, int64_t n,

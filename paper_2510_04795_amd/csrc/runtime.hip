@@ -349,14 +349,12 @@ int ozaki_dgemm(ozaki_ctx ctx, char transa, char transb, int64_t M, int64_t N, i
 
     if (slices == 0) {
         hipEvent_t t0 = mark(ctx, s);
-        const PairShape sh = dgemm_shape();
         Dgemm64Args a{};
-        a.tiles_n = static_cast<int32_t>(ceil_div(N, sh.bn));
         a.term = Term64{A, B, lda, ldb, static_cast<int32_t>(K), 0, alpha};
         a.out = OutDesc{C, ldc, static_cast<int32_t>(M), static_cast<int32_t>(N)};
         a.mode = kModeGemm;
         a.beta = beta;
-        e = launch_dgemm_single(ta, tb, a, static_cast<int>(ceil_div(M, sh.bm)), s);
+        e = launch_dgemm_single(ta, tb, a, ctx->num_cu, s);
         phase(ctx, OZ_PHASE_FP64, t0, mark(ctx, s));
         return e == hipSuccess ? OZ_OK : hip_fail(e, "ozaki_dgemm (fp64) launch");
     }

@@ -189,6 +189,32 @@ def test_fp64_mfma_within_gamma_bound(oz, transa, transb):
     assert np.all(err <= gam * (np.abs(A) @ np.abs(B)) * (1 + 1e-12))
 
 
+@pytest.mark.parametrize("transa,transb", [("N", "N"), ("T", "N"), ("N", "T"), ("T", "T")])
+def test_fp64_mfma_large_tiles_within_gamma_bound(oz, transa, transb):
+    """An extent large enough for the 128 x 128 FP64 tiles (ragged in every
+    dimension, alpha and beta), sampled rows against the double-double sum."""
+    ozaki, ctx, torch = oz
+    rng = np.random.default_rng(12)
+    M, N, K = 3001, 2950, 333
+    A = wl.wide_normal(rng, (M, K), 10)
+    B = wl.wide_normal(rng, (K, N), 10)
+    C0 = rng.standard_normal((M, N))
+    As = A.T.copy() if transa == "T" else A
+    Bs = B.T.copy() if transb == "T" else B
+    C = dev(torch, C0)
+    ctx.dgemm(dev(torch, As), dev(torch, Bs), slices=0, transa=transa, transb=transb,
+              alpha=-1.5, beta=0.5, C=C)
+    rows = np.array([0, 127, 128, 1500, 2999, 3000])
+    got = C.cpu().numpy()[rows]
+    hi, lo = oracle.dgemm_dd(A[rows], B)
+    u = 2.0 ** -53
+    gam = (K + 2) * u / (1 - (K + 2) * u)
+    ref = -1.5 * hi + 0.5 * C0[rows]
+    mag = 1.5 * (np.abs(A[rows]) @ np.abs(B)) + 0.5 * np.abs(C0[rows])
+    err = np.abs(got - ref - (-1.5 * lo))
+    assert np.all(err <= gam * mag * (1 + 1e-12) + 4 * u * np.abs(ref))
+
+
 def test_dgemm_full_size_sampled_rows(oz):
     """n = 8192, S = 6: the launch the benchmark times, checked on sampled rows
     (exponents are per row of A and per column of B, so rows are independent)."""

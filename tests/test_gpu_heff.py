@@ -80,6 +80,20 @@ def test_dense_fp64_within_bound(oz):
     assert np.all(np.abs(sig - ref) <= 2 * fp64_bound(L, R, psi, 90, 90))
 
 
+def test_dense_fp64_large_tiles_within_bound(oz):
+    """FP64 plan with enough first-product tiles for the 128 x 128 tiles and
+    a second product on 64 x 64 tiles; sampled rows against the oracle's FP64
+    rows, within the chained gamma bound."""
+    ozaki, ctx, torch = oz
+    L, R, psi = wl.heff_dense(D=512, kop=8, phys=4, seed=7)
+    plan, dpsi, keep = dense_plan(ozaki, ctx, torch, L, R, psi, 0)
+    sig = plan.apply(dpsi).reshape(psi.shape).cpu().numpy()
+    rows = [0, 255, 511]
+    ref = oracle.heff_dense_rows(L, R, psi, rows, S=0)
+    bound = fp64_bound(L, R, psi, 512, 512)[rows]
+    assert np.all(np.abs(sig[rows] - ref) <= 2 * bound)
+
+
 def test_dense_d256_full(oz):
     """D = 256, phys 16: several tiles in every direction, all rows checked."""
     ozaki, ctx, torch = oz
