@@ -133,6 +133,51 @@ int ozaki_dgemm(ozaki_ctx ctx, char transa, char transb, int64_t M, int64_t N, i
                 double beta, double *C, int64_t ldc, int slices, int ndiag,
                 void *workspace, size_t workspace_bytes, void *stream);
 
+/* ---- emulation modes: mantissa width, automatic width, dispatch ------ */
+/* The paper's library lets the user give the mantissa width, or finds the
+ * width that keeps native FP64 accuracy itself, and uses emulation eagerly
+ * or only where it is faster ("Numerical procedure"; the rules there belong
+ * to a vendor library and are not published).  This library's rules:
+ *
+ * ozaki_choose_slices: statistics of the operands (one exponent pass and one
+ *  sum-of-squares pass over each, copied to the host: synchronises `stream`)
+ *  give rho_A = root mean square over the rows i of op(A) of
+ *  2^e_i / rms(row i), and rho_B over the columns of op(B).  Predicted
+ *  relative Frobenius errors:
+ *    emulated(S, G) = 0.75 2^-8S [ (rho_A + rho_B) / sqrt(3)
+ *                               + sqrt(n_G) (65536 / 12 / 2^14) rho_A rho_B 2^-8(G-S) ]
+ *    native(K)      = 0.3 2^-53 sqrt(K)
+ *  (n_G: slice pairs on the first dropped diagonal; the factors 0.75 and
+ *  0.3 fitted to measured errors).  Chosen: the (S, G), S in [2, 8],
+ *  G in {S, S + 1}, with the fewest slice pairs whose prediction is no larger
+ *  than native(K); (8, 9) if none; (2, 2) if an operand is all zeros; (7, 7)
+ *  if an operand holds NaN/Inf.
+ *  stats_out (nullable, host, 4 doubles): rho_A, rho_B, emulated(S, G),
+ *  native(K).  workspace: ozaki_dgemm_auto_workspace_bytes(M, N, K) bytes. */
+int ozaki_choose_slices(ozaki_ctx ctx, char transa, char transb, int64_t M, int64_t N, int64_t K,
+                        const double *A, int64_t lda, const double *B, int64_t ldb, void *workspace,
+                        size_t workspace_bytes, void *stream, int32_t *slices_out, int32_t *ndiag_out,
+                        double *stats_out);
+/* Workspace of ozaki_dgemm_auto and ozaki_choose_slices (covers every (S, G)
+ * the automatic choice can return). */
+size_t ozaki_dgemm_auto_workspace_bytes(int64_t M, int64_t N, int64_t K);
+/* C = alpha op(A) op(B) + beta C with the width and path chosen here:
+ *  bits > 0: S = ozaki_slices_for_bits(bits) clamped to [2, 8], ndiag = S;
+ *  bits = 0: (S, G) from ozaki_choose_slices (synchronises).
+ *  performant = 0 (eager): the emulated GEMM with that (S, G).
+ *  performant = 1: the first call of a (transa, transb, M, N, K, S, G) with
+ *   beta = 0 runs the native FP64 and the emulated GEMM once each into C,
+ *   timed (synchronises), keeps the faster for this context and then computes
+ *   C with it; later calls of that shape use the kept path; a shape not yet
+ *   timed (first seen with beta != 0) uses the emulated path.
+ *  slices_out, ndiag_out (nullable, host): the path taken (0, 0: native FP64).
+ *  Results are those of ozaki_dgemm with that (slices, ndiag).  Errors as for
+ *  ozaki_dgemm; OZ_ERR_ARG for bits < 0 or performant not 0 / 1. */
+int ozaki_dgemm_auto(ozaki_ctx ctx, char transa, char transb, int64_t M, int64_t N, int64_t K,
+                     double alpha, const double *A, int64_t lda, const double *B, int64_t ldb,
+                     double beta, double *C, int64_t ldc, int bits, int performant, void *workspace,
+                     size_t workspace_bytes, void *stream, int32_t *slices_out, int32_t *ndiag_out);
+
 /* ---- tile variants and autotuning ------------------------------------ */
 /* The int8 pair GEMM is built in several tile variants per (S, G) (waves of
  * MB x NB blocks of 32 x 32 outputs).  Every variant gives bit-identical

@@ -208,6 +208,64 @@ def gemm(A, B, S: int = 0, G: int | None = None, **kw) -> np.ndarray:
 
 
 # ----------------------------------------------------------------------------
+# Automatic slice count (a reading of the library behaviour the paper names in
+# "Numerical procedure" without giving its rule; the rule is this build's own:
+# predicted relative Frobenius errors of the emulated and of a native FP64
+# product, the cheapest (S, G) whose prediction is no larger than native)
+# ----------------------------------------------------------------------------
+def _pairs_on_diagonal(S: int, g: int) -> int:
+    return sum(1 for s in range(S) if 0 <= g - s < S)
+
+
+def rho(X, by_columns: bool = False) -> float:
+    """Root mean square over the groups (rows, or columns) of 2^e / rms(group),
+    e the shared exponent of the group; groups of zeros are left out; NaN when
+    a group holds NaN/Inf."""
+    X = _f64(X)
+    _, e, bad = split(X, 2, by_columns=by_columns)
+    if bad.any():
+        return float("nan")
+    ss = np.sum(X * X, axis=0 if by_columns else 1)
+    K = X.shape[0] if by_columns else X.shape[1]
+    keep = ss > 0
+    if not keep.any():
+        return 0.0
+    r = np.exp2(2.0 * e[keep] - np.log2(ss[keep]) + np.log2(float(K)))
+    return float(np.sqrt(np.mean(r)))
+
+
+def predicted_emulated_error(S: int, G: int, rho_a: float, rho_b: float) -> float:
+    """Operand rounding (uniform in half a grid step) plus the first dropped
+    diagonal (digit variance 256^2 / 12), times the fitted factor 0.75."""
+    rep = (rho_a + rho_b) / np.sqrt(3.0)
+    trunc = np.sqrt(_pairs_on_diagonal(S, G)) * (65536.0 / 12.0 / 16384.0) * rho_a * rho_b * 2.0 ** (-8 * (G - S))
+    return 0.75 * 2.0 ** (-8 * S) * (rep + trunc)
+
+
+def predicted_native_error(K: int) -> float:
+    return 0.3 * 2.0 ** -53 * np.sqrt(max(K, 1))
+
+
+def choose_slices(A, B):
+    """(S, G) of the automatic choice for the product A B (both as stored)."""
+    ra, rb = rho(A), rho(B, by_columns=True)
+    if not (np.isfinite(ra) and np.isfinite(rb)):
+        return 7, 7
+    if ra == 0.0 or rb == 0.0:
+        return 2, 2          # an operand of zeros: the product is exactly zero
+    target = predicted_native_error(A.shape[1])
+    best = None
+    for S in range(2, 9):
+        for G in (S, S + 1):
+            if predicted_emulated_error(S, G, ra, rb) > target:
+                continue
+            P = pair_count(S, G)
+            if best is None or P < best[0]:
+                best = (P, S, G)
+    return (best[1], best[2]) if best else (8, 9)
+
+
+# ----------------------------------------------------------------------------
 # Error metrics and the a-priori bound
 # ----------------------------------------------------------------------------
 def rel_frobenius(C, hi, lo) -> float:

@@ -145,6 +145,10 @@ hipError_t launch_row_exponents(const double *X, int64_t ld, int64_t R, int64_t 
 size_t col_exponent_scratch(int64_t K, int64_t R);
 hipError_t launch_col_exponents(const double *X, int64_t ld, int64_t K, int64_t R, int32_t *e,
                                 double *part, uint32_t *flag, hipStream_t s);
+// Sum of squares of each group: rows of X (R x K) when by_rows, else columns
+// of X (K x R, part: col_exponent_scratch(K, R) bytes).
+hipError_t launch_group_sumsq(bool by_rows, const double *X, int64_t ld, int64_t R, int64_t K, double *ss,
+                              double *part, hipStream_t s);
 // Slice X into the packed layout.  trans = false: X is R x K (groups are rows);
 // trans = true: X is K x R (groups are columns).  Pads rows to Rp, K to Kp with 0.
 hipError_t launch_slice(int S, bool trans, const double *X, int64_t ld, int64_t R, int64_t K,

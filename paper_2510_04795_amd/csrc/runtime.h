@@ -7,6 +7,8 @@
 #include "../../include/ozaki.h"
 #include "internal.h"
 
+#include <array>
+#include <map>
 #include <vector>
 
 struct ozaki_ctx_s {
@@ -24,6 +26,8 @@ struct ozaki_ctx_s {
     size_t next_event = 0;
     struct Rec { int phase; hipEvent_t a, b; };
     std::vector<Rec> recs;
+    // performant dispatch: (transa, transb, M, N, K, S, G) -> 1 emulated, 0 native
+    std::map<std::array<int64_t, 7>, int> dispatch;
 };
 
 namespace oz {

@@ -83,6 +83,44 @@ __global__ __launch_bounds__(256) void k_col_final(const double *__restrict__ pa
     e[c] = finish_exponent(mu, flag);
 }
 
+// Sums of squares per group (statistics of the automatic slice count).
+// Rows: one wave per row, lanes stride the row, fixed shuffle tree.
+__global__ __launch_bounds__(256) void k_row_sumsq(const double *__restrict__ X, int64_t ld, int64_t R,
+                                                    int64_t K, double *__restrict__ ss) {
+    const int lane = threadIdx.x & 63;
+    const int64_t r = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (r >= R) return;
+    const double *row = X + r * ld;
+    double acc = 0.0;
+    for (int64_t k = lane; k < K; k += 64) acc = fma(row[k], row[k], acc);
+    for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) ss[r] = acc;
+}
+
+// Columns of X (K x R): partial sums over row chunks, then the chunks in order.
+__global__ __launch_bounds__(256) void k_col_sumsq_partial(const double *__restrict__ X, int64_t ld,
+                                                            int64_t K, int64_t R, double *__restrict__ part) {
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (c >= R) return;
+    const int64_t k0 = static_cast<int64_t>(blockIdx.y) * kColChunk;
+    const int64_t k1 = k0 + kColChunk < K ? k0 + kColChunk : K;
+    double acc = 0.0;
+    for (int64_t k = k0; k < k1; ++k) {
+        const double x = X[k * ld + c];
+        acc = fma(x, x, acc);
+    }
+    part[static_cast<int64_t>(blockIdx.y) * R + c] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_col_sumsq_final(const double *__restrict__ part, int64_t nchunk,
+                                                          int64_t R, double *__restrict__ ss) {
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (c >= R) return;
+    double acc = 0.0;
+    for (int64_t q = 0; q < nchunk; ++q) acc += part[q * R + c];
+    ss[c] = acc;
+}
+
 // Balanced base-256 digits of RNE(x 2^(8S-1-e)), most significant first, as
 // bytes of four consecutive elements packed into one word per slice.
 template <int S>
@@ -348,6 +386,23 @@ hipError_t launch_col_exponents(const double *X, int64_t ld, int64_t K, int64_t 
     }
     hipLaunchKernelGGL(k_col_final, dim3(static_cast<unsigned>(ceil_div(R, 256))), dim3(256), 0, s,
                        part, nchunk, R, e, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_sumsq(bool by_rows, const double *X, int64_t ld, int64_t R, int64_t K, double *ss,
+                              double *part, hipStream_t s) {
+    if (R == 0) return hipSuccess;
+    if (by_rows) {
+        hipLaunchKernelGGL(k_row_sumsq, dim3(static_cast<unsigned>(ceil_div(R, 4))), dim3(256), 0, s, X, ld, R, K, ss);
+        return hipGetLastError();
+    }
+    const int64_t nchunk = ceil_div(K, kColChunk);
+    if (nchunk > 0)
+        hipLaunchKernelGGL(k_col_sumsq_partial,
+                           dim3(static_cast<unsigned>(ceil_div(R, 256)), static_cast<unsigned>(nchunk)), dim3(256), 0, s,
+                           X, ld, K, R, part);
+    hipLaunchKernelGGL(k_col_sumsq_final, dim3(static_cast<unsigned>(ceil_div(R, 256))), dim3(256), 0, s, part, nchunk,
+                       R, ss);
     return hipGetLastError();
 }
 

@@ -76,6 +76,11 @@ _sig("ozaki_max_exact_k", _i64, [_i32, _i32])
 _sig("ozaki_dgemm_workspace_bytes", _sz, [_i64, _i64, _i64, _i32, _i32])
 _sig("ozaki_dgemm", _i32, [_ptr, ctypes.c_char, ctypes.c_char, _i64, _i64, _i64, _dbl, _ptr, _i64,
                            _ptr, _i64, _dbl, _ptr, _i64, _i32, _i32, _ptr, _sz, _ptr])
+_sig("ozaki_dgemm_auto_workspace_bytes", _sz, [_i64, _i64, _i64])
+_sig("ozaki_choose_slices", _i32, [_ptr, ctypes.c_char, ctypes.c_char, _i64, _i64, _i64, _ptr, _i64, _ptr,
+                                   _i64, _ptr, _sz, _ptr, _ptr, _ptr, _ptr])
+_sig("ozaki_dgemm_auto", _i32, [_ptr, ctypes.c_char, ctypes.c_char, _i64, _i64, _i64, _dbl, _ptr, _i64,
+                                _ptr, _i64, _dbl, _ptr, _i64, _i32, _i32, _ptr, _sz, _ptr, _ptr, _ptr])
 _sig("ozaki_split", _i32, [_ptr, _i32, _i64, _i64, _ptr, _i64, _i32, _ptr, _ptr, _ptr])
 _sig("ozaki_pair_products", _i32, [_ptr, _i64, _i64, _i64, _i32, _i32, _ptr, _ptr, _ptr, _ptr])
 _sig("heff_plan_create", _i32, [_ptr, ctypes.POINTER(_ptr), ctypes.POINTER(HeffLayout), _ptr, _ptr,
@@ -97,6 +102,7 @@ EXPORTED = [
     "ozaki_pair_variants", "ozaki_ctx_set_variant", "ozaki_ctx_get_variant",
     "ozaki_ctx_set_autotune", "ozaki_dgemm_tune", "heff_plan_variants", "ozaki_slices_for_bits", "ozaki_pair_count",
     "ozaki_max_exact_k", "ozaki_dgemm_workspace_bytes", "ozaki_dgemm", "ozaki_split",
+    "ozaki_choose_slices", "ozaki_dgemm_auto_workspace_bytes", "ozaki_dgemm_auto",
     "ozaki_pair_products", "heff_plan_create", "heff_apply", "heff_plan_set_graphs",
     "heff_plan_graph_count", "heff_vector_length", "heff_flops",
     "heff_plan_destroy", "davidson_create", "davidson_step", "davidson_get_vector",
@@ -268,6 +274,67 @@ class Context:
                                 beta, C.data_ptr(), _ld(C, "C"), slices, ndiag, wptr, wlen,
                                 _stream(stream)), "ozaki_dgemm")
         return C
+
+    # ---- emulation modes --------------------------------------------------
+    def auto_workspace(self, M, N, K) -> torch.Tensor | None:
+        n = int(_lib.ozaki_dgemm_auto_workspace_bytes(M, N, K))
+        if n == 0:
+            return None
+        return torch.empty(n, dtype=torch.uint8, device="cuda:%d" % self.device)
+
+    @staticmethod
+    def _dims(A, B, transa, transb):
+        ta, tb = transa.upper() == "T", transb.upper() == "T"
+        M = A.size(1) if ta else A.size(0)
+        K = A.size(0) if ta else A.size(1)
+        N = B.size(0) if tb else B.size(1)
+        if (B.size(1) if tb else B.size(0)) != K:
+            raise ValueError("inner dimensions differ")
+        return M, N, K
+
+    def choose_slices(self, A, B, transa: str = "N", transb: str = "N", workspace=None, stream=None):
+        """(slices, ndiag, {rho_a, rho_b, predicted, native}) of the automatic choice."""
+        import numpy as np
+        _dev_f64(A, "A")
+        _dev_f64(B, "B")
+        M, N, K = self._dims(A, B, transa, transb)
+        if workspace is None:
+            workspace = self.auto_workspace(M, N, K)
+        s_out, g_out = ctypes.c_int32(), ctypes.c_int32()
+        st = np.zeros(4, dtype=np.float64)
+        _check(_lib.ozaki_choose_slices(self.handle, transa.upper().encode(), transb.upper().encode(), M, N, K,
+                                        A.data_ptr(), _ld(A, "A"), B.data_ptr(), _ld(B, "B"),
+                                        workspace.data_ptr() if workspace is not None else None,
+                                        workspace.numel() if workspace is not None else 0, _stream(stream),
+                                        ctypes.byref(s_out), ctypes.byref(g_out), st.ctypes.data),
+               "ozaki_choose_slices")
+        return s_out.value, g_out.value, {"rho_a": float(st[0]), "rho_b": float(st[1]),
+                                          "predicted": float(st[2]), "native": float(st[3])}
+
+    def dgemm_auto(self, A, B, bits: int = 0, performant: bool = False, alpha: float = 1.0,
+                   beta: float = 0.0, C=None, transa: str = "N", transb: str = "N", workspace=None,
+                   stream=None):
+        """C = alpha op(A) op(B) + beta C with the width (bits; 0 = automatic) and the path
+        (performant: timed per shape) chosen by the library; returns (C, slices, ndiag)
+        of the path taken (0, 0 = native FP64)."""
+        _dev_f64(A, "A")
+        _dev_f64(B, "B")
+        M, N, K = self._dims(A, B, transa, transb)
+        if C is None:
+            if beta != 0.0:
+                raise ValueError("beta != 0 needs C")
+            C = torch.empty((M, N), dtype=torch.float64, device=A.device)
+        _dev_f64(C, "C")
+        if workspace is None:
+            workspace = self.auto_workspace(M, N, K)
+        s_out, g_out = ctypes.c_int32(), ctypes.c_int32()
+        _check(_lib.ozaki_dgemm_auto(self.handle, transa.upper().encode(), transb.upper().encode(), M, N, K,
+                                     alpha, A.data_ptr(), _ld(A, "A"), B.data_ptr(), _ld(B, "B"), beta,
+                                     C.data_ptr(), _ld(C, "C"), int(bits), int(performant),
+                                     workspace.data_ptr() if workspace is not None else None,
+                                     workspace.numel() if workspace is not None else 0, _stream(stream),
+                                     ctypes.byref(s_out), ctypes.byref(g_out)), "ozaki_dgemm_auto")
+        return C, s_out.value, g_out.value
 
     # ---- steps on their own (tests) --------------------------------------
     def split(self, X, slices: int, by_columns: bool = False, stream=None):

@@ -474,3 +474,52 @@ def test_davidson_small_basis_restart_and_stagnation():
     # an unreachable tolerance ends in stagnation, not an endless loop
     th, _, st, its, _ = oracle.davidson(mv, prob.hdiag, prob.x0, tol=1e-30, max_iter=200)
     assert st in (oracle.STAGNATED, oracle.MAX_ITER) and abs(th - ev[0]) < 1e-9
+
+
+# ---- automatic slice count (this build's rule; the paper gives none) --------
+def test_auto_slices_keep_native_accuracy():
+    """The chosen (S, G) gives an emulated product whose error against the
+    double-double reference is within 1.5x of the plain FP64 product's, and
+    no cheaper pair count does (the purpose of the rule)."""
+    for U in (0, 10, 30):
+        A, B = wl.gemm_pair(192, U=U, seed=4)
+        hi, lo = oracle.dgemm_dd(A, B)
+        e64 = oracle.rel_frobenius(oracle.dgemm_fp64(A, B), hi, lo)
+        S, G = oracle.choose_slices(A, B)
+        err = oracle.rel_frobenius(oracle.ozaki_dgemm(A, B, S, G), hi, lo)
+        assert err <= 1.5 * e64, (U, S, G, err, e64)
+        # the next cheaper candidate misses native accuracy (the choice is not wasteful)
+        cheaper = [(s, g) for s in range(2, 9) for g in (s, s + 1)
+                   if oracle.pair_count(s, g) < oracle.pair_count(S, G)]
+        best = max(cheaper, key=lambda sg: oracle.pair_count(*sg))
+        err_c = oracle.rel_frobenius(oracle.ozaki_dgemm(A, B, *best), hi, lo)
+        assert err_c > 0.5 * e64, (U, best, err_c, e64)
+
+
+def test_error_model_tracks_measured_errors():
+    """Measured / predicted emulated error within [0.3, 3] where the emulation
+    error is well above the double-double floor."""
+    A, B = wl.gemm_pair(256, U=10, seed=5)
+    hi, lo = oracle.dgemm_dd(A, B)
+    ra, rb = oracle.rho(A), oracle.rho(B, by_columns=True)
+    for (S, G) in [(4, 4), (4, 5), (5, 5), (6, 6), (6, 7), (7, 7)]:
+        err = oracle.rel_frobenius(oracle.ozaki_dgemm(A, B, S, G), hi, lo)
+        pred = oracle.predicted_emulated_error(S, G, ra, rb)
+        assert 0.3 <= err / pred <= 3.0, (S, G, err, pred)
+    e64 = oracle.rel_frobenius(oracle.dgemm_fp64(A, B), hi, lo)
+    assert 0.3 <= e64 / oracle.predicted_native_error(256) <= 3.0
+
+
+def test_rho_closed_forms():
+    """rho of a constant matrix is 1 * 2^e / |c| (e the bumped exponent);
+    zero groups are left out; NaN marks a non-finite group."""
+    c = 0.75
+    X = np.full((5, 64), c)
+    e = 0  # 0.75 = 0.75 * 2^0, mantissa <= 127/128 -> no bump
+    assert oracle.rho(X) == pytest.approx(2.0 ** e / c, rel=1e-15)
+    X[2] = 0.0
+    assert oracle.rho(X) == pytest.approx(2.0 ** e / c, rel=1e-15)
+    X[3, 7] = np.nan
+    assert np.isnan(oracle.rho(X))
+    assert oracle.choose_slices(X, np.ones((64, 3))) == (7, 7)
+    assert oracle.choose_slices(np.zeros((4, 8)), np.ones((8, 4))) == (2, 2)
