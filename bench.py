@@ -134,12 +134,17 @@ def gemm_section(args, ozaki, ctx, torch, oracle):
             " slice %.3f ms" % (S, G, P, variant, t * 1e3, r["tflops"], err, pair_ms or 0,
                                 100 * (r["int8_frac"] or 0), slice_ms or 0))
     ctx.set_timing(False)
+    S_a, G_a, st = ctx.choose_slices(dA, dB)
+    auto = {"slices": S_a, "ndiag": G_a, "predicted_error": st["predicted"],
+            "predicted_native_error": st["native"], "rho_a": st["rho_a"], "rho_b": st["rho_b"]}
+    log("[bench] automatic width: S=%d G=%d (predicted relF %.2e, native %.2e)"
+        % (S_a, G_a, st["predicted"], st["native"]))
     eq = [r for r in results if r["rel_frobenius"] <= err64]
     chosen = min(eq, key=lambda r: r["ms"]) if eq else min(results, key=lambda r: r["rel_frobenius"])
     tol = [r for r in results if r["rel_frobenius"] <= 1e-12]
     at_1e12 = min(tol, key=lambda r: r["ms"]) if tol else None
     return {"n": n, "fp64": fp64, "vendor_fp64": vendor, "emulated": results, "chosen": chosen,
-            "at_1e-12": at_1e12, "rows_for_error": len(rows)}, (A, B)
+            "at_1e-12": at_1e12, "rows_for_error": len(rows), "auto": auto}, (A, B)
 
 
 def gemm_case(ozaki, ctx, torch, oracle, n, U, err_rows, steps, warmup, slices=range(4, 9)):
@@ -186,6 +191,23 @@ def gemm_case(ozaki, ctx, torch, oracle, n, U, err_rows, steps, warmup, slices=r
             res.append({"slices": S, "ndiag": G, "variant": v, "ms": t * 1e3, "tflops": flops / t / 1e12,
                         "rel_frobenius": rf, "componentwise": cw})
     out["emulated"] = res
+    # emulation modes: the automatic width and the performant path for this shape
+    S_a, G_a, st = ctx.choose_slices(dA, dB)
+    auto = {"slices": S_a, "ndiag": G_a, "rho_a": st["rho_a"], "rho_b": st["rho_b"],
+            "predicted_error": st["predicted"], "predicted_native_error": st["native"]}
+    hit = [r for r in res if (r["slices"], r["ndiag"]) == (S_a, G_a)]
+    if hit:
+        auto["rel_frobenius"] = hit[0]["rel_frobenius"]
+        auto["ms"] = hit[0]["ms"]
+    # performant dispatch at the 53-bit width (the automatic width re-reads the
+    # operand statistics on every call, which would dominate small shapes)
+    aw = ctx.auto_workspace(n, n, n)
+    _, S_p, G_p = ctx.dgemm_auto(dA, dB, bits=53, performant=True, C=C, workspace=aw)
+    t = time_calls(lambda: ctx.dgemm_auto(dA, dB, bits=53, performant=True, C=C, workspace=aw),
+                   steps, warmup, torch)
+    auto["performant"] = {"slices": S_p, "ndiag": G_p, "ms": t * 1e3, "tflops": flops / t / 1e12,
+                          "path": "emulated" if S_p else "native fp64"}
+    out["auto"] = auto
     eq = [r for r in res if r["rel_frobenius"] <= out["fp64"]["rel_frobenius"]]
     out["equal_error"] = min(eq, key=lambda r: r["ms"]) if eq else None
     log("[bench] n=%d U=%d: fp64 %.3f ms (relF %.2e), vendor %.3f ms; equal error: %s"
@@ -194,6 +216,9 @@ def gemm_case(ozaki, ctx, torch, oracle, n, U, err_rows, steps, warmup, slices=r
                                                                    out["equal_error"]["ndiag"],
                                                                    out["equal_error"]["ms"],
                                                                    out["equal_error"]["tflops"])))
+    log("[bench]   automatic width: S=%d G=%d (relF %s); performant at 53 bits: %s %.3f ms"
+        % (S_a, G_a, "%.2e" % auto["rel_frobenius"] if "rel_frobenius" in auto else "-",
+           auto["performant"]["path"], auto["performant"]["ms"]))
     for r in res:
         log("[bench]   S=%d G=%d v%d %.3f ms %.1f TFLOP/s relF %.2e comp %.2e"
             % (r["slices"], r["ndiag"], r["variant"], r["ms"], r["tflops"], r["rel_frobenius"], r["componentwise"]))
@@ -448,6 +473,7 @@ def main():
         "speedup_vs_vendor_fp64": gemm["vendor_fp64"]["ms"] / chosen["ms"],
         "emulated_per_slices": gemm["emulated"],
         "at_1e-12": gemm["at_1e-12"],
+        "automatic_width": gemm["auto"],
         "cpu_baseline": cpu,
     }
     line.update(extra)
