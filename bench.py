@@ -372,6 +372,64 @@ def davidson_section(args, ozaki, ctx, torch):
     return out
 
 
+def stability_section(args, ozaki, ctx, torch):
+    """Low-slice stability of the two Krylov solvers (the paper's numerical
+    stability study): for several independent H_eff problems (standing in
+    for the successive steps of a sweep), Davidson and Lanczos at S = 2, 3, 4
+    and residual thresholds 1e-2 .. 1e-8, against the FP64 ground energy E0
+    of the same problem (FP64 Lanczos to 1e-10).  Reported per solver, S and
+    threshold: iterations (mean over problems), statuses, the largest
+    |E - E0| / |E0| and the number of non-variational energies (E below E0 by
+    more than 1e-13 |E0|)."""
+    from paper_2510_04795_amd import workloads as wl
+    D, kop, nprob = args.stab_d, 8, args.stab_problems
+    tols = [1e-2, 1e-3, 1e-4, 1e-5, 1e-8]
+    log("[bench] stability study: %d problems D=%d (n=%d), Kop=%d" % (nprob, D, D * D, kop))
+    acc = {}
+    for seed in range(nprob):
+        prob = wl.davidson_problem(D=D, kop=kop, seed=seed)
+        layout, Lf, Rf, _, triples = wl.flatten_dense(prob.L, prob.R, prob.x0[:, None, :])
+        hd = torch.from_numpy(prob.hdiag.ravel().copy()).cuda()
+        x0 = torch.from_numpy(prob.x0.ravel().copy()).cuda()
+        e0 = None
+        for S in [0, 2, 3, 4]:
+            plan, tplan, keep = heff_flat_plan(ozaki, ctx, torch, layout, Lf, Rf, triples, S, 0,
+                                               diag=prob.delta.ravel().copy())
+            if S == 0:
+                lz = ozaki.Lanczos(ctx, plan, x0, m_max=32, tol=1e-10, max_iter=600)
+                e0, st, _, _ = lz.run()
+                lz.close()
+                if st != "converged":
+                    raise RuntimeError("FP64 reference Lanczos did not converge (%s)" % st)
+            for tol in tols:
+                for method in ("davidson", "lanczos"):
+                    if method == "davidson":
+                        sol = ozaki.Davidson(ctx, plan, hd, x0, m_max=32, tol=tol, max_iter=300)
+                    else:
+                        sol = ozaki.Lanczos(ctx, plan, x0, m_max=32, tol=tol, max_iter=300)
+                    th, st, its, _ = sol.run()
+                    sol.close()
+                    r = acc.setdefault((method, S, tol), {"iterations": [], "status": {}, "rel_err": [],
+                                                          "nonvariational": 0})
+                    r["iterations"].append(its)
+                    r["status"][st] = r["status"].get(st, 0) + 1
+                    r["rel_err"].append((th - e0) / abs(e0))
+                    if th < e0 - 1e-13 * abs(e0):
+                        r["nonvariational"] += 1
+            plan.close()
+            del keep
+    rows = []
+    for (method, S, tol), r in sorted(acc.items()):
+        rows.append({"solver": method, "slices": S, "tol": tol,
+                     "mean_iterations": float(np.mean(r["iterations"])),
+                     "status": r["status"], "max_abs_rel_err": float(np.max(np.abs(r["rel_err"]))),
+                     "min_rel_err": float(np.min(r["rel_err"])), "nonvariational": r["nonvariational"]})
+        log("[bench] stability %-8s S=%d tol=%.0e: it %.1f  %s  max|dE/E| %.2e  non-variational %d/%d"
+            % (method, S, tol, rows[-1]["mean_iterations"], r["status"], rows[-1]["max_abs_rel_err"],
+               r["nonvariational"], nprob))
+    return {"D": D, "n": D * D, "kop": kop, "problems": nprob, "m_max": 32, "rows": rows}
+
+
 def cpu_baseline(oracle, A, B, S, G, rows_count):
     rows = sampled_rows(A.shape[0], rows_count, seed=2)
     n = A.shape[0]
@@ -393,8 +451,9 @@ def main():
     ap.add_argument("--err-rows", type=int, default=16)
     ap.add_argument("--cpu-rows", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--sections", default="gemm,dense,sparse,davidson,sweep",
-                    help="comma list of gemm, dense, sparse, davidson, sweep (the GEMM section always runs)")
+    ap.add_argument("--sections", default="gemm,dense,sparse,davidson,stability,sweep",
+                    help="comma list of gemm, dense, sparse, davidson, stability, sweep "
+                         "(the GEMM section always runs)")
     ap.add_argument("--gemm-configs", default="",
                     help="comma list of S:G for the GEMM section (default: S = 4..8, G in {S, S+1})")
     ap.add_argument("--variant", type=int, default=-1,
@@ -403,6 +462,8 @@ def main():
     ap.add_argument("--heff-kop", type=int, default=64)
     ap.add_argument("--heff-steps", type=int, default=3)
     ap.add_argument("--dav-d", type=int, default=1024)
+    ap.add_argument("--stab-d", type=int, default=96)
+    ap.add_argument("--stab-problems", type=int, default=6)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -441,6 +502,8 @@ def main():
             layout, Lf, Rf, pf, triples, [(6, 6), (7, 7), (8, 8)])
     if "davidson" in sections:
         extra["davidson"] = davidson_section(args, ozaki, ctx, torch)
+    if "stability" in sections:
+        extra["stability"] = stability_section(args, ozaki, ctx, torch)
     if "sweep" in sections:
         extra["gemm_sweep"] = sweep_section(args, ozaki, ctx, torch, oracle)
     line = {

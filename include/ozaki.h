@@ -328,6 +328,31 @@ int davidson_step(davidson dav, davidson_info *info, void *stream);
 int davidson_get_vector(davidson dav, double *x_out, void *stream);
 int davidson_destroy(davidson dav);
 
+/* ---- Lanczos eigensolver (lowest eigenpair) ------------------------- */
+/* The other Krylov method the paper runs for the same step ("Numerical
+ * stability": Lanczos against Davidson at low slice counts and several
+ * residual thresholds).  Lanczos with full reorthogonalisation (two
+ * classical Gram-Schmidt passes against the whole basis) and explicit
+ * restart: the tridiagonal T_m (alpha_j = q_j . H q_j from the first pass,
+ * beta_j = |w_j|) is diagonalised on the host (cyclic Jacobi, m <= 64); the
+ * residual estimate is beta_{m-1} |y_{m-1}| for the lowest Ritz pair
+ * (theta, y).  When m reaches m_max the basis restarts from the Ritz vector.
+ * The matvec is heff_apply of H; everything else is FP64 on the device.
+ * lanczos_create: x0 (device, heff_vector_length elements) is copied and
+ * normalised; 2 <= m_max <= 64; allocates m_max + 1 basis vectors.
+ * lanczos_step: one matvec and one Ritz solve; synchronises the stream to
+ * fill *info (theta, residual estimate, iteration, basis size, status);
+ * returns OZ_OK while running, else OZ_CONVERGED (estimate <= tol or an
+ * invariant subspace), OZ_STAGNATED (the last 20 estimates never below half
+ * the best before them) or OZ_MAX_ITER.
+ * lanczos_get_vector writes the current Ritz vector Q y (unit norm). */
+typedef struct lanczos_s *lanczos;
+int lanczos_create(ozaki_ctx ctx, lanczos *out, heff_plan H, const double *x0, int m_max, double tol,
+                   int max_iter, void *stream);
+int lanczos_step(lanczos lz, davidson_info *info, void *stream);
+int lanczos_get_vector(lanczos lz, double *x_out, void *stream);
+int lanczos_destroy(lanczos lz);
+
 #ifdef __cplusplus
 }
 #endif

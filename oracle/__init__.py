@@ -472,6 +472,62 @@ def davidson(matvec, hdiag, x0, m_max: int = 32, tol: float = 1e-8, max_iter: in
     return theta, x, MAX_ITER, max_iter, hist
 
 
+def lanczos(matvec, x0, m_max: int = 32, tol: float = 1e-8, max_iter: int = 300, stall_window: int = 20,
+            trace=None):
+    """Lowest eigenpair by Lanczos with full reorthogonalisation and explicit restart
+    (the Krylov solver the paper names for the H_eff diagonalisation and
+    compares with Davidson in its numerical-stability discussion; the
+    variant's details are this implementation's reading: the paper gives none).
+
+    Start: q_0 = x0 / |x0|.  Each step (one matvec) with basis q_0 .. q_{m-1}:
+      1. w = H q_{m-1}; c = Q w (alpha_{m-1} = c[m-1]); w -= c Q; once more
+         w -= (Q w) Q (two classical Gram-Schmidt passes); beta = |w|;
+      2. lowest eigenpair (theta, y) of the tridiagonal T_m (diagonal alpha,
+         off-diagonal beta_0 .. beta_{m-2}; numpy eigh), sign fixed so the
+         largest |y_i| is positive; residual estimate rho = beta |y_{m-1}|;
+      3. converged when rho <= tol or beta <= 1e-14 (|alpha| + previous beta);
+         stagnation as in davidson();
+      4. basis full (m = m_max): restart from x = y Q normalised; else
+         q_m = w / beta.
+    Returns (theta, x, status, iterations, residual history)."""
+    v = np.asarray(x0, dtype=np.float64).ravel().copy()
+    Q = [v / np.linalg.norm(v)]
+    alpha, beta, hist = [], [], []
+    theta, x = 0.0, Q[0]
+    for it in range(1, max_iter + 1):
+        m = len(Q)
+        Qm = np.array(Q)
+        w = matvec(Q[-1])
+        c = Qm @ w
+        a = float(c[-1])
+        w = w - c @ Qm
+        w = w - (Qm @ w) @ Qm
+        b = float(np.linalg.norm(w))
+        alpha.append(a)
+        T = np.diag(alpha) + np.diag(beta, 1) + np.diag(beta, -1)
+        evals, evecs = np.linalg.eigh(T)
+        theta = float(evals[0])
+        y = evecs[:, 0]
+        if y[np.argmax(np.abs(y))] < 0:
+            y = -y
+        rho = b * abs(float(y[-1]))
+        hist.append(rho)
+        if trace is not None:
+            trace(it, theta, rho, m)
+        x = y @ Qm
+        if rho <= tol or not (b > 1e-14 * (abs(a) + (beta[-1] if beta else 0.0))):
+            return theta, x, CONVERGED, it, hist
+        if len(hist) > stall_window and min(hist[-stall_window:]) > 0.5 * min(hist[:-stall_window]):
+            return theta, x, STAGNATED, it, hist
+        if m == m_max:
+            Q = [x / np.linalg.norm(x)]
+            alpha, beta = [], []
+        else:
+            beta.append(b)
+            Q.append(w / b)
+    return theta, x, MAX_ITER, max_iter, hist
+
+
 def heff_matvec(L, R, diag=None, S: int = 0, G: int | None = None):
     """x (length D^2) -> sigma (length D^2) for phys = 1, via heff_dense."""
     D = L.shape[1]

@@ -470,3 +470,281 @@ int davidson_destroy(davidson d) {
 }
 
 }  // extern "C"
+
+// ---- Lanczos with full reorthogonalisation and explicit restart -------------
+
+namespace {
+
+// x = Q^T y over the first m basis vectors.
+__global__ void k_combine(const double *__restrict__ Q, int64_t n, int m, const double *__restrict__ y,
+                          double *__restrict__ x) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        double s = 0.0;
+        for (int j = 0; j < m; ++j) s = fma(y[j], Q[j * n + i], s);
+        x[i] = s;
+    }
+}
+
+// Lowest eigenpair of the symmetric m x m matrix a (row-major), cyclic
+// Jacobi on the host; y normalised with its largest-magnitude entry positive.
+double host_lowest_eigenpair(std::vector<double> a, int m, std::vector<double> *y) {
+    std::vector<double> v(static_cast<size_t>(m) * m, 0.0);
+    for (int i = 0; i < m; ++i) v[static_cast<size_t>(i) * m + i] = 1.0;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) {
+                const double x = a[static_cast<size_t>(i) * m + j] * a[static_cast<size_t>(i) * m + j];
+                tot += x;
+                if (i != j) off += x;
+            }
+        if (std::sqrt(off) <= 1e-15 * std::sqrt(tot)) break;
+        for (int p = 0; p < m - 1; ++p)
+            for (int q = p + 1; q < m; ++q) {
+                const double apq = a[static_cast<size_t>(p) * m + q];
+                if (apq == 0.0) continue;
+                const double th = (a[static_cast<size_t>(q) * m + q] - a[static_cast<size_t>(p) * m + p]) / (2.0 * apq);
+                const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+                const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+                for (int k = 0; k < m; ++k) {  // rows p, q
+                    const double ap = a[static_cast<size_t>(p) * m + k], aq = a[static_cast<size_t>(q) * m + k];
+                    a[static_cast<size_t>(p) * m + k] = c * ap - s * aq;
+                    a[static_cast<size_t>(q) * m + k] = s * ap + c * aq;
+                }
+                for (int k = 0; k < m; ++k) {  // columns p, q and the eigenvectors
+                    const double ap = a[static_cast<size_t>(k) * m + p], aq = a[static_cast<size_t>(k) * m + q];
+                    a[static_cast<size_t>(k) * m + p] = c * ap - s * aq;
+                    a[static_cast<size_t>(k) * m + q] = s * ap + c * aq;
+                    const double vp = v[static_cast<size_t>(k) * m + p], vq = v[static_cast<size_t>(k) * m + q];
+                    v[static_cast<size_t>(k) * m + p] = c * vp - s * vq;
+                    v[static_cast<size_t>(k) * m + q] = s * vp + c * vq;
+                }
+            }
+    }
+    int best = 0;
+    for (int i = 1; i < m; ++i)
+        if (a[static_cast<size_t>(i) * m + i] < a[static_cast<size_t>(best) * m + best]) best = i;
+    int big = 0;
+    for (int i = 1; i < m; ++i)
+        if (std::fabs(v[static_cast<size_t>(i) * m + best]) > std::fabs(v[static_cast<size_t>(big) * m + best])) big = i;
+    const double sgn = v[static_cast<size_t>(big) * m + best] < 0 ? -1.0 : 1.0;
+    y->resize(m);
+    for (int i = 0; i < m; ++i) (*y)[i] = sgn * v[static_cast<size_t>(i) * m + best];
+    return a[static_cast<size_t>(best) * m + best];
+}
+
+}  // namespace
+
+struct lanczos_s {
+    ozaki_ctx ctx = nullptr;
+    heff_plan H = nullptr;
+    int64_t n = 0;
+    int m_max = 0, max_iter = 0;
+    double tol = 0;
+    std::vector<void *> allocs;
+    double *Q = nullptr, *w = nullptr, *coef = nullptr, *partial = nullptr, *scal = nullptr, *y_dev = nullptr;
+    int *gate = nullptr;
+    double *host = nullptr;  // pinned: coefficients of the first pass, |w|^2
+    std::vector<double> alpha, beta, y;
+    int m = 0, iter = 0, status = OZ_OK;
+    double theta = 0, rho = 0;
+    std::vector<double> hist;
+};
+
+namespace {
+
+int lalloc(lanczos l, size_t bytes, void **p) {
+    hipError_t e = hipMalloc(p, bytes < 8 ? 8 : bytes);
+    if (e != hipSuccess) return fail(OZ_ERR_NOMEM, "lanczos_create: %zu bytes: %s", bytes, hipGetErrorString(e));
+    l->allocs.push_back(*p);
+    return OZ_OK;
+}
+
+void lfree(lanczos l) {
+    for (void *p : l->allocs) hipFree(p);
+    if (l->host) hipHostFree(l->host);
+    delete l;
+}
+
+// out[i] = Q_i . v for i < rows, with the Davidson dot kernels
+hipError_t ldots(lanczos l, const double *Q, int rows, const double *v, double *out, hipStream_t s) {
+    const int nb = dot_blocks(l->n);
+    hipLaunchKernelGGL(k_dots_partial, dim3(nb, rows), dim3(kDotThreads), 0, s, Q, l->n, v, l->n, l->partial, nullptr);
+    hipLaunchKernelGGL(k_dots_final, dim3(rows), dim3(kDotThreads), 0, s, l->partial, nb, out, 1, nullptr, 0, nullptr);
+    return hipGetLastError();
+}
+
+// q_0 = x / |x| into the basis; resets T
+int lanczos_reset(lanczos l, const double *x, hipStream_t s) {
+    hipError_t e;
+    double *nrm2 = l->scal;
+    if ((e = ldots(l, x, 1, x, nrm2, s)) != hipSuccess) return hip_fail(e, "lanczos: norm");
+    hipLaunchKernelGGL(k_scale_into, dim3(grid_n(l->n)), dim3(256), 0, s, x, nrm2, l->Q, l->n);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "lanczos: normalise");
+    l->m = 1;
+    l->alpha.clear();
+    l->beta.clear();
+    return OZ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lanczos_create(ozaki_ctx ctx, lanczos *out, heff_plan H, const double *x0, int m_max, double tol, int max_iter,
+                   void *stream) {
+    if (!out) return fail(OZ_ERR_ARG, "lanczos_create: out is NULL");
+    *out = nullptr;
+    if (!ctx || !H || !x0) return fail(OZ_ERR_ARG, "lanczos_create: NULL argument");
+    if (m_max < 2 || m_max > 64) return fail(OZ_ERR_ARG, "lanczos_create: m_max = %d (2..64)", m_max);
+    if (!(tol >= 0) || max_iter < 1) return fail(OZ_ERR_ARG, "lanczos_create: tol / max_iter");
+    const int64_t n = heff_vector_length(H);
+    if (n < 1) return fail(OZ_ERR_ARG, "lanczos_create: empty operator");
+    hipError_t e;
+    if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    lanczos l = new lanczos_s();
+    l->ctx = ctx;
+    l->H = H;
+    l->n = n;
+    l->m_max = m_max;
+    l->tol = tol;
+    l->max_iter = max_iter;
+    int rc;
+    void *p;
+#define OZ_LA(field, bytes) \
+    if ((rc = lalloc(l, (bytes), &p)) != OZ_OK) { lfree(l); return rc; } \
+    l->field = static_cast<decltype(l->field)>(p);
+    OZ_LA(Q, sizeof(double) * (m_max + 1) * n)
+    OZ_LA(w, sizeof(double) * n)
+    OZ_LA(coef, sizeof(double) * 72)
+    OZ_LA(partial, sizeof(double) * 66 * 512)
+    OZ_LA(scal, sizeof(double) * 8)
+    OZ_LA(y_dev, sizeof(double) * 72)
+    OZ_LA(gate, sizeof(int) * 4)
+#undef OZ_LA
+    if ((e = hipHostMalloc(reinterpret_cast<void **>(&l->host), sizeof(double) * 72, 0)) != hipSuccess) {
+        l->host = nullptr;
+        lfree(l);
+        return hip_fail(e, "lanczos_create: pinned buffer");
+    }
+    // start vector: |x0| must be positive and finite
+    if ((e = ldots(l, x0, 1, x0, l->scal, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(l->host, l->scal, sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess) {
+        lfree(l);
+        return hip_fail(e, "lanczos_create: start vector");
+    }
+    if (!(l->host[0] > 0) || !std::isfinite(l->host[0])) {
+        lfree(l);
+        return fail(OZ_ERR_ARG, "lanczos_create: start vector is zero or not finite");
+    }
+    if ((rc = lanczos_reset(l, x0, s)) != OZ_OK) { lfree(l); return rc; }
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) { lfree(l); return hip_fail(e, "lanczos_create: sync"); }
+    *out = l;
+    return OZ_OK;
+}
+
+int lanczos_step(lanczos l, davidson_info *info, void *stream) {
+    if (!l) return fail(OZ_ERR_ARG, "lanczos_step: NULL solver");
+    if (l->status != OZ_OK) {
+        if (info) *info = davidson_info{l->theta, l->rho, l->iter, l->m, l->status};
+        return fail(OZ_ERR_STATE, "lanczos_step: the iteration has already ended (%s)", ozaki_status_string(l->status));
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    if ((e = hipSetDevice(l->ctx->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+    const int64_t n = l->n;
+    const int m = l->m;  // basis q_0 .. q_{m-1}; this step expands from q_{m-1}
+    double *qj = l->Q + static_cast<int64_t>(m - 1) * n;
+    int rc = heff_apply(l->H, qj, l->w, s);
+    if (rc != OZ_OK) return rc;
+    // two classical Gram-Schmidt passes against the whole basis; alpha from the first
+    for (int pass = 0; pass < 2; ++pass) {
+        if ((e = ldots(l, l->Q, m, l->w, l->coef, s)) != hipSuccess) return hip_fail(e, "lanczos: projection");
+        if (pass == 0 && (e = hipMemcpyAsync(l->host, l->coef, sizeof(double) * m, hipMemcpyDeviceToHost, s)) != hipSuccess)
+            return hip_fail(e, "lanczos: coefficients");
+        hipLaunchKernelGGL(k_project, dim3(grid_n(n)), dim3(256), 0, s, l->Q, n, m, l->coef, l->w, nullptr);
+    }
+    if ((e = ldots(l, l->w, 1, l->w, l->scal, s)) != hipSuccess) return hip_fail(e, "lanczos: norm");
+    if ((e = hipMemcpyAsync(l->host + 64, l->scal, sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_fail(e, "lanczos: step");
+    l->iter += 1;
+    const double a = l->host[m - 1];
+    const double b = std::sqrt(l->host[64] > 0 ? l->host[64] : 0.0);
+    l->alpha.push_back(a);
+    // Ritz pair of T_m
+    std::vector<double> T(static_cast<size_t>(m) * m, 0.0);
+    for (int i = 0; i < m; ++i) {
+        T[static_cast<size_t>(i) * m + i] = l->alpha[i];
+        if (i + 1 < m) T[static_cast<size_t>(i) * m + i + 1] = T[static_cast<size_t>(i + 1) * m + i] = l->beta[i];
+    }
+    l->theta = host_lowest_eigenpair(T, m, &l->y);
+    l->rho = b * std::fabs(l->y[m - 1]);
+    l->hist.push_back(l->rho);
+    int status = OZ_OK;
+    const bool invariant = !(b > 1e-14 * (std::fabs(a) + (m > 1 ? l->beta[m - 2] : 0.0)));
+    if (l->rho <= l->tol || invariant) {
+        status = OZ_CONVERGED;
+    } else if (l->hist.size() > 20) {
+        const size_t first_recent = l->hist.size() - 20;
+        double recent = INFINITY, before = INFINITY;
+        for (size_t i = 0; i < l->hist.size(); ++i) {
+            if (i >= first_recent) recent = std::min(recent, l->hist[i]);
+            else before = std::min(before, l->hist[i]);
+        }
+        if (recent > 0.5 * before) status = OZ_STAGNATED;
+    }
+    if (status == OZ_OK && l->iter >= l->max_iter) status = OZ_MAX_ITER;
+    if (status == OZ_OK) {
+        if (m == l->m_max) {
+            // restart from the Ritz vector x = Q y (written to w, then normalised into q_0)
+            if ((e = hipMemcpyAsync(l->y_dev, l->y.data(), sizeof(double) * m, hipMemcpyHostToDevice, s)) != hipSuccess)
+                return hip_fail(e, "lanczos: Ritz coefficients");
+            hipLaunchKernelGGL(k_combine, dim3(grid_n(n)), dim3(256), 0, s, l->Q, n, m, l->y_dev, l->w);
+            if ((rc = lanczos_reset(l, l->w, s)) != OZ_OK) return rc;
+        } else {
+            l->beta.push_back(b);
+            hipLaunchKernelGGL(k_scale_into, dim3(grid_n(n)), dim3(256), 0, s, l->w, l->scal,
+                               l->Q + static_cast<int64_t>(m) * n, n);
+            if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "lanczos: expand");
+            l->m = m + 1;
+        }
+    } else {
+        // keep the Ritz coefficients of the final basis for lanczos_get_vector
+        l->m = m;
+    }
+    l->status = status;
+    if (info) *info = davidson_info{l->theta, l->rho, l->iter, l->m, status};
+    return status;
+}
+
+int lanczos_get_vector(lanczos l, double *x_out, void *stream) {
+    if (!l || !x_out) return fail(OZ_ERR_ARG, "lanczos_get_vector: NULL argument");
+    if (l->iter == 0 || l->y.empty()) return fail(OZ_ERR_STATE, "lanczos_get_vector: no step taken yet");
+    if (l->status == OZ_OK && l->m == 1 && l->alpha.empty()) {
+        // just restarted: q_0 is the Ritz vector
+        hipError_t e = hipMemcpyAsync(x_out, l->Q, sizeof(double) * l->n, hipMemcpyDeviceToDevice,
+                                      static_cast<hipStream_t>(stream));
+        return e == hipSuccess ? OZ_OK : hip_fail(e, "lanczos_get_vector");
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int m = static_cast<int>(l->y.size());
+    hipError_t e = hipMemcpyAsync(l->y_dev, l->y.data(), sizeof(double) * m, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "lanczos_get_vector: coefficients");
+    hipLaunchKernelGGL(k_combine, dim3(grid_n(l->n)), dim3(256), 0, s, l->Q, l->n, m, l->y_dev, x_out);
+    e = hipStreamSynchronize(s);  // y_dev is reused by the next step
+    return e == hipSuccess ? OZ_OK : hip_fail(e, "lanczos_get_vector");
+}
+
+int lanczos_destroy(lanczos l) {
+    if (!l) return OZ_OK;
+    hipSetDevice(l->ctx->device);
+    hipDeviceSynchronize();
+    lfree(l);
+    return OZ_OK;
+}
+
+}  // extern "C"

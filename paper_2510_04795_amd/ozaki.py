@@ -95,6 +95,10 @@ _sig("davidson_create", _i32, [_ptr, ctypes.POINTER(_ptr), _ptr, _ptr, _ptr, _i3
 _sig("davidson_step", _i32, [_ptr, ctypes.POINTER(DavidsonInfo), _ptr])
 _sig("davidson_get_vector", _i32, [_ptr, _ptr, _ptr])
 _sig("davidson_destroy", _i32, [_ptr])
+_sig("lanczos_create", _i32, [_ptr, ctypes.POINTER(_ptr), _ptr, _ptr, _i32, _dbl, _i32, _ptr])
+_sig("lanczos_step", _i32, [_ptr, ctypes.POINTER(DavidsonInfo), _ptr])
+_sig("lanczos_get_vector", _i32, [_ptr, _ptr, _ptr])
+_sig("lanczos_destroy", _i32, [_ptr])
 
 EXPORTED = [
     "ozaki_status_string", "ozaki_last_error", "ozaki_version", "ozaki_ctx_create",
@@ -106,7 +110,7 @@ EXPORTED = [
     "ozaki_pair_products", "heff_plan_create", "heff_apply", "heff_plan_set_graphs",
     "heff_plan_graph_count", "heff_vector_length", "heff_flops",
     "heff_plan_destroy", "davidson_create", "davidson_step", "davidson_get_vector",
-    "davidson_destroy",
+    "davidson_destroy", "lanczos_create", "lanczos_step", "lanczos_get_vector", "lanczos_destroy",
 ]
 
 
@@ -479,6 +483,50 @@ class Davidson:
     def close(self):
         if getattr(self, "handle", None):
             _lib.davidson_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Lanczos:
+    """Device-resident Lanczos iteration (full reorthogonalisation, explicit
+    restart) for the lowest eigenpair of a HeffPlan; same step interface as
+    Davidson."""
+
+    def __init__(self, ctx: Context, plan: HeffPlan, x0, m_max: int = 32, tol: float = 1e-8,
+                 max_iter: int = 300, stream=None):
+        self.ctx = ctx
+        self.plan = plan
+        h = _ptr()
+        _check(_lib.lanczos_create(ctx.handle, ctypes.byref(h), plan.handle, _dev_f64(x0, "x0").data_ptr(),
+                                   m_max, tol, max_iter, _stream(stream)), "lanczos_create")
+        self.handle = h
+
+    def step(self, stream=None) -> DavidsonInfo:
+        info = DavidsonInfo()
+        _check(_lib.lanczos_step(self.handle, ctypes.byref(info), _stream(stream)), "lanczos_step")
+        return info
+
+    def vector(self, out=None, stream=None):
+        if out is None:
+            out = torch.empty(self.plan.n, dtype=torch.float64, device="cuda:%d" % self.ctx.device)
+        _check(_lib.lanczos_get_vector(self.handle, out.data_ptr(), _stream(stream)), "lanczos_get_vector")
+        return out
+
+    def run(self, stream=None):
+        """Iterate until a terminal status; returns (theta, status, iterations, residual)."""
+        while True:
+            info = self.step(stream)
+            if info.status != OZ_OK:
+                return info.theta, STATUS[info.status], info.iter, info.resnorm
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.lanczos_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -101,3 +101,108 @@ def test_bad_arguments(oz):
     prob = wl.davidson_problem(D=8, kop=2)
     with pytest.raises(ozaki.OzakiError):
         solver(ozaki, ctx, torch, prob, 0, m_max=1)
+
+
+# ---------------------------------------------------------------- Lanczos
+def lanczos_solver(ozaki, ctx, torch, prob, S, G=0, m_max=32, tol=1e-8, max_iter=300):
+    layout, Lf, Rf, _, triples = wl.flatten_dense(prob.L, prob.R, prob.x0[:, None, :])
+    keep = [dev(torch, Lf), dev(torch, Rf), dev(torch, prob.delta.ravel())]
+    plan = ozaki.HeffPlan(ctx, layout, keep[0], keep[1], triples, diag=keep[2], slices=S, ndiag=G)
+    x0 = dev(torch, prob.x0.ravel())
+    lz = ozaki.Lanczos(ctx, plan, x0, m_max=m_max, tol=tol, max_iter=max_iter)
+    return lz, (plan, keep, x0)
+
+
+def test_lanczos_d16_against_brute_force(oz):
+    ozaki, ctx, torch = oz
+    prob = wl.davidson_problem(D=16, kop=32)
+    ev, evec = brute(prob)
+    lz, keep = lanczos_solver(ozaki, ctx, torch, prob, 0)
+    theta, status, its, res = lz.run()
+    assert status == "converged" and res <= 1e-8
+    assert abs(theta - ev[0]) < 1e-10
+    x = lz.vector().cpu().numpy()
+    assert abs(np.linalg.norm(x) - 1) < 1e-12
+    assert abs(abs(x @ evec[:, 0]) - 1) < 1e-8
+    for S in (4, 6):
+        lz, keep = lanczos_solver(ozaki, ctx, torch, prob, S)
+        th, st, _, _ = lz.run()
+        assert st == "converged" and abs(th - ev[0]) < 1e-6, (S, th - ev[0])
+
+
+@pytest.mark.parametrize("S", [0, 3, 5])
+def test_lanczos_matches_oracle(oz, S):
+    """Same problem and start: the device and the oracle Lanczos agree in
+    energy far inside the matvec's own error and in the iteration count (the
+    tridiagonal eigensolvers differ: Jacobi on the host, LAPACK in the oracle)."""
+    ozaki, ctx, torch = oz
+    prob = wl.davidson_problem(D=40, kop=8)
+    lz, keep = lanczos_solver(ozaki, ctx, torch, prob, S, m_max=12)
+    th, st, its, res = lz.run()
+    mv = oracle.heff_matvec(prob.L, prob.R, prob.delta, S=S)
+    th_ref, x_ref, st_ref, its_ref, _ = oracle.lanczos(mv, prob.x0, m_max=12, tol=1e-8)
+    assert st == st_ref == oracle.CONVERGED
+    # with S = 3 a last-bit change of the vector can move a slice boundary and
+    # the matvec by its own error (~1e-7 relative): the runs then differ slightly
+    assert abs(th - th_ref) < {0: 1e-10, 3: 1e-6, 5: 1e-9}[S]
+    assert abs(its - its_ref) <= (3 if S == 3 else 2)
+    x = lz.vector().cpu().numpy()
+    assert abs(abs(x @ x_ref) - 1) < 1e-8
+
+
+def test_lanczos_restart_vector(oz):
+    """m_max = 4: the fourth step restarts from the Ritz vector, which the
+    solver then returns; the oracle's fourth-step Ritz vector is the same."""
+    ozaki, ctx, torch = oz
+    prob = wl.davidson_problem(D=12, kop=6)
+    lz, keep = lanczos_solver(ozaki, ctx, torch, prob, 0, m_max=4, tol=1e-12)
+    for _ in range(4):
+        info = lz.step()
+    assert info.status == 0 and info.iter == 4
+    x = lz.vector().cpu().numpy()
+    mv = oracle.heff_matvec(prob.L, prob.R, prob.delta)
+    th4, x4, _, _, _ = oracle.lanczos(mv, prob.x0, m_max=4, tol=1e-12, max_iter=4)
+    assert abs(info.theta - th4) < 1e-11
+    assert abs(abs(x @ x4) / np.linalg.norm(x4) - 1) < 1e-10
+    ev, _ = brute(prob)
+    th, st, its, _ = lz.run()
+    assert st == "converged" and abs(th - ev[0]) < 1e-10
+
+
+def test_lanczos_invariant_subspace(oz):
+    """Diagonal L_k, R_k give a diagonal H; a start vector on three basis
+    states spans an invariant subspace, found at the third step."""
+    ozaki, ctx, torch = oz
+    prob = wl.davidson_problem(D=6, kop=2)
+    rng = np.random.default_rng(7)
+    for k in range(2):
+        prob.L[k] = np.diag(rng.standard_normal(6))
+        prob.R[k] = np.diag(rng.standard_normal(6))
+    prob.delta[:] = 0.0
+    prob.x0[:] = 0.0
+    prob.x0[0, 0] = prob.x0[2, 3] = prob.x0[5, 1] = 1.0
+    hd = sum(np.outer(np.diag(prob.L[k]), np.diag(prob.R[k])) for k in range(2))
+    lz, keep = lanczos_solver(ozaki, ctx, torch, prob, 0, tol=0.0)
+    th, st, its, _ = lz.run()
+    assert st == "converged" and its == 3
+    assert abs(th - min(hd[0, 0], hd[2, 3], hd[5, 1])) < 1e-13
+
+
+def test_lanczos_stagnation_and_errors(oz):
+    ozaki, ctx, torch = oz
+    prob = wl.davidson_problem(D=10, kop=6)
+    lz, keep = lanczos_solver(ozaki, ctx, torch, prob, 3, m_max=8, tol=1e-30)
+    th, st, its, res = lz.run()
+    assert st == "stagnated"
+    with pytest.raises(ozaki.OzakiError):
+        lz.step()
+    lz, keep = lanczos_solver(ozaki, ctx, torch, prob, 0)
+    with pytest.raises(ozaki.OzakiError):
+        lz.vector()
+    with pytest.raises(ozaki.OzakiError):
+        lanczos_solver(ozaki, ctx, torch, prob, 0, m_max=1)
+    with pytest.raises(ozaki.OzakiError):
+        lanczos_solver(ozaki, ctx, torch, prob, 0, m_max=65)
+    prob.x0[:] = 0.0
+    with pytest.raises(ozaki.OzakiError):
+        lanczos_solver(ozaki, ctx, torch, prob, 0)

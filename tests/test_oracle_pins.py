@@ -476,6 +476,71 @@ def test_davidson_small_basis_restart_and_stagnation():
     assert st in (oracle.STAGNATED, oracle.MAX_ITER) and abs(th - ev[0]) < 1e-9
 
 
+def test_lanczos_brute_force_d16():
+    prob = wl.davidson_problem(D=16, kop=32)
+    H = _dense_H(prob)
+    ev, evec = np.linalg.eigh(H)
+    mv = oracle.heff_matvec(prob.L, prob.R, prob.delta)
+    theta, x, status, its, hist = oracle.lanczos(mv, prob.x0, m_max=32, tol=1e-8)
+    assert status == oracle.CONVERGED
+    assert abs(theta - ev[0]) < 1e-10
+    assert abs(np.linalg.norm(x) - 1) < 1e-12
+    assert abs(abs(x @ evec[:, 0]) - 1) < 1e-8
+    # a small basis restarts from the Ritz vector and still converges
+    th4, _, st4, its4, _ = oracle.lanczos(mv, prob.x0, m_max=4, tol=1e-8, max_iter=2000)
+    assert st4 == oracle.CONVERGED and abs(th4 - ev[0]) < 1e-10 and its4 > its
+
+
+def test_lanczos_ritz_values_of_the_krylov_space():
+    """Without restart, step m returns the lowest Rayleigh-Ritz value of H on
+    the Krylov space span(x0, H x0, ..., H^{m-1} x0), built here from the
+    power basis and a QR factorisation, and its residual estimate is the true
+    residual norm |H x - theta x| of the Ritz vector."""
+    prob = wl.davidson_problem(D=8, kop=6)
+    H = _dense_H(prob)
+    x0 = np.asarray(prob.x0, dtype=np.float64).ravel()
+    seen = []
+    oracle.lanczos(lambda v: H @ v, x0, m_max=40, tol=0.0, max_iter=6,
+                   trace=lambda it, th, rho, m: seen.append((th, rho, m)))
+    assert [m for _, _, m in seen] == [1, 2, 3, 4, 5, 6]
+    for m in range(1, 7):
+        K = np.empty((x0.size, m))
+        v = x0 / np.linalg.norm(x0)
+        for j in range(m):
+            K[:, j] = v
+            v = H @ v
+            v /= np.linalg.norm(v)
+        Qk, _ = np.linalg.qr(K)
+        w, y = np.linalg.eigh(Qk.T @ H @ Qk)
+        th, rho, _ = seen[m - 1]
+        assert abs(th - w[0]) < 1e-9 * abs(w[0])
+        xr = Qk @ y[:, 0]
+        assert abs(rho - np.linalg.norm(H @ xr - w[0] * xr)) < 1e-7 * np.linalg.norm(H, 2)
+
+
+def test_lanczos_invariant_subspace_and_stagnation():
+    # a start vector inside a 3-dimensional invariant subspace: the third step
+    # finds beta = 0 and ends converged with the exact eigenvalue of the subspace
+    d = np.array([-2.0, 1.0, 3.0, 5.0, 7.0, -9.0])
+    x0 = np.array([1.0, 1.0, 1.0, 0.0, 0.0, 0.0])
+    th, x, st, its, _ = oracle.lanczos(lambda v: d * v, x0, m_max=10, tol=0.0)
+    assert st == oracle.CONVERGED and its == 3 and abs(th + 2.0) < 1e-13
+    assert np.allclose(np.abs(x), [1, 0, 0, 0, 0, 0], atol=1e-12)
+    # tolerance 1e-30 with an exact matvec: after a restart from a Ritz vector
+    # accurate to rounding, beta itself is at rounding level and counts as an
+    # invariant subspace (converged)
+    prob = wl.davidson_problem(D=10, kop=6)
+    ev = np.linalg.eigvalsh(_dense_H(prob))
+    mv = oracle.heff_matvec(prob.L, prob.R, prob.delta)
+    th, _, st, its, _ = oracle.lanczos(mv, prob.x0, m_max=8, tol=1e-30, max_iter=300)
+    assert st == oracle.CONVERGED and its < 100 and abs(th - ev[0]) < 1e-12
+    # with a 3-slice matvec the estimate never reaches 1e-30 nor rounding level:
+    # the iteration stagnates, at an energy within the matvec's error
+    mv3 = oracle.heff_matvec(prob.L, prob.R, prob.delta, S=3)
+    th, _, st, _, _ = oracle.lanczos(mv3, prob.x0, m_max=8, tol=1e-30, max_iter=300)
+    assert st == oracle.STAGNATED and abs(th - ev[0]) < 1e-5
+
+
 # ---- automatic slice count (this build's rule; the paper gives none) --------
 def test_auto_slices_keep_native_accuracy():
     """The chosen (S, G) gives an emulated product whose error against the
