@@ -430,6 +430,76 @@ def stability_section(args, ozaki, ctx, torch):
     return {"D": D, "n": D * D, "kop": kop, "problems": nprob, "m_max": 32, "rows": rows}
 
 
+def rdm_section(args, ozaki, ctx, torch):
+    """Truncation and renormalisation (the site-update steps beside the H_eff
+    diagonalisation) with their linear algebra emulated at S slices or in
+    native FP64, as in the paper's numerical-stability discussion: rho =
+    psi psi^T of a planted two-site tensor (Schmidt values known), its D
+    dominant eigenpairs by the block-Jacobi solver, and U^T O U for Kop
+    block operators.  Errors are against the planted spectrum and subspace
+    (truncation) and against the FP64 renormalisation."""
+    from paper_2510_04795_amd import workloads as wl
+    n, D, kop = args.rdm_n, args.rdm_n // 4, args.rdm_kop
+    log("[bench] RDM truncation: rho %d x %d, keep D=%d; renormalisation of %d operators" % (n, n, D, kop))
+    t = wl.two_site_psi(n, seed=12)
+    psi = torch.from_numpy(t.psi).cuda()
+    s2 = t.schmidt ** 2
+    dw_exact = float(s2[D:].sum())
+    left = torch.from_numpy(np.ascontiguousarray(t.left[:, :D])).cuda()
+    out = {"n": n, "D": D, "kop": kop, "spectrum": "s_i^2 ~ exp(-i / (n/64)), unit trace", "truncation": [],
+           "renormalisation": []}
+    U64 = None
+    for S in [0, 2, 3, 4, 5, 6, 7, 8]:
+        eig = ozaki.RdmEig(ctx, n, S)
+        ozaki.truncate(ctx, psi, D, slices=S, eig=eig, max_sweeps=1)  # warm-up (allocations, code objects)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        U, w, dw, info = ozaki.truncate(ctx, psi, D, slices=S, eig=eig, max_sweeps=args.rdm_sweeps)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        eig.close()
+        wn = w.cpu().numpy()
+        orth = float((U.T @ U - torch.eye(D, dtype=torch.float64, device=U.device)).abs().max().item())
+        sv = torch.linalg.svdvals(left.T @ U)
+        r = {"slices": S, "ms": ms, "sweeps": info.sweeps, "status": ozaki.STATUS[info.status],
+             "eig_rel_err": float(np.max(np.abs(wn - s2[:D])) / s2[0]),
+             "discarded_weight": dw, "discarded_weight_err": abs(dw - dw_exact),
+             "orthogonality": orth, "subspace_err": float(1.0 - sv.min().item())}
+        out["truncation"].append(r)
+        log("[bench] truncation S=%d: %.1f ms, %d sweeps (%s), eig err %.1e, dw err %.1e, |U^T U - I| %.1e, "
+            "subspace %.1e" % (S, ms, info.sweeps, r["status"], r["eig_rel_err"], r["discarded_weight_err"], orth,
+                               r["subspace_err"]))
+        if S == 0:
+            U64 = U
+    rho = ctx.dgemm(psi, psi, slices=0, transb="T")
+    torch.linalg.eigh(rho)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    torch.linalg.eigh(rho)
+    torch.cuda.synchronize()
+    out["vendor_eigh_ms"] = (time.perf_counter() - t0) * 1e3
+    log("[bench] vendor FP64 eigh (torch.linalg.eigh) of rho: %.1f ms" % out["vendor_eigh_ms"])
+    ops = [torch.from_numpy(o).cuda() for o in wl.block_operators(n, kop, seed=13)]
+    ref = None
+    for S in [0, 3, 6, 7]:
+        ws = torch.empty(ozaki._lib.ozaki_renormalize_workspace_bytes(n, D, S, 0), dtype=torch.uint8, device="cuda")
+        res = ctx.renormalize(U64, ops, slices=S, workspace=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = ctx.renormalize(U64, ops, slices=S, workspace=ws, outs=res)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        if S == 0:
+            ref = [x.clone() for x in res]
+        err = max(float(torch.linalg.norm(a - b).item() / torch.linalg.norm(b).item()) for a, b in zip(res, ref))
+        flops = kop * (2.0 * n * n * D + 2.0 * D * D * n)
+        out["renormalisation"].append({"slices": S, "ms": ms, "tflops": flops / (ms * 1e-3) / 1e12,
+                                       "rel_err_vs_fp64": err})
+        log("[bench] renormalisation S=%d: %.2f ms for %d operators (%.1f TFLOP/s), rel err vs FP64 %.1e"
+            % (S, ms, kop, flops / (ms * 1e-3) / 1e12, err))
+    return out
+
+
 def cpu_baseline(oracle, A, B, S, G, rows_count):
     rows = sampled_rows(A.shape[0], rows_count, seed=2)
     n = A.shape[0]
@@ -451,8 +521,8 @@ def main():
     ap.add_argument("--err-rows", type=int, default=16)
     ap.add_argument("--cpu-rows", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--sections", default="gemm,dense,sparse,davidson,stability,sweep",
-                    help="comma list of gemm, dense, sparse, davidson, stability, sweep "
+    ap.add_argument("--sections", default="gemm,dense,sparse,davidson,stability,rdm,sweep",
+                    help="comma list of gemm, dense, sparse, davidson, stability, rdm, sweep "
                          "(the GEMM section always runs)")
     ap.add_argument("--gemm-configs", default="",
                     help="comma list of S:G for the GEMM section (default: S = 4..8, G in {S, S+1})")
@@ -462,6 +532,9 @@ def main():
     ap.add_argument("--heff-kop", type=int, default=64)
     ap.add_argument("--heff-steps", type=int, default=3)
     ap.add_argument("--dav-d", type=int, default=1024)
+    ap.add_argument("--rdm-n", type=int, default=2048)
+    ap.add_argument("--rdm-kop", type=int, default=16)
+    ap.add_argument("--rdm-sweeps", type=int, default=40)
     ap.add_argument("--stab-d", type=int, default=96)
     ap.add_argument("--stab-problems", type=int, default=6)
     args = ap.parse_args()
@@ -504,6 +577,8 @@ def main():
         extra["davidson"] = davidson_section(args, ozaki, ctx, torch)
     if "stability" in sections:
         extra["stability"] = stability_section(args, ozaki, ctx, torch)
+    if "rdm" in sections:
+        extra["rdm"] = rdm_section(args, ozaki, ctx, torch)
     if "sweep" in sections:
         extra["gemm_sweep"] = sweep_section(args, ozaki, ctx, torch, oracle)
     line = {

@@ -353,6 +353,68 @@ int lanczos_step(lanczos lz, davidson_info *info, void *stream);
 int lanczos_get_vector(lanczos lz, double *x_out, void *stream);
 int lanczos_destroy(lanczos lz);
 
+/* ---- DMRG truncation and renormalisation --------------------------- */
+/* The two steps beside the H_eff diagonalisation in a site update: the
+ * eigenvalue decomposition of the reduced density matrix rho = Psi Psi^T
+ * (its dominant eigenvectors form the kept basis U, "Algorithm" and the
+ * numerical-stability discussion of the paper) and the renormalisation of
+ * block operators into that basis (network contraction by GEMMs).  The
+ * paper runs both with native and with emulated FP64; both take (slices,
+ * ndiag) like ozaki_dgemm, slices = 0 meaning native FP64.
+ *
+ * rdm_eig: eigenpairs of a symmetric n x n matrix (a reduced density
+ * matrix) by two-sided block Jacobi on the device (n <= 8192; blocks of 32
+ * rows, padded to n_p = roundup(n, 64)).  A sweep runs n_p/32 - 1 rounds;
+ * a round diagonalises the 64 x 64 diagonal blocks of the paired blocks of
+ * M = W A W^T (cyclic Jacobi, one workgroup per pair, in FP64) and applies
+ * the rotations to the rows and columns of M and to the basis W: three
+ * grouped GEMMs of inner length 64 in the plan's arithmetic (emulated with
+ * (slices, ndiag), or native FP64 for slices = 0).
+ * rdm_eig_create allocates 4 n_p^2 doubles plus, when emulated, 2 S n_p^2
+ * bytes of slices.  OZ_ERR_ARG for n outside 1..8192 or bad (slices, ndiag).
+ * rdm_eig_solve: A (device, row-major, lda >= n) is read, not modified;
+ * writes the nev largest eigenvalues in decreasing order to evals (device,
+ * nev doubles) and their unit eigenvectors as the columns of Z (device,
+ * n x nev row-major, ldz >= nev).  tol = 0 selects 4 sqrt(n_p) u, with u
+ * the unit roundoff of the arithmetic (2^-53, or 2^(1-8S) when emulated).
+ * The iteration ends when a whole sweep meets no off-diagonal entry of M
+ * larger than tol |A|_F (absolute accuracy, as a tridiagonal-based solver
+ * gives), when three sweeps in a row fail to halve the best off-diagonal
+ * mass (the arithmetic's floor), or after max_sweeps.  With nev < n the
+ * couplings between two rows outside the wanted part (diagonal below the
+ * middle of the gap at the nev-th value of the previous sweep) are exempt
+ * from tol, provided their Frobenius mass cannot lift an unwanted eigenvalue
+ * above the nev-th one (Weyl's bound): the tail of a graded spectrum is not
+ * resolved beyond what the kept eigenpairs need.  info (may be NULL):
+ * sweeps run, status (OZ_CONVERGED, OZ_STAGNATED or OZ_MAX_ITER), the last
+ * sweep's largest off-diagonal entry over |A|_F and the sum of all n
+ * eigenvalues.  Results are written in all three cases.  The upper triangle
+ * of the diagonal blocks is used where symmetry is assumed; NaN or Inf in
+ * A: OZ_ERR_ARG.  Synchronises the stream.  One solve at a time per plan. */
+typedef struct rdm_eig_s *rdm_eig;
+typedef struct {
+    int32_t sweeps, status;
+    double off;    /* largest off-diagonal entry of the last sweep over |A|_F */
+    double trace;  /* sum of all n eigenvalues (discarded weight = trace - kept sum) */
+} rdm_eig_info;
+int rdm_eig_create(ozaki_ctx ctx, rdm_eig *out, int64_t n, int slices, int ndiag);
+int rdm_eig_solve(rdm_eig plan, const double *A, int64_t lda, int64_t nev, double *evals, double *Z,
+                  int64_t ldz, double tol, int max_sweeps, rdm_eig_info *info, void *stream);
+int rdm_eig_destroy(rdm_eig plan);
+
+/* ozaki_renormalize: O'_k = U^T O_k U for k < count, with U (device, n x D
+ * row-major, ldu >= D, D <= n), O_k (device pointers in the host array ops,
+ * n x n, ldo >= n) and O'_k (device pointers in outs, D x D, ldout >= D).
+ * Two GEMMs per operator, T = O_k U then U^T T, each an ozaki_dgemm with
+ * the given (slices, ndiag) (slices = 0: native FP64), so the results are
+ * those of the two ozaki_dgemm calls.  workspace: device, 256-byte aligned,
+ * ozaki_renormalize_workspace_bytes(n, D, slices, ndiag) bytes (the
+ * intermediate T and the GEMM workspace).  Asynchronous on the stream. */
+size_t ozaki_renormalize_workspace_bytes(int64_t n, int64_t D, int slices, int ndiag);
+int ozaki_renormalize(ozaki_ctx ctx, int64_t n, int64_t D, const double *U, int64_t ldu, int count,
+                      const double *const *ops, int64_t ldo, double *const *outs, int64_t ldout, int slices,
+                      int ndiag, void *workspace, size_t workspace_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

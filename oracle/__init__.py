@@ -32,6 +32,16 @@ Functions and the passage of the paper they follow:
                       subroutine; its details are not given in the paper and
                       follow the standard method).
 * ``ozaki_bound``     a-priori componentwise error bound of the emulated GEMM.
+* ``lanczos``         lowest eigenpair by Lanczos with full
+                      reorthogonalisation (the other Krylov solver the paper
+                      names and compares in its numerical-stability part).
+* ``rdm_eigh``, ``truncate``  eigenpairs of the reduced density matrix
+                      rho = psi psi^T and the truncation to the D dominant
+                      ones (the third subroutine of a site update, "Theory of
+                      TNS/DMRG"; diagonalised with a library eigensolver, as
+                      the paper does with syevd).
+* ``renormalize``     O' = U^T O U for each block operator (the network
+                      contraction of the renormalisation step, by GEMMs).
 
 Parity status: every function above is pinned by the CPU tests
 (``tests/test_oracle_pins.py``) except ``heff_sparse``'s synthetic block
@@ -537,3 +547,34 @@ def heff_matvec(L, R, diag=None, S: int = 0, G: int | None = None):
                        None if diag is None else np.asarray(diag).reshape(D, 1, D))
         return s.ravel()
     return mv
+
+
+# ----------------------------------------------------------------------------
+# Truncation and renormalisation (the site-update steps beside the H_eff
+# diagonalisation: "Theory of TNS/DMRG" and the numerical-stability part)
+# ----------------------------------------------------------------------------
+def rdm_eigh(A, nev: int | None = None):
+    """The nev largest eigenvalues of the symmetric matrix A in decreasing
+    order and their unit eigenvectors as columns (numpy's LAPACK eigh)."""
+    A = _f64(A)
+    n = A.shape[0]
+    nev = n if nev is None else nev
+    w, v = np.linalg.eigh(A)
+    order = np.argsort(-w, kind="stable")[:nev]
+    return w[order], v[:, order]
+
+
+def truncate(psi, D: int, S: int = 0, G: int | None = None):
+    """rho = psi psi^T (FP64 or emulated GEMM), its D dominant eigenpairs;
+    returns (U, kept eigenvalues, discarded weight = trace(rho) - kept sum)."""
+    psi = _f64(psi)
+    rho = gemm(psi, psi, S, G, transb="T")
+    w, U = rdm_eigh(rho, D)
+    return U, w, float(np.trace(rho) - w.sum())
+
+
+def renormalize(U, ops, S: int = 0, G: int | None = None):
+    """O'_k = U^T (O_k U) for each operator: two GEMMs per operator, FP64
+    (S = 0) or emulated, in this order."""
+    U = _f64(U)
+    return [gemm(U, gemm(_f64(O), U, S, G), S, G, transa="T") for O in ops]

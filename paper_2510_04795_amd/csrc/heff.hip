@@ -96,40 +96,6 @@ void free_plan(heff_plan p) {
     delete p;
 }
 
-// Slice descriptors for a list of blocks: exponent tasks (kExpTaskRows rows
-// or kExpTaskCols columns each) and slice tasks (32 groups x kSliceTaskKB
-// 32-wide K blocks each).
-struct SliceSet {
-    std::vector<SliceBlock> blocks;
-    std::vector<SliceTask> etasks, stasks;
-    int64_t e_total = 0, p_total = 0;
-
-    int64_t add(int64_t x_off, int64_t ld, int64_t R, int64_t K, bool trans, int S, int64_t *e_off,
-                int64_t *p_off) {
-        SliceBlock b{};
-        b.x_off = x_off;
-        b.ld = ld;
-        b.R = static_cast<int32_t>(R);
-        b.K = static_cast<int32_t>(K);
-        b.trans = trans ? 1 : 0;
-        b.Rp = round_up(R, kRowQ);
-        b.e_off = e_total;
-        b.p_off = p_total;
-        *e_off = b.e_off;
-        *p_off = b.p_off;
-        e_total += b.Rp;
-        p_total += align256(static_cast<size_t>(S) * b.Rp * round_up(K, kKB));
-        const int id = static_cast<int>(blocks.size());
-        blocks.push_back(b);
-        const int step = trans ? kExpTaskCols : kExpTaskRows;
-        for (int64_t g = 0; g < R; g += step) etasks.push_back(SliceTask{id, static_cast<int32_t>(g), 0, 0});
-        for (int64_t kb = 0; kb < ceil_div(K, kKB); kb += kSliceTaskKB)
-            for (int64_t r0 = 0; r0 < b.Rp; r0 += 32)
-                stasks.push_back(SliceTask{id, static_cast<int32_t>(r0), static_cast<int32_t>(kb), 0});
-        return id;
-    }
-};
-
 // Slice a set of blocks of x_base once (plan creation): grouped exponent and
 // slice launches into freshly allocated exponent / packed buffers.
 int slice_once(heff_plan p, const SliceSet &set, const double *x_base, int S, hipStream_t s,

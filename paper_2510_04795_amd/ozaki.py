@@ -48,6 +48,11 @@ class DavidsonInfo(ctypes.Structure):
                 ("m", ctypes.c_int32), ("status", ctypes.c_int32)]
 
 
+class RdmEigInfo(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int32), ("status", ctypes.c_int32), ("off", ctypes.c_double),
+                ("trace", ctypes.c_double)]
+
+
 def _sig(name, res, args):
     f = getattr(_lib, name)
     f.restype = res
@@ -99,6 +104,13 @@ _sig("lanczos_create", _i32, [_ptr, ctypes.POINTER(_ptr), _ptr, _ptr, _i32, _dbl
 _sig("lanczos_step", _i32, [_ptr, ctypes.POINTER(DavidsonInfo), _ptr])
 _sig("lanczos_get_vector", _i32, [_ptr, _ptr, _ptr])
 _sig("lanczos_destroy", _i32, [_ptr])
+_sig("rdm_eig_create", _i32, [_ptr, ctypes.POINTER(_ptr), _i64, _i32, _i32])
+_sig("rdm_eig_solve", _i32, [_ptr, _ptr, _i64, _i64, _ptr, _ptr, _i64, _dbl, _i32,
+                             ctypes.POINTER(RdmEigInfo), _ptr])
+_sig("rdm_eig_destroy", _i32, [_ptr])
+_sig("ozaki_renormalize_workspace_bytes", _sz, [_i64, _i64, _i32, _i32])
+_sig("ozaki_renormalize", _i32, [_ptr, _i64, _i64, _ptr, _i64, _i32, ctypes.POINTER(_ptr), _i64,
+                                 ctypes.POINTER(_ptr), _i64, _i32, _i32, _ptr, _sz, _ptr])
 
 EXPORTED = [
     "ozaki_status_string", "ozaki_last_error", "ozaki_version", "ozaki_ctx_create",
@@ -111,6 +123,8 @@ EXPORTED = [
     "heff_plan_graph_count", "heff_vector_length", "heff_flops",
     "heff_plan_destroy", "davidson_create", "davidson_step", "davidson_get_vector",
     "davidson_destroy", "lanczos_create", "lanczos_step", "lanczos_get_vector", "lanczos_destroy",
+    "rdm_eig_create", "rdm_eig_solve", "rdm_eig_destroy", "ozaki_renormalize_workspace_bytes",
+    "ozaki_renormalize",
 ]
 
 
@@ -278,6 +292,33 @@ class Context:
                                 beta, C.data_ptr(), _ld(C, "C"), slices, ndiag, wptr, wlen,
                                 _stream(stream)), "ozaki_dgemm")
         return C
+
+    def renormalize(self, U, ops, slices: int = 6, ndiag: int = 0, outs=None, workspace=None, stream=None):
+        """O'_k = U^T O_k U for every O_k in ops (two GEMMs each, emulated or
+        native FP64 by ``slices``); returns the list of D x D results."""
+        _dev_f64(U, "U")
+        n, D = U.shape
+        ops = list(ops)
+        for o in ops:
+            _dev_f64(o, "ops[k]")
+            if tuple(o.shape) != (n, n):
+                raise ValueError("every operator must be %d x %d" % (n, n))
+        if outs is None:
+            outs = [torch.empty((D, D), dtype=torch.float64, device=U.device) for _ in ops]
+        ldo = _ld(ops[0], "ops[0]") if ops else max(n, 1)
+        ldout = _ld(outs[0], "outs[0]") if outs else max(D, 1)
+        if any(_ld(o, "ops[k]") != ldo for o in ops) or any(_ld(o, "outs[k]") != ldout for o in outs):
+            raise ValueError("all operators (and all outputs) must share one leading dimension")
+        if workspace is None:
+            nb = _lib.ozaki_renormalize_workspace_bytes(n, D, slices, ndiag)
+            workspace = torch.empty(max(nb, 1), dtype=torch.uint8, device=U.device)
+        po = (_ptr * max(len(ops), 1))(*[o.data_ptr() for o in ops])
+        pr = (_ptr * max(len(outs), 1))(*[o.data_ptr() for o in outs])
+        _check(_lib.ozaki_renormalize(self.handle, n, D, U.data_ptr(), _ld(U, "U"), len(ops), po, ldo, pr,
+                                      ldout, slices, ndiag, workspace.data_ptr(),
+                                      workspace.numel() * workspace.element_size(), _stream(stream)),
+               "ozaki_renormalize")
+        return outs
 
     # ---- emulation modes --------------------------------------------------
     def auto_workspace(self, M, N, K) -> torch.Tensor | None:
@@ -534,3 +575,61 @@ class Lanczos:
             self.close()
         except Exception:
             pass
+
+
+class RdmEig:
+    """Eigenpairs of a symmetric positive semidefinite matrix (a reduced
+    density matrix) by one-sided block Jacobi on the device; the GEMMs run
+    emulated (slices >= 2) or in native FP64 (slices = 0)."""
+
+    def __init__(self, ctx: Context, n: int, slices: int = 0, ndiag: int = 0):
+        self.ctx = ctx
+        self.n = n
+        h = _ptr()
+        _check(_lib.rdm_eig_create(ctx.handle, ctypes.byref(h), n, slices, ndiag), "rdm_eig_create")
+        self.handle = h
+
+    def solve(self, A, nev: int | None = None, tol: float = 0.0, max_sweeps: int = 30, stream=None):
+        """Returns (evals [nev], Z [n, nev] with the eigenvectors as columns, info)."""
+        _dev_f64(A, "A")
+        if tuple(A.shape) != (self.n, self.n):
+            raise ValueError("A must be %d x %d" % (self.n, self.n))
+        nev = self.n if nev is None else nev
+        evals = torch.empty(max(nev, 1), dtype=torch.float64, device=A.device)[:nev]
+        Z = torch.empty((self.n, max(nev, 1)), dtype=torch.float64, device=A.device)
+        info = RdmEigInfo()
+        _check(_lib.rdm_eig_solve(self.handle, A.data_ptr(), _ld(A, "A"), nev, evals.data_ptr(), Z.data_ptr(),
+                                  Z.stride(0), tol, max_sweeps, ctypes.byref(info), _stream(stream)),
+               "rdm_eig_solve")
+        return evals, Z[:, :nev], info
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.rdm_eig_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def truncate(ctx: Context, psi, D: int, slices: int = 0, ndiag: int = 0, eig: RdmEig | None = None,
+             max_sweeps: int = 30):
+    """DMRG truncation of a two-site tensor psi (m x k, row-major): rho =
+    psi psi^T by ozaki_dgemm, its D dominant eigenpairs by RdmEig, both in
+    the arithmetic (slices, ndiag).  Returns (U [m, D], kept eigenvalues,
+    discarded weight = trace(rho) - sum of the kept ones, info)."""
+    _dev_f64(psi, "psi")
+    m = psi.size(0)
+    rho = ctx.dgemm(psi, psi, slices=slices, ndiag=ndiag, transb="T")
+    own = eig is None
+    if own:
+        eig = RdmEig(ctx, m, slices, ndiag)
+    try:
+        evals, U, info = eig.solve(rho, D, max_sweeps=max_sweeps)
+    finally:
+        if own:
+            eig.close()
+    return U, evals, info.trace - sum(evals.tolist()), info

@@ -23,6 +23,11 @@ for them with the same shapes):
 * ``davidson_problem`` - a symmetric H_eff = sum_k L_k (x) R_k + diagonal
   shift scaled to a spectral norm of about 10 Ha, with its diagonal and a
   start vector, for the Krylov eigensolver step.
+* ``two_site_psi``   - a two-site tensor reshaped to a matrix (D d) x (d D)
+  with a planted Schmidt spectrum (exponentially decaying, unit norm), for
+  the reduced-density-matrix truncation step.
+* ``block_operators`` - symmetric block operators of the enlarged block for
+  the renormalisation step.
 """
 from __future__ import annotations
 
@@ -275,4 +280,42 @@ def unflatten_sparse(prob: "HeffSparse", flat: np.ndarray) -> dict:
         n = int(prob.dims[l]) * int(prob.dims[r])
         out[(l, r)] = flat[off:off + n].reshape(int(prob.dims[l]), int(prob.dims[r]))
         off += n
+    return out
+
+
+@dataclasses.dataclass
+class TwoSitePsi:
+    psi: np.ndarray       # m x k, row-major
+    schmidt: np.ndarray   # planted Schmidt values, decreasing, sum of squares 1
+    left: np.ndarray      # m x r orthonormal left Schmidt vectors (columns)
+
+
+def _orthonormal_columns(rng: np.random.Generator, rows: int, cols: int) -> np.ndarray:
+    q, r = np.linalg.qr(rng.standard_normal((rows, cols)))
+    return q * np.sign(np.diag(r))
+
+
+def two_site_psi(m: int, k: int | None = None, tau: float | None = None, seed: int = 0) -> TwoSitePsi:
+    """psi = X diag(s) Y^T with X (m x r), Y (k x r) Haar-like orthonormal
+    columns (QR of N(0,1) matrices, drawn in that order) and r = min(m, k);
+    s_i^2 proportional to exp(-i / tau) (default tau = m / 64, so the weight
+    beyond the leading quarter of the spectrum is about e^-16), normalised to
+    unit Frobenius norm.  The eigenvalues of rho = psi psi^T are s_i^2."""
+    k = m if k is None else k
+    r = min(m, k)
+    tau = m / 64.0 if tau is None else tau
+    rng = np.random.default_rng(seed)
+    X = _orthonormal_columns(rng, m, r)
+    Y = _orthonormal_columns(rng, k, r)
+    w = np.exp(-np.arange(r) / tau)
+    s = np.sqrt(w / w.sum())
+    return TwoSitePsi(psi=np.ascontiguousarray((X * s) @ Y.T), schmidt=s, left=X)
+
+
+def block_operators(n: int, count: int, seed: int = 0) -> np.ndarray:
+    """count symmetric n x n operators sym(N(0,1)) / sqrt(n) (spectral norm ~ 2)."""
+    rng = np.random.default_rng(seed)
+    out = np.empty((count, n, n))
+    for c in range(count):
+        out[c] = symmetrize(rng.standard_normal((n, n))) / math.sqrt(n)
     return out

@@ -15,7 +15,7 @@ def declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\**\s*([a-z_0-9]+)\s*\(", src, flags=re.M)
-    return sorted(set(n for n in names if n.startswith(("ozaki_", "heff_", "davidson_", "lanczos_"))))
+    return sorted(set(n for n in names if n.startswith(("ozaki_", "heff_", "davidson_", "lanczos_", "rdm_"))))
 
 
 @pytest.fixture(scope="module")

@@ -588,3 +588,47 @@ def test_rho_closed_forms():
     assert np.isnan(oracle.rho(X))
     assert oracle.choose_slices(X, np.ones((64, 3))) == (7, 7)
     assert oracle.choose_slices(np.zeros((4, 8)), np.ones((8, 4))) == (2, 2)
+
+
+# ---- truncation and renormalisation ------------------------------------------
+def test_truncate_planted_spectrum():
+    """rho = psi psi^T of a planted Schmidt decomposition: its eigenvalues are
+    the squared Schmidt values, the discarded weight their tail sum and the
+    kept eigenvectors span the planted left vectors (closed forms of the
+    construction)."""
+    t = wl.two_site_psi(96, 80, tau=6.0, seed=3)
+    s2 = t.schmidt ** 2
+    for D in (1, 20, 80):
+        U, w, dw = oracle.truncate(t.psi, D)
+        assert np.max(np.abs(w - s2[:D])) < 1e-15
+        assert abs(dw - s2[D:].sum()) < 1e-14
+        sv = np.linalg.svd(t.left[:, :D].T @ U, compute_uv=False)
+        assert np.all(np.abs(sv - 1) < 1e-10)
+    # emulated rho: the eigenvalue error follows the slice count
+    for S, tol in ((7, 1e-15), (4, 1e-8), (3, 1e-6)):
+        U, w, dw = oracle.truncate(t.psi, 20, S=S)
+        assert np.max(np.abs(w - s2[:20])) < tol, S
+
+
+def test_renormalize_selector_is_exact():
+    """U = columns idx of the identity: U^T O U = O[idx][:, idx] exactly, for
+    FP64 and every slice count (integer entries below 2^10 fit any slicing);
+    O is not symmetric, so a transposed operand fails."""
+    rng = np.random.default_rng(5)
+    n, D = 70, 23
+    ops = [rng.integers(-1000, 1001, size=(n, n)).astype(np.float64) for _ in range(3)]
+    idx = np.sort(rng.choice(n, D, replace=False))[::-1]
+    U = np.zeros((n, D))
+    U[idx, np.arange(D)] = 1.0
+    for S in (0, 2, 5, 8):
+        out = oracle.renormalize(U, ops, S=S)
+        for O, Op in zip(ops, out):
+            assert np.array_equal(Op, O[np.ix_(idx, idx)]), S
+
+
+def test_renormalize_orthogonal_similarity():
+    """A full orthogonal U keeps the spectrum of a symmetric operator."""
+    ops = wl.block_operators(60, 2, seed=6)
+    U = np.linalg.qr(np.random.default_rng(7).standard_normal((60, 60)))[0]
+    for O, Op in zip(ops, oracle.renormalize(U, ops)):
+        assert np.max(np.abs(np.linalg.eigvalsh(Op) - np.linalg.eigvalsh(O))) < 1e-13
