@@ -541,6 +541,22 @@ def rdm_section(args, ozaki, ctx, torch):
     return out
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def device_record(torch):
+    p = torch.cuda.get_device_properties(0)
+    return {"name": p.name, "arch": getattr(p, "gcnArchName", None), "compute_units": p.multi_processor_count,
+            "memory_gib": round(p.total_memory / 2 ** 30, 1)}
+
+
 def cpu_baseline(oracle, A, B, S, G, rows_count):
     rows = sampled_rows(A.shape[0], rows_count, seed=2)
     n = A.shape[0]
@@ -548,7 +564,7 @@ def cpu_baseline(oracle, A, B, S, G, rows_count):
     oracle.ozaki_dgemm(A[rows], B, S, G)
     t = time.perf_counter() - t0
     return {"value": 2.0 * len(rows) * n * n / t / 1e12, "unit": "TFLOP/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
+            "cpu_model": cpu_model(), "kind": "oracle",
             "sample": "emulated GEMM (S=%d, G=%d) of %d sampled rows of A (n=%d) times all of B, "
                       "%.1f s; rate scaled as 2*rows*n*n/time" % (S, G, len(rows), n, t)}
 
@@ -665,6 +681,7 @@ def main():
         "at_1e-12": gemm["at_1e-12"],
         "automatic_width": gemm["auto"],
         "cpu_baseline": cpu,
+        "device": device_record(torch),
         "paper_context": "The paper prints no absolute throughput for the emulated DGEMM or H_eff (its "
                          "figures are not available). In text, on DGX B200 with NVIDIA's pre-release "
                          "cuBLAS emulation: eager mode makes the H_eff diagonalisation markedly slower "
