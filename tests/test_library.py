@@ -78,3 +78,26 @@ def test_errors_without_device(lib):
     if not torch.cuda.is_available():
         h = ctypes.c_void_p()
         assert ozaki._lib.ozaki_ctx_create(ctypes.byref(h), 0) == -3
+
+
+def test_new_entry_points_reject_bad_arguments_on_the_host():
+    """The Lanczos, RDM eigensolver and renormalisation entry points check
+    their handles and sizes before touching a device."""
+    from paper_2510_04795_amd import ozaki
+    L = ozaki._lib
+    h = ctypes.c_void_p()
+    assert L.lanczos_create(None, ctypes.byref(h), None, None, 32, 1e-8, 300, None) == -1
+    assert L.lanczos_step(None, None, None) == -1
+    assert L.lanczos_get_vector(None, None, None) == -1
+    assert L.lanczos_destroy(None) == 0
+    assert L.rdm_eig_create(None, ctypes.byref(h), 16, 0, 0) == -1
+    assert b"ctx" in L.ozaki_last_error()
+    assert L.rdm_eig_solve(None, None, 16, 4, None, None, 4, 0.0, 10, None, None) == -1
+    assert L.rdm_eig_destroy(None) == 0
+    assert L.ozaki_renormalize(None, 100, 20, None, 20, 1, None, 100, None, 20, 0, 0, None, 0, None) == -1
+    # workspace: the intermediate T (n x D doubles, 256-byte aligned), plus the GEMM workspace when emulated
+    t = (100 * 20 * 8 + 255) // 256 * 256
+    assert L.ozaki_renormalize_workspace_bytes(100, 20, 0, 0) == t
+    w6 = L.ozaki_renormalize_workspace_bytes(100, 20, 6, 0)
+    assert w6 == t + max(L.ozaki_dgemm_workspace_bytes(100, 20, 100, 6, 0),
+                         L.ozaki_dgemm_workspace_bytes(20, 20, 100, 6, 0))
