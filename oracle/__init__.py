@@ -42,11 +42,19 @@ Functions and the passage of the paper they follow:
                       the paper does with syevd).
 * ``renormalize``     O' = U^T O U for each block operator (the network
                       contraction of the renormalisation step, by GEMMs).
+* ``rho``, ``predicted_emulated_error``, ``predicted_native_error``,
+  ``choose_slices``   the automatic mantissa width the paper names in
+                      "Numerical procedure" without giving its rule: operand
+                      statistics, predicted errors and the cheapest (S, G) at
+                      native accuracy (the rule is this implementation's own).
 
 Parity status: every function above is pinned by the CPU tests
-(``tests/test_oracle_pins.py``) except ``heff_sparse``'s synthetic block
-structure, whose composition is checked against an exact rational
-computation on a tiny case only.
+(``tests/test_oracle_pins.py``), with two limits.  ``heff_sparse``'s
+synthetic block structure is checked against an exact rational computation
+on a tiny case only.  ``choose_slices`` has no rule in the paper to pin
+against ("parity unpinned" for the rule itself): it is pinned by tests of
+its purpose (the chosen width reaches native accuracy and the next cheaper
+one does not) and its statistics by closed forms.
 """
 from __future__ import annotations
 
