@@ -260,3 +260,22 @@ def test_tune_picks_a_built_variant(oz):
     ctx.set_variant(6, 0, -1)
     with pytest.raises(ozaki.OzakiError):
         ctx.set_variant(8, 15, 3)   # 2x2 blocks of 15 accumulator sets are not built
+
+
+@pytest.mark.parametrize("S,G", [(2, 3), (5, 5), (8, 15)])
+def test_dgemm_vector_shapes_zero_rows_and_extreme_exponents(oz, S, G):
+    """M = 1 and N = 1 products, a zero row of A and a zero column of B,
+    subnormal entries and entries near 2^900 and 2^-1000 in the same operands: the
+    emulated GEMM stays bit-exact with the oracle."""
+    ozaki, ctx, torch = oz
+    rng = np.random.default_rng(40 + S)
+    A = rng.standard_normal((37, 301)) * np.ldexp(1.0, rng.integers(-20, 20, size=(37, 301)))
+    B = rng.standard_normal((301, 45)) * np.ldexp(1.0, rng.integers(-20, 20, size=(301, 45)))
+    A[5] = 0.0
+    B[:, 7] = 0.0
+    A[9, :4] = [5e-324, -1e-310, 2.2e-308, 1e-300]
+    A[11] = np.ldexp(A[11], 900)
+    B[:, 13] = np.ldexp(B[:, 13], -1000)
+    for (a, b) in [(A, B), (A[:1], B), (A, B[:, :1]), (A[:1], B[:, :1])]:
+        got = ctx.dgemm(dev(torch, a), dev(torch, b), slices=S, ndiag=G).cpu().numpy()
+        assert_bitexact(got, oracle.ozaki_dgemm(a, b, S, G), "shape %s x %s" % (a.shape, b.shape))
