@@ -52,8 +52,18 @@ __global__ __launch_bounds__(256) void k_row_exponents(const double *__restrict_
     const int64_t r = static_cast<int64_t>(blockIdx.x) * 4 + (threadIdx.x >> 6);
     if (r >= R) return;
     const double *row = X + r * ld;
-    double mu = 0.0;
-    for (int64_t k = lane; k < K; k += 64) mu = combine_max(mu, abs_or_nan(row[k]));
+    // four loads in flight per lane; the maximum does not depend on the order
+    double m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
+    int64_t k = lane;
+    for (; k + 192 < K; k += 256) {
+        const double a = row[k], b = row[k + 64], c = row[k + 128], d = row[k + 192];
+        m0 = combine_max(m0, abs_or_nan(a));
+        m1 = combine_max(m1, abs_or_nan(b));
+        m2 = combine_max(m2, abs_or_nan(c));
+        m3 = combine_max(m3, abs_or_nan(d));
+    }
+    for (; k < K; k += 64) m0 = combine_max(m0, abs_or_nan(row[k]));
+    double mu = combine_max(combine_max(m0, m1), combine_max(m2, m3));
     for (int off = 32; off >= 1; off >>= 1) mu = combine_max(mu, __shfl_xor(mu, off, 64));
     if (lane == 0) e[r] = finish_exponent(mu, flag);
 }
@@ -68,8 +78,20 @@ __global__ __launch_bounds__(256) void k_col_partial(const double *__restrict__ 
     if (c >= R) return;
     const int64_t k0 = static_cast<int64_t>(blockIdx.y) * kColChunk;
     const int64_t k1 = k0 + kColChunk < K ? k0 + kColChunk : K;
-    double mu = 0.0;
-    for (int64_t k = k0; k < k1; ++k) mu = combine_max(mu, abs_or_nan(X[k * ld + c]));
+    // eight loads in flight per lane; the maximum does not depend on the order
+    double m[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int64_t k = k0;
+    for (; k + 8 <= k1; k += 8) {
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = X[(k + q) * ld + c];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) m[q] = combine_max(m[q], abs_or_nan(v[q]));
+    }
+    for (; k < k1; ++k) m[0] = combine_max(m[0], abs_or_nan(X[k * ld + c]));
+    double mu = m[0];
+#pragma unroll
+    for (int q = 1; q < 8; ++q) mu = combine_max(mu, m[q]);
     part[static_cast<int64_t>(blockIdx.y) * R + c] = mu;
 }
 
@@ -121,6 +143,18 @@ __global__ __launch_bounds__(256) void k_col_sumsq_final(const double *__restric
     ss[c] = acc;
 }
 
+// Balanced base-256 digits of one element, most significant first.
+template <int S>
+__device__ inline void digits(double x, int32_t e, int (&d)[S]) {
+    long long X = static_cast<long long>(rint(ldexp(x, 8 * S - 1 - e)));
+#pragma unroll
+    for (int t = S - 1; t >= 1; --t) {
+        d[t] = static_cast<int>((X + 128) & 255) - 128;
+        X = (X - d[t]) >> 8;
+    }
+    d[0] = static_cast<int>(X);
+}
+
 // Balanced base-256 digits of RNE(x 2^(8S-1-e)), most significant first, as
 // bytes of four consecutive elements packed into one word per slice.
 template <int S>
@@ -154,29 +188,63 @@ __global__ __launch_bounds__(256) void k_slice(const double *__restrict__ X, int
     const int64_t r0 = static_cast<int64_t>(blockIdx.x) * 32;
     const int64_t kb = blockIdx.y;
     const int64_t k0 = kb * 32;
-    int r, kq;
     if (TRANS) {
-        r = t & 31;
-        kq = t >> 5;
+        // lanes take consecutive groups (columns): every load is coalesced
+        const int r = t & 31, kq = t >> 5;
+        const int64_t gr = r0 + r;
+        double x[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int64_t k = k0 + kq * 4 + q;
+            x[q] = (gr < R && k < K) ? X[k * ld + gr] : 0.0;
+        }
+        uint32_t w[S];
+        slice4<S>(x, gr < R ? e[gr] : 0, w);
+        const int c = kq >> 2, word = kq & 3;
+#pragma unroll
+        for (int s = 0; s < S; ++s) reinterpret_cast<uint32_t *>(&tile[s * 2 + c][r])[word] = w[s];
     } else {
-        r = t >> 3;
-        kq = t & 7;
-    }
-    const int64_t gr = r0 + r;
-    double x[4];
+        // 16 lanes per row, two consecutive elements each (one 16-byte load
+        // when the block is whole and aligned), rows r and r + 16; the two
+        // bytes per slice of a lane pair make one word of the tile
+        const int kp = t & 15;
+        const bool full = r0 + 32 <= R && k0 + 32 <= K && (ld & 1) == 0 &&
+                          (reinterpret_cast<uintptr_t>(X) & 15) == 0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int64_t k = k0 + kq * 4 + q;
-        x[q] = 0.0;
-        if (gr < R && k < K) x[q] = TRANS ? X[k * ld + gr] : X[gr * ld + k];
-    }
-    const int32_t ee = gr < R ? e[gr] : 0;
-    uint32_t w[S];
-    slice4<S>(x, ee, w);
-    const int c = kq >> 2;     // which 16-byte half of the 32-wide block
-    const int word = kq & 3;   // which 4-byte word inside the half
+        for (int h = 0; h < 2; ++h) {
+            const int r = (t >> 4) + 16 * h;
+            const int64_t gr = r0 + r;
+            const int64_t k = k0 + 2 * kp;
+            double x0 = 0.0, x1 = 0.0;
+            if (full) {
+                const double2 v = *reinterpret_cast<const double2 *>(X + gr * ld + k);
+                x0 = v.x;
+                x1 = v.y;
+            } else if (gr < R) {
+                if (k < K) x0 = X[gr * ld + k];
+                if (k + 1 < K) x1 = X[gr * ld + k + 1];
+            }
+            const int32_t ee = gr < R ? e[gr] : 0;
+            uint32_t half[S];
 #pragma unroll
-    for (int s = 0; s < S; ++s) reinterpret_cast<uint32_t *>(&tile[s * 2 + c][r])[word] = w[s];
+            for (int s = 0; s < S; ++s) half[s] = 0;
+            if (ee != kExpBad) {
+                int d0[S], d1[S];
+                digits<S>(x0, ee, d0);
+                digits<S>(x1, ee, d1);
+#pragma unroll
+                for (int s = 0; s < S; ++s)
+                    half[s] = (static_cast<uint32_t>(d0[s]) & 0xffu) | ((static_cast<uint32_t>(d1[s]) & 0xffu) << 8);
+            }
+            const int kq = kp >> 1, c = kq >> 2, word = kq & 3;
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const uint32_t other = static_cast<uint32_t>(__shfl_down(static_cast<int>(half[s]), 1, 64));
+                if ((kp & 1) == 0)
+                    reinterpret_cast<uint32_t *>(&tile[s * 2 + c][r])[word] = half[s] | (other << 16);
+            }
+        }
+    }
     __syncthreads();
     // write 2S runs of 32 rows x 16 bytes
     uint4 *out = reinterpret_cast<uint4 *>(packed);
