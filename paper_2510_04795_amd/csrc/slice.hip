@@ -345,37 +345,10 @@ __global__ __launch_bounds__(256) void k_slice_grouped(const SliceBlock *__restr
     const int32_t *e = e_base + bl.e_off;
     const int t = threadIdx.x;
     const int64_t r0 = tk.a;
-    int r, kq;
-    if (bl.trans) {
-        r = t & 31;
-        kq = t >> 5;
-    } else {
-        r = t >> 3;
-        kq = t & 7;
-    }
-    const int64_t gr = r0 + r;
-    const int32_t ee = gr < bl.R ? e[gr] : 0;
     const int nkb = (bl.K + kKB - 1) / kKB;
     const int kb_end = tk.b + kSliceTaskKB < nkb ? tk.b + kSliceTaskKB : nkb;
-    auto load = [&](int kb, double (&x)[4]) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int64_t k = static_cast<int64_t>(kb) * 32 + kq * 4 + q;
-            x[q] = 0.0;
-            if (gr < bl.R && k < bl.K) x[q] = bl.trans ? X[k * bl.ld + gr] : X[gr * bl.ld + k];
-        }
-    };
-    double x[4], nx[4];
-    load(tk.b, x);
     uint4 *out = reinterpret_cast<uint4 *>(p_base + bl.p_off);
-    const int c = kq >> 2;
-    const int word = kq & 3;
-    for (int kb = tk.b; kb < kb_end; ++kb) {
-        if (kb + 1 < kb_end) load(kb + 1, nx);
-        uint32_t w[S];
-        slice4<S>(x, ee, w);
-#pragma unroll
-        for (int s = 0; s < S; ++s) reinterpret_cast<uint32_t *>(&tile[s * 2 + c][r])[word] = w[s];
+    auto flush = [&](int kb) {
         __syncthreads();
         for (int q = t; q < S * 2 * 32; q += 256) {
             const int sc = q >> 5;
@@ -383,6 +356,88 @@ __global__ __launch_bounds__(256) void k_slice_grouped(const SliceBlock *__restr
             out[(static_cast<int64_t>(kb) * S * 2 + sc) * bl.Rp + r0 + rr] = tile[sc][rr];
         }
         __syncthreads();
+    };
+    if (bl.trans) {
+        // lanes take consecutive groups (columns): every load is coalesced
+        const int r = t & 31, kq = t >> 5;
+        const int64_t gr = r0 + r;
+        const int32_t ee = gr < bl.R ? e[gr] : 0;
+        auto load = [&](int kb, double (&x)[4]) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int64_t k = static_cast<int64_t>(kb) * 32 + kq * 4 + q;
+                x[q] = (gr < bl.R && k < bl.K) ? X[k * bl.ld + gr] : 0.0;
+            }
+        };
+        double x[4], nx[4];
+        load(tk.b, x);
+        const int c = kq >> 2, word = kq & 3;
+        for (int kb = tk.b; kb < kb_end; ++kb) {
+            if (kb + 1 < kb_end) load(kb + 1, nx);
+            uint32_t w[S];
+            slice4<S>(x, ee, w);
+#pragma unroll
+            for (int s = 0; s < S; ++s) reinterpret_cast<uint32_t *>(&tile[s * 2 + c][r])[word] = w[s];
+            flush(kb);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) x[q] = nx[q];
+        }
+        return;
+    }
+    // row groups: 16 lanes per row, two consecutive elements each (one
+    // 16-byte load when aligned and inside the block), rows r and r + 16;
+    // the two bytes per slice of a lane pair make one word of the tile
+    const int kp = t & 15;
+    const int rA = t >> 4;
+    const bool aligned = (bl.ld & 1) == 0 && (reinterpret_cast<uintptr_t>(X) & 15) == 0;
+    int32_t ee[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) ee[h] = r0 + rA + 16 * h < bl.R ? e[r0 + rA + 16 * h] : 0;
+    auto load = [&](int kb, double (&x)[4]) {
+        const int64_t k = static_cast<int64_t>(kb) * 32 + 2 * kp;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int64_t gr = r0 + rA + 16 * h;
+            x[2 * h] = 0.0;
+            x[2 * h + 1] = 0.0;
+            if (gr < bl.R) {
+                if (aligned && k + 1 < bl.K) {
+                    const double2 v = *reinterpret_cast<const double2 *>(X + gr * bl.ld + k);
+                    x[2 * h] = v.x;
+                    x[2 * h + 1] = v.y;
+                } else {
+                    if (k < bl.K) x[2 * h] = X[gr * bl.ld + k];
+                    if (k + 1 < bl.K) x[2 * h + 1] = X[gr * bl.ld + k + 1];
+                }
+            }
+        }
+    };
+    double x[4], nx[4];
+    load(tk.b, x);
+    const int kq = kp >> 1, c = kq >> 2, word = kq & 3;
+    for (int kb = tk.b; kb < kb_end; ++kb) {
+        if (kb + 1 < kb_end) load(kb + 1, nx);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            uint32_t half[S];
+#pragma unroll
+            for (int s = 0; s < S; ++s) half[s] = 0;
+            if (ee[h] != kExpBad) {
+                int d0[S], d1[S];
+                digits<S>(x[2 * h], ee[h], d0);
+                digits<S>(x[2 * h + 1], ee[h], d1);
+#pragma unroll
+                for (int s = 0; s < S; ++s)
+                    half[s] = (static_cast<uint32_t>(d0[s]) & 0xffu) | ((static_cast<uint32_t>(d1[s]) & 0xffu) << 8);
+            }
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const uint32_t other = static_cast<uint32_t>(__shfl_down(static_cast<int>(half[s]), 1, 64));
+                if ((kp & 1) == 0)
+                    reinterpret_cast<uint32_t *>(&tile[s * 2 + c][rA + 16 * h])[word] = half[s] | (other << 16);
+            }
+        }
+        flush(kb);
 #pragma unroll
         for (int q = 0; q < 4; ++q) x[q] = nx[q];
     }
