@@ -369,12 +369,14 @@ def heff_section(args, ozaki, ctx, torch, name, layout, Lf, Rf, pf, triples, sli
              "tflops": plan.flops / t / 1e12, "rel_frobenius_vs_fp64": err, "plan_s": tplan,
              "rel_err_vs_dd_sampled": dd_err(sig),
              "cold_ms": (t + tplan) * 1e3, "phase_ms": phs,
+             "tile_variants": list(plan.variants), "streamed_launches": list(plan.launches),
              "int8_frac_pair_phases": (P * plan.flops / ((phs.get("heff_L", 0) + phs.get("heff_R", 0)) * 1e-3)
                                        / 1e12 / INT8_PEAK_TOPS) if phs else None}
         res.append(r)
-        log("[bench] %s S=%d G=%d: %.3f ms/apply  %.2f TFLOP/s  err vs fp64 %.2e  vs dd %s  phases %s"
+        log("[bench] %s S=%d G=%d: %.3f ms/apply  %.2f TFLOP/s  err vs fp64 %.2e  vs dd %s  phases %s  "
+            "variants %s streamed %s"
             % (name, S, G, t * 1e3, r["tflops"], err, r["rel_err_vs_dd_sampled"],
-               {k: round(v, 3) for k, v in phs.items()}))
+               {k: round(v, 3) for k, v in phs.items()}, plan.variants, plan.launches))
         plan.close()
         del keep
     out["emulated"] = res

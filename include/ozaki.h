@@ -195,6 +195,15 @@ int ozaki_ctx_get_variant(ozaki_ctx ctx, int slices, int ndiag);
  * keeps the fastest (default on; a variant fixed with ozaki_ctx_set_variant
  * takes precedence). */
 int ozaki_ctx_set_autotune(ozaki_ctx ctx, int enable);
+/* How heff plans created afterwards launch their two grouped pair phases:
+ * 0 = one workgroup per output tile; k > 0 = the streamed kernel, in which
+ * as many workgroups as fit at once on min(k, number of CUs) compute units
+ * walk the tile list and the first K block of each (tile, term) item is
+ * loaded during the last block of the item before it; -1 (default) = when
+ * autotuning is on, time both for the first phase if its items average at
+ * most 16 K blocks (the streamed kernel saves a fixed cost per item), else 0.
+ * Results are bit-identical in every mode.  OZ_ERR_ARG for mode < -1. */
+int ozaki_ctx_set_heff_launch(ozaki_ctx ctx, int mode);
 /* Time every built variant of this GEMM (alpha = 1, beta = 0 into C, one
  * warm-up and three timed calls each) and fix the fastest for (slices,
  * ndiag) in the context.  ms_out (host, nullable, one slot per variant) gets
@@ -287,7 +296,10 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *layout,
  * per plan; evicting the least recently used one synchronises `stream`.
  * The launches are issued directly instead when phase timing is on, when
  * `stream` is being captured by the caller, or after
- * heff_plan_set_graphs(plan, 0).  Results are identical either way. */
+ * heff_plan_set_graphs(plan, 0).  Results are identical either way.
+ * Applies of one plan must not overlap in time (the plan's slice buffers
+ * and tile counters are shared by its applies): issue them on one stream
+ * or order the streams. */
 int heff_apply(heff_plan plan, const double *psi, double *sigma, void *stream);
 /* Enable (default) or disable graph replay in heff_apply. */
 int heff_plan_set_graphs(heff_plan plan, int enable);
@@ -296,6 +308,9 @@ int heff_plan_graph_count(heff_plan plan);
 /* Tile variants the plan's two grouped phases use (emulated plans; -1 for
  * native FP64 plans). */
 int heff_plan_variants(heff_plan plan, int32_t *first, int32_t *second);
+/* Launch kind of the plan's two grouped phases (0 one workgroup per tile,
+ * 1 streamed; -1 for native FP64 plans). */
+int heff_plan_launches(heff_plan plan, int32_t *first, int32_t *second);
 /* Total elements of psi for the plan's layout. */
 int64_t heff_vector_length(heff_plan plan);
 /* FP64-equivalent flops of one heff_apply (2 m n k summed over all GEMMs). */

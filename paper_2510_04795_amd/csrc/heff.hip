@@ -516,6 +516,11 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
         (rc = upload(P, outsR, &doR))) { free_plan(P); return rc; }
     P->argsL.terms = dmL; P->argsL.outs = doL; P->argsL.mode = kModeGemm;
     P->argsR.terms = dmR; P->argsR.outs = doR; P->argsR.mode = kModeAccum;
+    {
+        // tile counters of the streamed launches (zero; every launch leaves them zero)
+        const std::vector<int32_t> zq(kStreamQueueInts, 0);
+        if ((rc = upload(P, zq, &P->argsL.queue)) || (rc = upload(P, zq, &P->argsR.queue))) { free_plan(P); return rc; }
+    }
 
     const int fixed = ctx->variant[S][G];
     std::vector<int> cands;
@@ -539,48 +544,89 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
         hipEventCreate(&ev0);
         hipEventCreate(&ev1);
     }
-    // candidates: tile variant x tile order (the XCD order first, the default)
-    std::vector<std::pair<int, bool>> runs;
-    for (int v : cands) {
-        runs.push_back({v, true});
-        if (tuning) runs.push_back({v, false});
-    }
-    for (auto [v, xcd] : runs) {
-        std::vector<TileDesc> tl, tr;
-        std::vector<int64_t> cl, cr;
-        tiles_for(v, xcd, &tl, &tr, &cl, &cr);
-        TileDesc *dtl, *dtr;
-        if ((rc = upload(P, tl, &dtl)) || (rc = upload(P, tr, &dtr))) { if (tmp_sigma) hipFree(tmp_sigma); free_plan(P); return rc; }
+    // candidates: tile variant x tile order (the XCD order first, the
+    // default) x launch (one workgroup per tile, or the streamed kernel whose
+    // resident workgroups walk the list and prefetch across items)
+    struct Run { int v; bool xcd; bool stream; };
+    constexpr double kStreamMaxMeanBlocks = 16.0;
+    std::vector<Run> runs;
+    std::vector<bool> launches;
+    if (ctx->heff_launch >= 0) launches.push_back(ctx->heff_launch > 0);
+    else if (tuning) launches = {false, true};
+    else launches.push_back(false);
+    for (int v : cands)
+        for (bool xcd : {true, false}) {
+            if (!xcd && !tuning) break;
+            for (bool st : launches) runs.push_back({v, xcd, st});
+        }
+    int32_t last_key = -1;  // tile lists are built once per (variant, order) and shared by both launches
+    TileDesc *dtl = nullptr, *dtr = nullptr;
+    std::vector<int64_t> cl, cr;
+    int32_t ntl = 0, ntr = 0;
+    for (auto [v, xcd, st] : runs) {
+        const int32_t key = v * 2 + (xcd ? 1 : 0);
+        if (key != last_key) {
+            std::vector<TileDesc> tl, tr;
+            cl.clear();
+            cr.clear();
+            tiles_for(v, xcd, &tl, &tr, &cl, &cr);
+            if ((rc = upload(P, tl, &dtl)) || (rc = upload(P, tr, &dtr))) { if (tmp_sigma) hipFree(tmp_sigma); free_plan(P); return rc; }
+            ntl = static_cast<int32_t>(tl.size());
+            ntr = static_cast<int32_t>(tr.size());
+            last_key = key;
+        }
+        const int32_t scus = !st ? 0 : ctx->heff_launch > 0 ? std::min(ctx->heff_launch, ctx->num_cu) : ctx->num_cu;
         if (!tuning) {
-            P->argsL.tiles = dtl; P->argsL.ntiles = static_cast<int32_t>(tl.size()); P->varL = v;
-            P->argsR.tiles = dtr; P->argsR.ntiles = static_cast<int32_t>(tr.size()); P->varR = v;
+            P->argsL.tiles = dtl; P->argsL.ntiles = ntl; P->varL = v; P->argsL.stream_cus = scus;
+            P->argsR.tiles = dtr; P->argsR.ntiles = ntr; P->varR = v; P->argsR.stream_cus = scus;
             break;
         }
         for (int ph = 0; ph < 2; ++ph) {
             const std::vector<int64_t> &cost = ph == 0 ? cl : cr;
-            int64_t total = 0;
-            for (auto c : cost) total += c;
-            const int prefix = static_cast<int>(std::min<size_t>(cost.size(), static_cast<size_t>(8 * ctx->num_cu)));
+            int64_t total = 0, items = 0;
+            for (auto c : cost) {
+                total += c;
+                items += c > 0;
+            }
+            if (st && ctx->heff_launch < 0) {
+                // Timed choice: the streamed kernel saves a fixed cost per
+                // (tile, term) item (the first K block's load, the exposed
+                // epilogue), so it is a candidate for the GEMM-mode phase
+                // with short items only; in the accumulating phase it was
+                // slower at every measured shape.
+                const PairShape sh = pair_shape(S, G, v);
+                const double mean_kb = items ? static_cast<double>(total) / items / (sh.bm * sh.bn) : 0.0;
+                if (ph == 1 || mean_kb > kStreamMaxMeanBlocks) continue;
+            }
+            // 64 tiles per CU: whole lists of block-sparse batches, a few
+            // percent of large dense ones (a short prefix of a longest-first
+            // list holds only its longest items and misjudges launches whose
+            // gain is per item)
+            const int prefix = static_cast<int>(std::min<size_t>(cost.size(), static_cast<size_t>(64 * ctx->num_cu)));
             int64_t part = 0;
             for (int i = 0; i < prefix; ++i) part += cost[i];
             PairArgs a = ph == 0 ? P->argsL : P->argsR;
             a.tiles = ph == 0 ? dtl : dtr;
             a.ntiles = prefix;
+            a.stream_cus = scus;
             if (ph == 1) a.out_base = static_cast<double *>(tmp_sigma);
+            // a warm-up launch, then the faster of two timed ones
             float ms = 0.f;
-            for (int rep = 0; rep < 2; ++rep) {
+            for (int rep = 0; rep < 3; ++rep) {
+                float r = 0.f;
                 hipEventRecord(ev0, s);
                 if ((e = launch_pair_grouped(S, G, v, a, s)) != hipSuccess) { hipFree(tmp_sigma); free_plan(P); return hip_fail(e, "heff_plan_create: tuning launch"); }
                 hipEventRecord(ev1, s);
                 hipEventSynchronize(ev1);
-                hipEventElapsedTime(&ms, ev0, ev1);
+                hipEventElapsedTime(&r, ev0, ev1);
+                if (rep == 1 || (rep > 1 && r < ms)) ms = r;
             }
             const double est = part > 0 ? ms * static_cast<double>(total) / static_cast<double>(part) : 0.0;
             double &best = ph == 0 ? bestL : bestR;
             if (best < 0 || est < best) {
                 best = est;
-                if (ph == 0) { P->argsL.tiles = dtl; P->argsL.ntiles = static_cast<int32_t>(tl.size()); P->varL = v; }
-                else { P->argsR.tiles = dtr; P->argsR.ntiles = static_cast<int32_t>(tr.size()); P->varR = v; }
+                if (ph == 0) { P->argsL.tiles = dtl; P->argsL.ntiles = ntl; P->varL = v; P->argsL.stream_cus = scus; }
+                else { P->argsR.tiles = dtr; P->argsR.ntiles = ntr; P->varR = v; P->argsR.stream_cus = scus; }
             }
         }
     }
@@ -722,6 +768,13 @@ int heff_plan_variants(heff_plan P, int32_t *first, int32_t *second) {
     if (!P) return fail(OZ_ERR_ARG, "heff_plan_variants: plan is NULL");
     if (first) *first = P->varL;
     if (second) *second = P->varR;
+    return OZ_OK;
+}
+
+int heff_plan_launches(heff_plan P, int32_t *first, int32_t *second) {
+    if (!P) return fail(OZ_ERR_ARG, "heff_plan_launches: plan is NULL");
+    if (first) *first = P->S ? (P->argsL.stream_cus > 0 ? 1 : 0) : -1;
+    if (second) *second = P->S ? (P->argsR.stream_cus > 0 ? 1 : 0) : -1;
     return OZ_OK;
 }
 

@@ -64,6 +64,10 @@ enum PairMode : int32_t {
     kModeQ64 = 3,      // one term over one K chunk; store (qw_first) or add its sums to Qw
 };
 
+// Counters of one streamed launch: a tile counter per XCD, then the number
+// of workgroups that found their queue empty.
+constexpr int kStreamQueueInts = 16;
+
 struct PairArgs {
     // grouped launch
     const TileDesc *tiles;
@@ -84,6 +88,11 @@ struct PairArgs {
     int64_t *Qw;
     int64_t qw_ld;         // leading dimension of one Qw plane (tiles_n * BN)
     int64_t qw_plane;      // elements per Qw plane
+    // grouped: 0 = one workgroup per listed tile; > 0 = the streamed kernel,
+    // resident workgroups on this many compute units taking tiles from
+    // `queue` (kStreamQueueInts zeroed ints, left zeroed by every launch)
+    int32_t stream_cus;
+    int32_t *queue;
 };
 
 // FP64 GEMM term: op(A) (M x K) times op(B) (K x N), both plain FP64.

@@ -23,6 +23,8 @@
 // padded row: they only feed outputs that are never stored.
 #pragma once
 
+#include <algorithm>
+
 #include "internal.h"
 
 namespace oz {
@@ -52,7 +54,11 @@ struct Cfg {
 // registers stay the same for the whole loop.
 constexpr int kBufferDword3 = 0x00020000;  // raw buffer, 32-bit data format
 
-template <int S, int G, int WM, int WN, int MB, int NB>
+// Tag only separates specializations: the streamed kernel uses its own
+// (Tag = 1).  With one shared specialization, hipcc's host pass silently
+// dropped the streamed kernel's host stub (the library then failed to load
+// with an undefined symbol).
+template <int S, int G, int WM, int WN, int MB, int NB, int Tag = 0>
 struct LoadPlan {
     using C = Cfg<S, G, WM, WN, MB, NB>;
     static constexpr int NL = (C::SEGS + C::NW - 1) / C::NW;
@@ -353,6 +359,251 @@ __device__ __forceinline__ void pair_tile(const PairArgs &a, GetTerm get_term, i
     }
 }
 
+// ---- streamed grouped kernel ----------------------------------------------
+// A grid of resident workgroups takes the listed tiles from per-XCD counters
+// (workgroup b serves queue b mod q, q = min(8, grid); queue x hands out
+// the tiles x, x + q, x + 2q, ..., so a tile stays on the XCD its position
+// in the list names, while the tiles of one XCD go to whichever of its
+// workgroups is free first).  Each workgroup takes its next tile when it
+// starts the current one and works through the terms in list order; the
+// first K block of the next (tile, term) item is loaded into the free LDS
+// stage during the last K block of the current one, so an item does not
+// start with an empty pipeline and the epilogue runs while that load is in
+// flight.  Same arithmetic as pair_tile, term by term.
+
+template <int S, int G, int WM, int WN, int MB, int NB, typename F, typename LP>
+__device__ __forceinline__ void stream_step(v16i (&acc)[G][MB][NB], F &f, const uint4 *cur, uint4 *nxt,
+                                            const LP &lp, int kb, int nkb, bool has_next, const TermDesc &next,
+                                            int nm0, int nn0, int wave, int lane, int wm, int wn, int half,
+                                            int l32) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    F g;
+    read_stage<S, G, WM, WN, MB, NB>(g, cur, wm, wn, half, l32);
+    if (kb + 1 < nkb) {
+        lp.issue(nxt, kb + 1);
+    } else if (has_next) {
+        LoadPlan<S, G, WM, WN, MB, NB, 1> np;
+        np.init(next.A, next.B, next.a_rows_p, next.b_rows_p, nm0, nn0, wave, lane);
+        np.issue(nxt, 0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    mfma_pairs<true, S, G, MB, NB>(acc, f);
+    mfma_pairs<false, S, G, MB, NB>(acc, g);
+    __builtin_amdgcn_sched_barrier(0);
+    f = g;
+}
+
+// Exact diagonal sums of one item whose first K block is already on its way
+// into `first`; the step of the last block starts the next item's first block.
+template <int S, int G, int WM, int WN, int MB, int NB>
+__device__ __forceinline__ void stream_mainloop(v16i (&acc)[G][MB][NB], uint4 *first, uint4 *second,
+                                                const TermDesc &T, int m0, int n0, bool has_next,
+                                                const TermDesc &next, int nm0, int nn0) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave / WN;
+    const int wn = wave % WN;
+    const int half = lane >> 5;
+    const int l32 = lane & 31;
+    const int nkb = T.kblocks;
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) acc[g][mb][nb] = v16i{};
+    if (nkb == 0) return;
+    LoadPlan<S, G, WM, WN, MB, NB, 1> lp;
+    lp.init(T.A, T.B, T.a_rows_p, T.b_rows_p, m0, n0, wave, lane);
+    Frags<S, G, MB, NB> f;
+#pragma unroll
+    for (int s = 0; s < Frags<S, G, MB, NB>::T; ++s) {
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) f.a[s][mb] = v4i{};
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) f.b[s][nb] = v4i{};
+    }
+    int kb = 0;
+    for (; kb + 2 <= nkb; kb += 2) {
+        stream_step<S, G, WM, WN, MB, NB>(acc, f, first, second, lp, kb, nkb, has_next, next, nm0, nn0, wave, lane,
+                                          wm, wn, half, l32);
+        stream_step<S, G, WM, WN, MB, NB>(acc, f, second, first, lp, kb + 1, nkb, has_next, next, nm0, nn0, wave,
+                                          lane, wm, wn, half, l32);
+    }
+    if (kb < nkb)
+        stream_step<S, G, WM, WN, MB, NB>(acc, f, first, second, lp, kb, nkb, has_next, next, nm0, nn0, wave, lane,
+                                          wm, wn, half, l32);
+    mfma_pairs<true, S, G, MB, NB>(acc, f);
+}
+
+// Starts the first K block of an item that was not prefetched; the stages
+// may still be read by the previous item, hence the barrier.
+template <int S, int G, int WM, int WN, int MB, int NB>
+__device__ __forceinline__ void stream_first_block(uint4 *stage, const TermDesc &T, int m0, int n0) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    LoadPlan<S, G, WM, WN, MB, NB, 1> lp;
+    lp.init(T.A, T.B, T.a_rows_p, T.b_rows_p, m0, n0, wave, lane);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    lp.issue(stage, 0);
+}
+
+// The next listed tile of this workgroup's queue that is not padding, or a
+// value >= a.ntiles when the queue is empty.  Thread 0 takes the counter;
+// the value reaches the other waves through LDS slot `slot` (two slots used
+// alternately, so a slot is rewritten only after every wave has read it).
+__device__ __forceinline__ int stream_take(const PairArgs &a, int *slots, int &slot) {
+    const int nq = min(static_cast<int>(gridDim.x), 8);
+    const int x = static_cast<int>(blockIdx.x) % nq;
+    int t;
+    do {
+        if (threadIdx.x == 0) slots[slot] = x + nq * atomicAdd(a.queue + x, 1);
+        __syncthreads();
+        t = slots[slot];
+        slot ^= 1;
+    } while (t < a.ntiles && a.tiles[t].out < 0);
+    return t;
+}
+
+// Called by every workgroup once its queue is empty: the last one to get
+// here leaves the counters zeroed for the next launch.
+__device__ __forceinline__ void stream_finish(const PairArgs &a) {
+    if (threadIdx.x == 0) {
+        __threadfence();
+        if (atomicAdd(a.queue + 8, 1) == static_cast<int>(gridDim.x) - 1) {
+            for (int q = 0; q <= 8; ++q) atomicExch(a.queue + q, 0);
+            __threadfence();
+        }
+    }
+}
+
+// One past the last term of a tile: the GEMM mode has one term per tile.
+template <int MODE>
+__device__ __forceinline__ int stream_term_end(const TileDesc &d) {
+    return MODE == kModeAccum ? d.term_end : d.term_begin + 1;
+}
+
+// The walk of one resident workgroup over its tiles and their terms.
+template <int S, int G, int WM, int WN, int MB, int NB, int MODE, typename GetTerm>
+__device__ __forceinline__ void stream_tiles(const PairArgs &a, GetTerm get_term, uint4 *lds0, uint4 *lds1) {
+    static_assert(MODE == kModeGemm || MODE == kModeAccum, "streamed launches run the GEMM or accumulating mode");
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wm = wave / WN;
+    const int wn = wave % WN;
+    const int half = lane >> 5;
+    const int l32 = lane & 31;
+    __shared__ int slots[2];
+    int slot = 0;
+    int t = stream_take(a, slots, slot);
+    if (t >= a.ntiles) {
+        stream_finish(a);
+        return;
+    }
+    TileDesc td = a.tiles[t];
+    bool pending = false;  // the current item's first block is on its way into lds0 (in0) or lds1
+    bool in0 = true;
+    constexpr int SIG = (MODE == kModeAccum) ? 16 : 1;
+    while (true) {
+        OutDesc od = a.outs[td.out];
+        if (a.out_base) od.C = a.out_base + reinterpret_cast<intptr_t>(od.C);
+        const int m0 = td.m0, n0 = td.n0;
+        const int te = stream_term_end<MODE>(td);
+        const int tn = stream_take(a, slots, slot);
+        double sig[MB][NB][SIG];
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                for (int r = 0; r < SIG; ++r) sig[mb][nb][r] = 0.0;
+        for (int ti = td.term_begin; ti < te; ++ti) {
+            const TermDesc T = get_term(ti);
+            // the next item: this tile's next term, else the next tile's first
+            bool has_next = false;
+            TermDesc N = T;
+            int nm0 = m0, nn0 = n0;
+            if (ti + 1 < te) {
+                N = get_term(ti + 1);
+                has_next = true;
+            } else if (tn < a.ntiles) {
+                const TileDesc nd = a.tiles[tn];
+                if (nd.term_begin < stream_term_end<MODE>(nd)) {
+                    N = get_term(nd.term_begin);
+                    nm0 = nd.m0;
+                    nn0 = nd.n0;
+                    has_next = true;
+                }
+            }
+            has_next = has_next && N.kblocks > 0 && T.kblocks > 0;
+            if (!pending && T.kblocks > 0) {
+                stream_first_block<S, G, WM, WN, MB, NB>(lds0, T, m0, n0);
+                in0 = true;
+            }
+            v16i acc[G][MB][NB];
+            if (in0)
+                stream_mainloop<S, G, WM, WN, MB, NB>(acc, lds0, lds1, T, m0, n0, has_next, N, nm0, nn0);
+            else
+                stream_mainloop<S, G, WM, WN, MB, NB>(acc, lds1, lds0, T, m0, n0, has_next, N, nm0, nn0);
+            // the next item's first block went into the stage the last step did not read
+            pending = has_next;
+            if (has_next && (T.kblocks & 1)) in0 = !in0;
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const int j = n0 + (wn * NB + nb) * 32 + l32;
+                const bool jok = j < od.N;
+                const int32_t fj = jok ? T.f[j] : 0;
+#pragma unroll
+                for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) {
+                        __builtin_amdgcn_sched_barrier(0);
+                        const int i = m0 + (wm * MB + mb) * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                        if (!jok || i >= od.M) continue;
+                        long long q[G];
+#pragma unroll
+                        for (int g = 0; g < G; ++g) q[g] = acc[g][mb][nb][r];
+                        const double c = horner<G>(q, T.e[i], fj);
+                        if (MODE == kModeGemm) {
+                            double *p = od.C + static_cast<int64_t>(i) * od.ldc + j;
+                            *p = (a.beta == 0.0) ? T.alpha * c : fma(T.alpha, c, a.beta * *p);
+                        } else {
+                            sig[mb][nb][r % SIG] = fma(T.alpha, c, sig[mb][nb][r % SIG]);
+                        }
+                    }
+            }
+        }
+        if (MODE == kModeAccum) {
+#pragma unroll
+            for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                    for (int r = 0; r < SIG; ++r) {
+                        const int i = m0 + (wm * MB + mb) * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                        const int j = n0 + (wn * NB + nb) * 32 + l32;
+                        if (i < od.M && j < od.N) od.C[static_cast<int64_t>(i) * od.ldc + j] = sig[mb][nb][r];
+                    }
+        }
+        if (tn >= a.ntiles) break;
+        t = tn;
+        td = a.tiles[t];
+    }
+    stream_finish(a);
+}
+
+template <int S, int G, int WM, int WN, int MB, int NB, int MODE>
+__global__ __launch_bounds__(64 * WM * WN) void k_pair_stream(PairArgs a) {
+    using C = Cfg<S, G, WM, WN, MB, NB>;
+    __shared__ uint4 lds0[C::STAGE];
+    __shared__ uint4 lds1[C::STAGE];
+    const TermDesc *terms = a.terms;
+    stream_tiles<S, G, WM, WN, MB, NB, MODE>(a, [&](int i) { return terms[i]; }, lds0, lds1);
+}
+
 // Tile index -> (tm, tn).  Blocks are dispatched to the 8 XCDs round robin;
 // give every XCD a contiguous range of tiles, walked in groups of `group`
 // tile rows, so the blocks that run together on one L2 share A and B panels.
@@ -477,6 +728,28 @@ hipError_t run_grouped_v(const PairArgs &a, hipStream_t s) {
         return hipErrorInvalidValue;
     } else {
         if (a.ntiles == 0) return hipSuccess;
+        if (a.stream_cus > 0) {
+            if (!a.queue) return hipErrorInvalidValue;
+            // resident workgroups only: the grid walks the list, nothing queues behind it
+            int per_cu = 1;
+            unsigned grid = 0;
+            if (a.mode == kModeGemm) {
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pair_stream<S, G, WM, WN, MB, NB, kModeGemm>,
+                                                                 NT, 0) != hipSuccess || per_cu < 1)
+                    per_cu = 1;
+                grid = static_cast<unsigned>(std::min<int64_t>(a.ntiles, static_cast<int64_t>(per_cu) * a.stream_cus));
+                hipLaunchKernelGGL((k_pair_stream<S, G, WM, WN, MB, NB, kModeGemm>), dim3(grid), dim3(NT), 0, s, a);
+            } else if (a.mode == kModeAccum) {
+                if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_pair_stream<S, G, WM, WN, MB, NB, kModeAccum>,
+                                                                 NT, 0) != hipSuccess || per_cu < 1)
+                    per_cu = 1;
+                grid = static_cast<unsigned>(std::min<int64_t>(a.ntiles, static_cast<int64_t>(per_cu) * a.stream_cus));
+                hipLaunchKernelGGL((k_pair_stream<S, G, WM, WN, MB, NB, kModeAccum>), dim3(grid), dim3(NT), 0, s, a);
+            } else {
+                return hipErrorInvalidValue;
+            }
+            return hipGetLastError();
+        }
         switch (a.mode) {
             case kModeGemm:
                 hipLaunchKernelGGL((k_pair_grouped<S, G, WM, WN, MB, NB, kModeGemm>), dim3(a.ntiles), dim3(NT), 0, s, a);

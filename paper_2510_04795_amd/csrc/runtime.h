@@ -20,6 +20,7 @@ struct ozaki_ctx_s {
     // tile variant of the pair GEMM per (S, G); -1 = library default
     int variant[9][16];
     bool autotune = true;  // heff plans time the variants of their grouped phases
+    int heff_launch = -1;  // grouped heff phases: -1 timed choice, 0 one workgroup per tile, k > 0 streamed on k CUs
     // phase timing (ozaki_ctx_set_timing)
     bool timing = false;
     std::vector<hipEvent_t> events;  // pool

@@ -245,6 +245,13 @@ int ozaki_ctx_set_autotune(ozaki_ctx ctx, int enable) {
     return OZ_OK;
 }
 
+int ozaki_ctx_set_heff_launch(ozaki_ctx ctx, int mode) {
+    if (!ctx) return fail(OZ_ERR_ARG, "ozaki_ctx_set_heff_launch: ctx is NULL");
+    if (mode < -1) return fail(OZ_ERR_ARG, "ozaki_ctx_set_heff_launch: mode = %d", mode);
+    ctx->heff_launch = mode;
+    return OZ_OK;
+}
+
 int ozaki_dgemm_tune(ozaki_ctx ctx, char transa, char transb, int64_t M, int64_t N, int64_t K,
                      const double *A, int64_t lda, const double *B, int64_t ldb, double *C,
                      int64_t ldc, int slices, int ndiag, void *workspace, size_t workspace_bytes,

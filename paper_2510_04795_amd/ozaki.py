@@ -75,6 +75,8 @@ _sig("ozaki_ctx_set_autotune", _i32, [_ptr, _i32])
 _sig("ozaki_dgemm_tune", _i32, [_ptr, ctypes.c_char, ctypes.c_char, _i64, _i64, _i64, _ptr, _i64, _ptr,
                                 _i64, _ptr, _i64, _i32, _i32, _ptr, _sz, _ptr, _ptr])
 _sig("heff_plan_variants", _i32, [_ptr, _ptr, _ptr])
+_sig("heff_plan_launches", _i32, [_ptr, _ptr, _ptr])
+_sig("ozaki_ctx_set_heff_launch", _i32, [_ptr, _i32])
 _sig("ozaki_slices_for_bits", _i32, [_i32])
 _sig("ozaki_pair_count", _i32, [_i32, _i32])
 _sig("ozaki_max_exact_k", _i64, [_i32, _i32])
@@ -116,7 +118,8 @@ EXPORTED = [
     "ozaki_status_string", "ozaki_last_error", "ozaki_version", "ozaki_ctx_create",
     "ozaki_ctx_destroy", "ozaki_ctx_flags", "ozaki_ctx_set_timing", "ozaki_ctx_phase_times",
     "ozaki_pair_variants", "ozaki_ctx_set_variant", "ozaki_ctx_get_variant",
-    "ozaki_ctx_set_autotune", "ozaki_dgemm_tune", "heff_plan_variants", "ozaki_slices_for_bits", "ozaki_pair_count",
+    "ozaki_ctx_set_autotune", "ozaki_ctx_set_heff_launch", "ozaki_dgemm_tune", "heff_plan_variants",
+    "heff_plan_launches", "ozaki_slices_for_bits", "ozaki_pair_count",
     "ozaki_max_exact_k", "ozaki_dgemm_workspace_bytes", "ozaki_dgemm", "ozaki_split",
     "ozaki_choose_slices", "ozaki_dgemm_auto_workspace_bytes", "ozaki_dgemm_auto",
     "ozaki_pair_products", "heff_plan_create", "heff_apply", "heff_plan_set_graphs",
@@ -237,6 +240,13 @@ class Context:
 
     def set_autotune(self, enable: bool = True):
         _check(_lib.ozaki_ctx_set_autotune(self.handle, int(bool(enable))), "ozaki_ctx_set_autotune")
+
+    def set_heff_launch(self, mode: int = -1):
+        """Launch of later heff plans' grouped phases: 0 one workgroup per
+        tile, k > 0 streamed on k compute units (capped at the device's),
+        -1 timed choice for the first phase when its items are short
+        (default)."""
+        _check(_lib.ozaki_ctx_set_heff_launch(self.handle, int(mode)), "ozaki_ctx_set_heff_launch")
 
     def tune(self, A, B, slices: int, ndiag: int = 0, C=None, transa="N", transb="N",
              workspace=None, stream=None):
@@ -457,6 +467,8 @@ class HeffPlan:
         a, b = ctypes.c_int32(), ctypes.c_int32()
         _check(_lib.heff_plan_variants(h, ctypes.byref(a), ctypes.byref(b)), "heff_plan_variants")
         self.variants = (a.value, b.value)
+        _check(_lib.heff_plan_launches(h, ctypes.byref(a), ctypes.byref(b)), "heff_plan_launches")
+        self.launches = (a.value, b.value)
 
     def apply(self, psi, sigma=None, stream=None):
         _dev_f64(psi, "psi")

@@ -154,12 +154,20 @@ def test_sparse_fp64(oz):
         assert np.all(np.abs(sig[b] - ref[b]) <= 2 * K * u * mag[b] + 1e-300), b
 
 
-def test_sparse_full_size_sampled_blocks(oz):
+@pytest.mark.parametrize("launch", [-1, 0, 100000])
+def test_sparse_full_size_sampled_blocks(oz, launch):
     """The 40-sector, 2000-triple batch; sigma blocks depend only on their own
-    triples, so the oracle recomputes a few blocks alone."""
+    triples, so the oracle recomputes a few blocks alone.  Timed launch
+    choice, one workgroup per tile, and the streamed kernel on every CU."""
     ozaki, ctx, torch = oz
     prob = wl.heff_sparse()
-    plan, dpsi, keep = sparse_plan(ozaki, ctx, torch, prob, 6)
+    ctx.set_heff_launch(launch)
+    try:
+        plan, dpsi, keep = sparse_plan(ozaki, ctx, torch, prob, 6)
+    finally:
+        ctx.set_heff_launch(-1)
+    if launch >= 0:
+        assert plan.launches == ((1, 1) if launch else (0, 0))
     sig = wl.unflatten_sparse(prob, plan.apply(dpsi).cpu().numpy())
     counts = {}
     for t in prob.triples:
@@ -208,6 +216,66 @@ def test_plan_variants_bitexact(oz):
     plan, dpsi, keep = sparse_plan(ozaki, ctx, torch, prob, 6)
     built = [x[0] for x in ozaki.pair_variants(6)]
     assert plan.variants[0] in built and plan.variants[1] in built
+
+
+@pytest.mark.parametrize("cus", [1, 3, 100000])
+def test_streamed_launch_bitexact(oz, cus):
+    """The streamed kernel (resident workgroups walk the tile list; the first
+    K block of the next tile or term is loaded during the last block of the
+    current one) gives the oracle's bits.  On 1 or 3 compute units every
+    workgroup walks many tiles and terms, with odd and even block counts."""
+    ozaki, ctx, torch = oz
+    ctx.set_heff_launch(cus)
+    try:
+        for S, G in [(6, 6), (7, 7), (5, 6), (3, 5), (8, 15)]:
+            L, R, psi = wl.heff_dense(D=70, kop=3, phys=4, seed=40 + S)
+            plan, dpsi, keep = dense_plan(ozaki, ctx, torch, L, R, psi, S, G)
+            assert plan.launches == (1, 1)
+            sig = plan.apply(dpsi).cpu().numpy().reshape(psi.shape)
+            assert_bitexact(sig, oracle.heff_dense(L, R, psi, S=S, G=G), "dense S=%d G=%d" % (S, G))
+            prob = small_sparse(50 + S)
+            plan, dpsi, keep = sparse_plan(ozaki, ctx, torch, prob, S, G)
+            assert plan.launches == (1, 1)
+            sig = wl.unflatten_sparse(prob, plan.apply(dpsi).cpu().numpy())
+            ref = oracle.heff_sparse(prob, S=S, G=G)
+            for b in prob.psi_blocks:
+                assert_bitexact(sig[b], ref[b], "sparse S=%d G=%d block %s" % (S, G, b))
+        prob = small_sparse(61)
+        ref = oracle.heff_sparse(prob, S=6)
+        for (v, tm, tn) in ozaki.pair_variants(6):
+            ctx.set_variant(6, 0, v)
+            plan, dpsi, keep = sparse_plan(ozaki, ctx, torch, prob, 6)
+            assert plan.variants == (v, v) and plan.launches == (1, 1)
+            sig = wl.unflatten_sparse(prob, plan.apply(dpsi).cpu().numpy())
+            for b in prob.psi_blocks:
+                assert_bitexact(sig[b], ref[b], "streamed variant %d block %s" % (v, b))
+    finally:
+        ctx.set_heff_launch(-1)
+        ctx.set_variant(6, 0, -1)
+
+
+def test_launch_modes(oz):
+    ozaki, ctx, torch = oz
+    with pytest.raises(ozaki.OzakiError):
+        ctx.set_heff_launch(-2)
+    L, R, psi = wl.heff_dense(D=40, kop=2, phys=4, seed=1)
+    try:
+        ctx.set_heff_launch(0)
+        plan, dpsi, keep = dense_plan(ozaki, ctx, torch, L, R, psi, 6)
+        assert plan.launches == (0, 0)
+        a = plan.apply(dpsi)
+        ctx.set_heff_launch(2)
+        plan2, _, keep2 = dense_plan(ozaki, ctx, torch, L, R, psi, 6)
+        assert plan2.launches == (1, 1)
+        assert torch.equal(a, plan2.apply(dpsi))
+    finally:
+        ctx.set_heff_launch(-1)
+    # timed choice: only the first phase may stream
+    plan3, _, keep3 = dense_plan(ozaki, ctx, torch, L, R, psi, 6)
+    assert plan3.launches[0] in (0, 1) and plan3.launches[1] == 0
+    assert torch.equal(a, plan3.apply(dpsi))
+    plan, dpsi, keep = dense_plan(ozaki, ctx, torch, L, R, psi, 0)
+    assert plan.launches == (-1, -1)
 
 
 @pytest.mark.parametrize("kind", ["dense", "sparse", "fp64"])

@@ -94,6 +94,8 @@ def test_new_entry_points_reject_bad_arguments_on_the_host():
     assert b"ctx" in L.ozaki_last_error()
     assert L.rdm_eig_solve(None, None, 16, 4, None, None, 4, 0.0, 10, None, None) == -1
     assert L.rdm_eig_destroy(None) == 0
+    assert L.ozaki_ctx_set_heff_launch(None, 0) == -1
+    assert L.heff_plan_launches(None, None, None) == -1
     assert L.ozaki_renormalize(None, 100, 20, None, 20, 1, None, 100, None, 20, 0, 0, None, 0, None) == -1
     # workspace: the intermediate T (n x D doubles, 256-byte aligned), plus the GEMM workspace when emulated
     t = (100 * 20 * 8 + 255) // 256 * 256
