@@ -46,6 +46,8 @@ struct heff_plan_s {
     int n_T_etasks = 0, n_T_stasks = 0;
     int32_t *T_e = nullptr;
     int8_t *T_p = nullptr;
+    int32_t *T_emax = nullptr;  // exponent-code maxima left by the first phase (null: T read again)
+    int64_t T_e_total = 0;
     PairArgs argsL{}, argsR{};
     int varL = -1, varR = -1;   // tile variants of the two grouped phases
     // FP64 path
@@ -438,6 +440,19 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
     P->psi_p = static_cast<int8_t *>(pp);
     P->T_e = static_cast<int32_t *>(te_);
     P->T_p = static_cast<int8_t *>(tp);
+    // T's row exponents from its producer: every row of the (left * phys) x
+    // right view must take whole 32-column groups of the first product
+    // (phys = 1, or right dimensions that are multiples of 32).  Then the
+    // first phase's epilogue leaves exponent-code maxima in T_emax and a
+    // small kernel turns them into T_e, instead of a pass that reads T.
+    bool fuse_T = Ts.e_total > 0;
+    for (const U &x : us) fuse_T = fuse_T && (p == 1 || rd[x.ri] % 32 == 0);
+    std::vector<int32_t> emax_init;
+    if (fuse_T) {
+        emax_init.assign(static_cast<size_t>(Ts.e_total), kEmaxZero);
+        if ((rc = upload(P, emax_init, &P->T_emax))) { free_plan(P); return rc; }
+        P->T_e_total = Ts.e_total;
+    }
 
     // terms and outputs (shared by every tile variant)
     std::vector<TermDesc> termsL, termsR;
@@ -457,7 +472,13 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
         tm.kblocks = static_cast<int32_t>(ceil_div(K, kKB));
         tm.alpha = 1.0;
         termsL.push_back(tm);
-        outsL.push_back(OutDesc{P->T + x.t_off, N, static_cast<int32_t>(M), static_cast<int32_t>(N)});
+        OutDesc o{P->T + x.t_off, N, static_cast<int32_t>(M), static_cast<int32_t>(N)};
+        if (P->T_emax) {
+            o.emax = P->T_emax + T_eoff[u];
+            o.ep = static_cast<int32_t>(p);
+            o.en = static_cast<int32_t>(rd[x.ri]);
+        }
+        outsL.push_back(o);
     }
     for (int b = 0; b < L->n_psi_blocks; ++b) {
         const int lo = L->psi_lr[2 * b], ro = L->psi_lr[2 * b + 1];
@@ -635,6 +656,9 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
         hipEventDestroy(ev1);
         hipStreamSynchronize(s);
         hipFree(tmp_sigma);
+        // the timed launches of the first phase may have left maxima
+        if (P->T_emax && (e = hipMemcpy(P->T_emax, emax_init.data(), sizeof(int32_t) * emax_init.size(),
+                                        hipMemcpyHostToDevice)) != hipSuccess) { free_plan(P); return hip_fail(e, "heff_plan_create: reset"); }
     }
     if ((e = hipStreamSynchronize(s)) != hipSuccess) { free_plan(P); return hip_fail(e, "heff_plan_create: sync"); }
     *out = P;
@@ -669,7 +693,8 @@ int enqueue_apply(heff_plan P, const double *psi, double *sigma, hipStream_t s) 
         if ((e = launch_pair_grouped(P->S, P->G, P->varL, P->argsL, s)) != hipSuccess) return hip_fail(e, "heff_apply: first product");
         hipEvent_t t2 = mark(ctx, s);
         phase(ctx, OZ_PHASE_HEFF_L, t1, t2);
-        if ((e = launch_exponents_grouped(P->T_blocks, P->T_etasks, P->n_T_etasks, P->T, P->T_e, ctx->d_flags, s)) != hipSuccess ||
+        if ((e = P->T_emax ? launch_emax_finish(P->T_emax, P->T_e, P->T_e_total, ctx->d_flags, s)
+                           : launch_exponents_grouped(P->T_blocks, P->T_etasks, P->n_T_etasks, P->T, P->T_e, ctx->d_flags, s)) != hipSuccess ||
             (e = launch_slice_grouped(P->S, P->T_blocks, P->T_stasks, P->n_T_stasks, P->T, P->T_e, P->T_p, s)) != hipSuccess)
             return hip_fail(e, "heff_apply: slicing T");
         hipEvent_t t3 = mark(ctx, s);

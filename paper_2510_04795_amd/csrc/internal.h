@@ -26,6 +26,26 @@ constexpr int kRowQ = 32;    // row granularity of the packed layout
 // that 2 * 8 * rows_p * 16 stays below 2^31.
 constexpr int64_t kMaxPackedRows = (INT32_MAX / (2 * 8 * 16)) / kRowQ * kRowQ;
 constexpr int32_t kExpBad = INT32_MIN;
+// Codes of the fused row-exponent maxima (an exponent code is the shared
+// exponent of one element's magnitude): an all-zero group, a NaN or +-Inf.
+constexpr int32_t kEmaxZero = INT32_MIN + 1;
+constexpr int32_t kEmaxNaN = INT32_MAX;
+
+// Exponent e of a group whose largest magnitude is mu: with mu = m 2^E,
+// m in [0.5, 1), e = E + [m > 127/128], so |x| 2^(8S-1-e) <= 127 256^(S-1)
+// and the leading slice fits in int8.  Computed from the bit pattern.  It is
+// non-decreasing in mu, so the largest exponent of a group's elements is the
+// exponent of its largest magnitude.
+__device__ inline int32_t shared_exponent(double mu) {
+    if (mu == 0.0) return 0;
+    const uint64_t b = static_cast<uint64_t>(__double_as_longlong(mu));
+    const int be = static_cast<int>((b >> 52) & 0x7ff);
+    const uint64_t fr = b & ((1ull << 52) - 1);
+    if (be != 0) return be - 1022 + (fr > (63ull << 46) ? 1 : 0);
+    // subnormal: mu = fr 2^-1074 with top bit p; frexp gives E = p - 1073, m = fr / 2^(p+1)
+    const int p = 63 - __clzll(static_cast<long long>(fr));
+    return p - 1073 + ((fr << 7) > (127ull << (p + 1)) ? 1 : 0);
+}
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 inline int64_t ceil_div(int64_t x, int64_t m) { return (x + m - 1) / m; }
@@ -55,6 +75,11 @@ struct OutDesc {
     double *C;
     int64_t ldc;
     int32_t M, N;          // valid extent (stores outside are skipped)
+    // GEMM mode, nullable: exponent-code maxima of the stored values, element
+    // (i, j) into emax[i * ep + j / en] (en a multiple of 32, or ep = 1 and
+    // en >= N), combined with atomic max
+    int32_t *emax;
+    int32_t ep, en;
 };
 
 enum PairMode : int32_t {
@@ -167,6 +192,9 @@ hipError_t launch_slice(int S, bool trans, const double *X, int64_t ld, int64_t 
 hipError_t launch_exponents_grouped(const SliceBlock *blocks, const SliceTask *tasks, int ntasks,
                                     const double *x_base, int32_t *e_base, uint32_t *flag,
                                     hipStream_t s);
+// Row exponents from the code maxima a GEMM-mode pair launch left in emax
+// (OutDesc::emax); emax is left at kEmaxZero.
+hipError_t launch_emax_finish(int32_t *emax, int32_t *e, int64_t n, uint32_t *flag, hipStream_t s);
 hipError_t launch_slice_grouped(int S, const SliceBlock *blocks, const SliceTask *tasks, int ntasks,
                                 const double *x_base, const int32_t *e_base, int8_t *p_base,
                                 hipStream_t s);

@@ -267,7 +267,62 @@ __device__ __forceinline__ double horner(const long long (&q)[G], int32_t ei, in
     return ldexp(h, ei + fj - 14);
 }
 
-template <int S, int G, int WM, int WN, int MB, int NB, int MODE, typename GetTerm>
+// Fused row maxima of a GEMM-mode output.  For one 32 x 32 block a lane
+// holds 16 stored values, value r of lane l at row 8 (r / 4) + 4 (l / 32) +
+// r % 4, column l % 32.  Their magnitudes, as bit patterns with the sign
+// cleared (integer order is magnitude order, NaN above Inf), are reduced
+// over the 32 columns by halving exchanges: each step keeps half of the rows
+// and takes the partner's other half.  The epilogue visits the values in
+// the order 0, 8, 1, 9, ... and makes the first exchange (partner l ^ 16)
+// as soon as values q and 8 + q exist, so only 8 partial maxima stay live.
+// First exchange of values q (lo) and 8 + q (hi): the partner's half.  Its
+// result is used one pair later, so the exchange latency is hidden behind
+// the next element's recombination.
+__device__ __forceinline__ void emax_issue(long long lo, long long hi, int l32, long long &keep, long long &got) {
+    const bool b4 = l32 & 16;
+    got = __shfl_xor(b4 ? lo : hi, 16);
+    keep = b4 ? hi : lo;
+}
+
+// The remaining exchanges (partners l ^ 8, 4, 2, 1), then the even lanes
+// turn their row's maximum into an exponent code and combine it into emax
+// with one atomic max.  The columns j0 .. j0 + 31 map to one emax group.
+__device__ __forceinline__ void emax_block(const OutDesc &out, const long long (&w8)[8], int i0, int j0,
+                                           int half, int l32) {
+    const bool b4 = l32 & 16, b3 = l32 & 8, b2 = l32 & 4, b1 = l32 & 2;
+    long long w4[4], w2[2];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const long long t = __shfl_xor(b3 ? w8[q] : w8[4 + q], 8);
+        const long long k = b3 ? w8[4 + q] : w8[q];
+        w4[q] = k > t ? k : t;
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const long long t = __shfl_xor(b2 ? w4[q] : w4[2 + q], 4);
+        const long long k = b2 ? w4[2 + q] : w4[q];
+        w2[q] = k > t ? k : t;
+    }
+    long long w;
+    {
+        const long long t = __shfl_xor(b1 ? w2[0] : w2[1], 2);
+        const long long k = b1 ? w2[1] : w2[0];
+        w = k > t ? k : t;
+    }
+    {
+        const long long t = __shfl_xor(w, 1);
+        w = w > t ? w : t;
+    }
+    // this lane's row: r = 8 b4 + 4 b3 + 2 b2 + b1
+    const int r = (b4 ? 8 : 0) + (b3 ? 4 : 0) + (b2 ? 2 : 0) + (b1 ? 1 : 0);
+    const int i = i0 + 8 * (r >> 2) + 4 * half + (r & 3);
+    if (!(l32 & 1) && i < out.M && j0 < out.N && w != 0) {
+        const int32_t code = w >= 0x7ff0000000000000ll ? kEmaxNaN : shared_exponent(__longlong_as_double(w));
+        atomicMax(out.emax + static_cast<int64_t>(i) * out.ep + j0 / out.en, code);
+    }
+}
+
+template <int S, int G, int WM, int WN, int MB, int NB, int MODE, bool EMAX = false, typename GetTerm>
 __device__ __forceinline__ void pair_tile(const PairArgs &a, GetTerm get_term, int tb, int te,
                                           const OutDesc &out, int m0, int n0, uint4 *lds0,
                                           uint4 *lds1) {
@@ -300,13 +355,17 @@ __device__ __forceinline__ void pair_tile(const PairArgs &a, GetTerm get_term, i
             int32_t fj = 0;
             if (MODE != kModeQ && MODE != kModeQ64 && jok) fj = T.f[j];
 #pragma unroll
-            for (int mb = 0; mb < MB; ++mb)
+            for (int mb = 0; mb < MB; ++mb) {
+                long long w8[8], mlo = 0, keep = 0, got = 0;
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
+                for (int rr = 0; rr < 16; ++rr) {
+                    // with the fused maxima, values q and 8 + q in turn
+                    const int r = EMAX ? ((rr & 1) ? 8 + (rr >> 1) : (rr >> 1)) : rr;
                     // keep one element's recombination at a time in registers
                     __builtin_amdgcn_sched_barrier(0);
                     const int i = m0 + (wm * MB + mb) * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
                     const bool ok = jok && i < out.M;
+                    long long mag = 0;
                     if (MODE == kModeQ) {
                         if (ok) {
                             const int64_t plane = static_cast<int64_t>(out.M) * out.N;
@@ -322,8 +381,7 @@ __device__ __forceinline__ void pair_tile(const PairArgs &a, GetTerm get_term, i
                             const long long v = acc[g][mb][nb][r];
                             *p = a.qw_first ? v : *p + v;
                         }
-                    } else {
-                        if (!ok) continue;
+                    } else if (ok) {
                         long long q[G];
 #pragma unroll
                         for (int g = 0; g < G; ++g) q[g] = acc[g][mb][nb][r];
@@ -335,12 +393,27 @@ __device__ __forceinline__ void pair_tile(const PairArgs &a, GetTerm get_term, i
                         const double c = horner<G>(q, T.e[i], fj);
                         if (MODE == kModeGemm) {
                             double *p = out.C + static_cast<int64_t>(i) * out.ldc + j;
-                            *p = (a.beta == 0.0) ? T.alpha * c : fma(T.alpha, c, a.beta * *p);
+                            const double v = (a.beta == 0.0) ? T.alpha * c : fma(T.alpha, c, a.beta * *p);
+                            *p = v;
+                            mag = __double_as_longlong(v) & 0x7fffffffffffffffll;
                         } else {
                             sig[mb][nb][r % SIG] = fma(T.alpha, c, sig[mb][nb][r % SIG]);
                         }
                     }
+                    if (EMAX && out.emax) {
+                        if (rr & 1) {
+                            if (rr > 1) w8[(rr >> 1) - 1] = keep > got ? keep : got;
+                            emax_issue(mlo, mag, l32, keep, got);
+                        } else {
+                            mlo = mag;
+                        }
+                    }
                 }
+                if (EMAX && out.emax) {
+                    w8[7] = keep > got ? keep : got;
+                    emax_block(out, w8, m0 + (wm * MB + mb) * 32, n0 + (wn * NB + nb) * 32, half, l32);
+                }
+            }
         }
     }
 
@@ -557,23 +630,43 @@ __device__ __forceinline__ void stream_tiles(const PairArgs &a, GetTerm get_term
                 const bool jok = j < od.N;
                 const int32_t fj = jok ? T.f[j] : 0;
 #pragma unroll
-                for (int mb = 0; mb < MB; ++mb)
+                for (int mb = 0; mb < MB; ++mb) {
+                    constexpr bool EMAX = MODE == kModeGemm;
+                    long long w8[8], mlo = 0, keep = 0, got = 0;
 #pragma unroll
-                    for (int r = 0; r < 16; ++r) {
+                    for (int rr = 0; rr < 16; ++rr) {
+                        const int r = EMAX ? ((rr & 1) ? 8 + (rr >> 1) : (rr >> 1)) : rr;
                         __builtin_amdgcn_sched_barrier(0);
                         const int i = m0 + (wm * MB + mb) * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
-                        if (!jok || i >= od.M) continue;
-                        long long q[G];
+                        long long mag = 0;
+                        if (jok && i < od.M) {
+                            long long q[G];
 #pragma unroll
-                        for (int g = 0; g < G; ++g) q[g] = acc[g][mb][nb][r];
-                        const double c = horner<G>(q, T.e[i], fj);
-                        if (MODE == kModeGemm) {
-                            double *p = od.C + static_cast<int64_t>(i) * od.ldc + j;
-                            *p = (a.beta == 0.0) ? T.alpha * c : fma(T.alpha, c, a.beta * *p);
-                        } else {
-                            sig[mb][nb][r % SIG] = fma(T.alpha, c, sig[mb][nb][r % SIG]);
+                            for (int g = 0; g < G; ++g) q[g] = acc[g][mb][nb][r];
+                            const double c = horner<G>(q, T.e[i], fj);
+                            if (MODE == kModeGemm) {
+                                double *p = od.C + static_cast<int64_t>(i) * od.ldc + j;
+                                const double v = (a.beta == 0.0) ? T.alpha * c : fma(T.alpha, c, a.beta * *p);
+                                *p = v;
+                                mag = __double_as_longlong(v) & 0x7fffffffffffffffll;
+                            } else {
+                                sig[mb][nb][r % SIG] = fma(T.alpha, c, sig[mb][nb][r % SIG]);
+                            }
+                        }
+                        if (EMAX && od.emax) {
+                            if (rr & 1) {
+                                if (rr > 1) w8[(rr >> 1) - 1] = keep > got ? keep : got;
+                                emax_issue(mlo, mag, l32, keep, got);
+                            } else {
+                                mlo = mag;
+                            }
                         }
                     }
+                    if (EMAX && od.emax) {
+                        w8[7] = keep > got ? keep : got;
+                        emax_block(od, w8, m0 + (wm * MB + mb) * 32, n0 + (wn * NB + nb) * 32, half, l32);
+                    }
+                }
             }
         }
         if (MODE == kModeAccum) {
@@ -651,8 +744,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_pair_grouped(PairArgs a) {
     OutDesc od = a.outs[td.out];
     if (a.out_base) od.C = a.out_base + reinterpret_cast<intptr_t>(od.C);
     const TermDesc *terms = a.terms;
-    pair_tile<S, G, WM, WN, MB, NB, MODE>(a, [&](int i) { return terms[i]; }, td.term_begin,
-                                          td.term_end, od, td.m0, td.n0, lds0, lds1);
+    pair_tile<S, G, WM, WN, MB, NB, MODE, MODE == kModeGemm>(a, [&](int i) { return terms[i]; }, td.term_begin,
+                                                            td.term_end, od, td.m0, td.n0, lds0, lds1);
 }
 
 // Per-(S, G) tile shape: as wide as the accumulators allow.

@@ -9,20 +9,6 @@
 namespace oz {
 namespace {
 
-// Exponent e of a group whose largest magnitude is mu: with mu = m 2^E,
-// m in [0.5, 1), e = E + [m > 127/128], so |x| 2^(8S-1-e) <= 127 256^(S-1)
-// and the leading slice fits in int8.  Computed from the bit pattern.
-__device__ inline int32_t shared_exponent(double mu) {
-    if (mu == 0.0) return 0;
-    const uint64_t b = static_cast<uint64_t>(__double_as_longlong(mu));
-    const int be = static_cast<int>((b >> 52) & 0x7ff);
-    const uint64_t fr = b & ((1ull << 52) - 1);
-    if (be != 0) return be - 1022 + (fr > (63ull << 46) ? 1 : 0);
-    // subnormal: mu = fr 2^-1074 with top bit p; frexp gives E = p - 1073, m = fr / 2^(p+1)
-    const int p = 63 - __clzll(static_cast<long long>(fr));
-    return p - 1073 + ((fr << 7) > (127ull << (p + 1)) ? 1 : 0);
-}
-
 // |x| for a finite x, NaN for NaN or +-Inf (marks the group as non-finite).
 __device__ inline double abs_or_nan(double x) {
     if (!(fabs(x) <= 1.79769313486231570815e308)) return __longlong_as_double(0x7ff8000000000000ll);
@@ -292,7 +278,21 @@ __global__ __launch_bounds__(256) void k_exponents_grouped(const SliceBlock *__r
         const double *row[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) row[j] = X + static_cast<int64_t>(r0 + j < bl.R ? r0 + j : 0) * bl.ld;
-        for (int k = lane; k < bl.K; k += 64) {
+        // two elements of each of the 4 rows per iteration: 8 loads in flight per lane
+        int k = lane;
+        for (; k + 64 < bl.K; k += 128) {
+            double v[4][2];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const bool ok = r0 + j < bl.R;
+                v[j][0] = ok ? row[j][k] : 0.0;
+                v[j][1] = ok ? row[j][k + 64] : 0.0;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                mu[j] = combine_max(mu[j], combine_max(abs_or_nan(v[j][0]), abs_or_nan(v[j][1])));
+        }
+        if (k < bl.K) {
 #pragma unroll
             for (int j = 0; j < 4; ++j)
                 if (r0 + j < bl.R) mu[j] = combine_max(mu[j], abs_or_nan(row[j][k]));
@@ -326,6 +326,27 @@ __global__ __launch_bounds__(256) void k_exponents_grouped(const SliceBlock *__r
             mu = combine_max(combine_max(part[0][lane], part[1][lane]), combine_max(part[2][lane], part[3][lane]));
             if (cok) e[c] = finish_exponent(mu, flag);
         }
+    }
+}
+
+// Exponents from the maxima a producing GEMM left in emax (one code per
+// group, combined with atomic max): the code itself, 0 for an all-zero
+// group, kExpBad and the flag for a non-finite one.  emax is reset to
+// kEmaxZero for the next product.
+__global__ __launch_bounds__(256) void k_emax_finish(int32_t *__restrict__ emax, int32_t *__restrict__ e,
+                                                      int64_t n, uint32_t *flag) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * 256) {
+        const int32_t v = emax[i];
+        int32_t x = v;
+        if (v == kEmaxNaN) {
+            atomicOr(flag, 1u);
+            x = kExpBad;
+        } else if (v == kEmaxZero) {
+            x = 0;
+        }
+        e[i] = x;
+        emax[i] = kEmaxZero;
     }
 }
 
@@ -550,6 +571,12 @@ hipError_t launch_exponents_grouped(const SliceBlock *blocks, const SliceTask *t
     if (ntasks == 0) return hipSuccess;
     hipLaunchKernelGGL(k_exponents_grouped, dim3(ntasks), dim3(256), 0, s, blocks, tasks, x_base,
                        e_base, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_emax_finish(int32_t *emax, int32_t *e, int64_t n, uint32_t *flag, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_emax_finish, dim3(grid_for(n, 256, 4096)), dim3(256), 0, s, emax, e, n, flag);
     return hipGetLastError();
 }
 

@@ -103,6 +103,36 @@ def test_dense_d256_full(oz):
     assert_bitexact(sig, oracle.heff_dense(L, R, psi, S=6), "D=256")
 
 
+@pytest.mark.parametrize("case", ["phys3_d96", "nonfinite", "subnormal_T", "fallback_d70"])
+def test_T_exponents_from_first_phase(oz, case):
+    """T's row exponents come from the first phase's epilogue (exponent-code
+    maxima combined with atomic max) when every T row takes whole 32-column
+    groups (phys 1, or right dimensions that are multiples of 32), else from
+    a pass over T.  Both give the oracle's bits, also with NaN / Inf inputs,
+    zero rows and subnormal T."""
+    ozaki, ctx, torch = oz
+    D, phys = (70, 4) if case == "fallback_d70" else (96, 3)
+    L, R, psi = wl.heff_dense(D=D, kop=2, phys=phys, seed=7)
+    if case == "nonfinite":
+        psi[5, 1, 7] = np.nan
+        psi[10, 0, 3] = np.inf
+        L[1][3, :] = 0.0
+    if case == "subnormal_T":
+        psi = psi * 2.0 ** -1000
+        L = L * 2.0 ** -60
+    ctx.flags()
+    plan, dpsi, keep = dense_plan(ozaki, ctx, torch, L, R, psi, 5)
+    sig = plan.apply(dpsi).cpu().numpy().reshape(psi.shape)
+    ref = oracle.heff_dense(L, R, psi, S=5)
+    assert_bitexact(sig, ref, case)
+    if case == "nonfinite":
+        assert np.isnan(ref).any() and not np.isnan(ref).all()
+        assert ctx.flags() & 1
+    if case == "subnormal_T":
+        T0 = L[0] @ psi.reshape(D, -1)
+        assert np.abs(T0).max() < 2.0 ** -1022
+
+
 def test_dense_d2048_sampled_rows(oz):
     """D = 2048, phys 16 (the benchmark's shape, fewer operator pairs): rows
     alpha' computed alone by the oracle, whole second products included."""
