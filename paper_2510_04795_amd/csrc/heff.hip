@@ -48,6 +48,8 @@ struct heff_plan_s {
     int8_t *T_p = nullptr;
     int32_t *T_emax = nullptr;  // exponent-code maxima left by the first phase (null: T read again)
     int64_t T_e_total = 0;
+    int32_t *psi_emax = nullptr;  // exponent-code maxima of psi's split column pass
+    int64_t psi_e_total = 0;
     PairArgs argsL{}, argsR{};
     int varL = -1, varR = -1;   // tile variants of the two grouped phases
     // FP64 path
@@ -300,6 +302,30 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
             return fail(OZ_ERR_UNSUPPORTED, "heff_plan_create: inner dimension above the exact int32 range");
     }
 
+    // Distinct first products ordered by their psi block, then L block: the
+    // per-XCD parts of the first phase's tile list then keep the products
+    // that read one psi block together (1-3 % less time in that phase on the
+    // block-sparse batch).  Results do not depend on this order.
+    {
+        std::vector<int> perm(us.size());
+        for (size_t k = 0; k < perm.size(); ++k) perm[k] = static_cast<int>(k);
+        std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) {
+            return std::make_pair(us[a].psib, us[a].Lb) < std::make_pair(us[b].psib, us[b].Lb);
+        });
+        std::vector<int> inv(us.size());
+        std::vector<U> sorted;
+        int64_t off = 0;
+        for (size_t k = 0; k < perm.size(); ++k) {
+            U x = us[perm[k]];
+            x.t_off = off;
+            off += ld[x.lo] * p * rd[x.ri];
+            sorted.push_back(x);
+            inv[perm[k]] = static_cast<int>(k);
+        }
+        for (auto &u : tri_u) u = inv[u];
+        us.swap(sorted);
+    }
+
     hipError_t e;
     if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -412,6 +438,7 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
 
     // psi blocks sliced by columns of the left x (phys * right) view, on every apply
     SliceSet Ps;
+    Ps.split_cols = true;  // row chunks of long columns in parallel, combined through codes
     std::vector<int64_t> P_eoff(L->n_psi_blocks), P_poff(L->n_psi_blocks);
     for (int b = 0; b < L->n_psi_blocks; ++b) {
         const int l = L->psi_lr[2 * b], r = L->psi_lr[2 * b + 1];
@@ -445,6 +472,11 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
     // (phys = 1, or right dimensions that are multiples of 32).  Then the
     // first phase's epilogue leaves exponent-code maxima in T_emax and a
     // small kernel turns them into T_e, instead of a pass that reads T.
+    if (Ps.e_total > 0) {
+        const std::vector<int32_t> init(static_cast<size_t>(Ps.e_total), kEmaxZero);
+        if ((rc = upload(P, init, &P->psi_emax))) { free_plan(P); return rc; }
+        P->psi_e_total = Ps.e_total;
+    }
     bool fuse_T = Ts.e_total > 0;
     for (const U &x : us) fuse_T = fuse_T && (p == 1 || rd[x.ri] % 32 == 0);
     std::vector<int32_t> emax_init;
@@ -685,7 +717,8 @@ int enqueue_apply(heff_plan P, const double *psi, double *sigma, hipStream_t s) 
         phase(ctx, OZ_PHASE_HEFF_R, t1, t2);
     } else {
         hipEvent_t t0 = mark(ctx, s);
-        if ((e = launch_exponents_grouped(P->psi_blocks, P->psi_etasks, P->n_psi_etasks, psi, P->psi_e, ctx->d_flags, s)) != hipSuccess ||
+        if ((e = launch_exponents_grouped(P->psi_blocks, P->psi_etasks, P->n_psi_etasks, psi, P->psi_e, ctx->d_flags, s, P->psi_emax)) != hipSuccess ||
+            (e = launch_emax_finish(P->psi_emax, P->psi_e, P->psi_e_total, ctx->d_flags, s)) != hipSuccess ||
             (e = launch_slice_grouped(P->S, P->psi_blocks, P->psi_stasks, P->n_psi_stasks, psi, P->psi_e, P->psi_p, s)) != hipSuccess)
             return hip_fail(e, "heff_apply: slicing psi");
         hipEvent_t t1 = mark(ctx, s);

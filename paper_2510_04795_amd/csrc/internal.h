@@ -162,11 +162,14 @@ struct SliceBlock {
 constexpr int kExpTaskRows = 16;
 constexpr int kExpTaskCols = 64;
 constexpr int kSliceTaskKB = 8;
+// Column exponent tasks of sets built with split columns cover this many
+// rows each and combine their maxima through exponent codes (atomic max).
+constexpr int kExpColChunk = 128;
 
 struct SliceTask {
     int32_t block;
     int32_t a;       // exponent task: first group; slice task: first group (32-aligned)
-    int32_t b;       // slice task: 32-wide K block index
+    int32_t b;       // slice task: 32-wide K block index; split column task: row chunk
     int32_t pad_;
 };
 
@@ -189,11 +192,14 @@ hipError_t launch_slice(int S, bool trans, const double *X, int64_t ld, int64_t 
                         const int32_t *e, int8_t *packed, int64_t Rp, hipStream_t s);
 // Grouped exponent pass (tasks of kExpTaskRows rows or kExpTaskCols columns)
 // and slice pass (tasks of 32 groups x kSliceTaskKB 32-wide K blocks).
+// With emax_base (column tasks split into row chunks of kExpColChunk), the
+// column tasks combine exponent codes into emax_base[e_off + group] with
+// atomic max instead of writing exponents; launch_emax_finish completes them.
 hipError_t launch_exponents_grouped(const SliceBlock *blocks, const SliceTask *tasks, int ntasks,
                                     const double *x_base, int32_t *e_base, uint32_t *flag,
-                                    hipStream_t s);
-// Row exponents from the code maxima a GEMM-mode pair launch left in emax
-// (OutDesc::emax); emax is left at kEmaxZero.
+                                    hipStream_t s, int32_t *emax_base = nullptr);
+// Exponents from code maxima left in emax by a GEMM-mode pair launch
+// (OutDesc::emax) or a split column exponent pass; emax is left at kEmaxZero.
 hipError_t launch_emax_finish(int32_t *emax, int32_t *e, int64_t n, uint32_t *flag, hipStream_t s);
 hipError_t launch_slice_grouped(int S, const SliceBlock *blocks, const SliceTask *tasks, int ntasks,
                                 const double *x_base, const int32_t *e_base, int8_t *p_base,

@@ -65,6 +65,8 @@ struct SliceSet {
     std::vector<SliceBlock> blocks;
     std::vector<SliceTask> etasks, stasks;
     int64_t e_total = 0, p_total = 0;
+    // column exponent tasks split into row chunks (exponents through codes)
+    bool split_cols = false;
 
     int64_t add(int64_t x_off, int64_t ld, int64_t R, int64_t K, bool trans, int S, int64_t *e_off,
                 int64_t *p_off) {
@@ -84,7 +86,10 @@ struct SliceSet {
         const int id = static_cast<int>(blocks.size());
         blocks.push_back(b);
         const int step = trans ? kExpTaskCols : kExpTaskRows;
-        for (int64_t g = 0; g < R; g += step) etasks.push_back(SliceTask{id, static_cast<int32_t>(g), 0, 0});
+        const int64_t chunks = (trans && split_cols) ? std::max<int64_t>(ceil_div(K, kExpColChunk), 1) : 1;
+        for (int64_t g = 0; g < R; g += step)
+            for (int64_t c = 0; c < chunks; ++c)
+                etasks.push_back(SliceTask{id, static_cast<int32_t>(g), static_cast<int32_t>(c), 0});
         for (int64_t kb = 0; kb < ceil_div(K, kKB); kb += kSliceTaskKB)
             for (int64_t r0 = 0; r0 < b.Rp; r0 += 32)
                 stasks.push_back(SliceTask{id, static_cast<int32_t>(r0), static_cast<int32_t>(kb), 0});

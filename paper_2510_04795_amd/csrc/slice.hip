@@ -264,7 +264,7 @@ __global__ __launch_bounds__(256) void k_exponents_grouped(const SliceBlock *__r
                                                             const SliceTask *__restrict__ tasks,
                                                             const double *__restrict__ x_base,
                                                             int32_t *__restrict__ e_base,
-                                                            uint32_t *flag) {
+                                                            uint32_t *flag, int32_t *emax_base) {
     __shared__ double part[4][kExpTaskCols];
     const SliceTask tk = tasks[blockIdx.x];
     const SliceBlock bl = blocks[tk.block];
@@ -301,22 +301,30 @@ __global__ __launch_bounds__(256) void k_exponents_grouped(const SliceBlock *__r
         for (int j = 0; j < 4; ++j) {
             double m = mu[j];
             for (int off = 32; off >= 1; off >>= 1) m = combine_max(m, __shfl_xor(m, off, 64));
-            if (lane == 0 && r0 + j < bl.R) e[r0 + j] = finish_exponent(m, flag);
+            if (lane == 0 && r0 + j < bl.R) {
+                if (!emax_base)
+                    e[r0 + j] = finish_exponent(m, flag);
+                else if (m != 0.0)
+                    atomicMax(emax_base + bl.e_off + r0 + j, m != m ? kEmaxNaN : shared_exponent(m));
+            }
         }
     } else {
         const int c = tk.a + lane;
         const bool cok = c < bl.R;
         const double *col = X + (cok ? c : 0);
+        // rows [k0, k1): all of them, or one chunk of a split column task
+        const int k0 = emax_base ? tk.b * kExpColChunk : 0;
+        const int k1 = emax_base ? min(bl.K, k0 + kExpColChunk) : bl.K;
         double m8[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) m8[u] = 0.0;
-        int k = wave;
-        for (; k + 28 < bl.K; k += 32) {
+        int k = k0 + wave;
+        for (; k + 28 < k1; k += 32) {
 #pragma unroll
             for (int u = 0; u < 8; ++u)
                 m8[u] = combine_max(m8[u], cok ? abs_or_nan(col[static_cast<int64_t>(k + 4 * u) * bl.ld]) : 0.0);
         }
-        for (; k < bl.K; k += 4) m8[0] = combine_max(m8[0], cok ? abs_or_nan(col[static_cast<int64_t>(k) * bl.ld]) : 0.0);
+        for (; k < k1; k += 4) m8[0] = combine_max(m8[0], cok ? abs_or_nan(col[static_cast<int64_t>(k) * bl.ld]) : 0.0);
         double mu = m8[0];
 #pragma unroll
         for (int u = 1; u < 8; ++u) mu = combine_max(mu, m8[u]);
@@ -324,7 +332,14 @@ __global__ __launch_bounds__(256) void k_exponents_grouped(const SliceBlock *__r
         __syncthreads();
         if (wave == 0) {
             mu = combine_max(combine_max(part[0][lane], part[1][lane]), combine_max(part[2][lane], part[3][lane]));
-            if (cok) e[c] = finish_exponent(mu, flag);
+            if (cok) {
+                if (!emax_base) {
+                    e[c] = finish_exponent(mu, flag);
+                } else if (mu != 0.0) {
+                    // the code is monotone in the magnitude: the chunks' largest code is the column's
+                    atomicMax(emax_base + bl.e_off + c, mu != mu ? kEmaxNaN : shared_exponent(mu));
+                }
+            }
         }
     }
 }
@@ -567,10 +582,10 @@ hipError_t launch_slice(int S, bool trans, const double *X, int64_t ld, int64_t 
 
 hipError_t launch_exponents_grouped(const SliceBlock *blocks, const SliceTask *tasks, int ntasks,
                                     const double *x_base, int32_t *e_base, uint32_t *flag,
-                                    hipStream_t s) {
+                                    hipStream_t s, int32_t *emax_base) {
     if (ntasks == 0) return hipSuccess;
     hipLaunchKernelGGL(k_exponents_grouped, dim3(ntasks), dim3(256), 0, s, blocks, tasks, x_base,
-                       e_base, flag);
+                       e_base, flag, emax_base);
     return hipGetLastError();
 }
 
