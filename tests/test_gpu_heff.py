@@ -103,7 +103,8 @@ def test_dense_d256_full(oz):
     assert_bitexact(sig, oracle.heff_dense(L, R, psi, S=6), "D=256")
 
 
-@pytest.mark.parametrize("case", ["phys3_d96", "nonfinite", "nonfinite_long", "subnormal_T", "fallback_d70"])
+@pytest.mark.parametrize("case", ["phys3_d96", "nonfinite", "nan_chunk2", "inf_chunk3", "chunks_long",
+                                  "subnormal_T", "fallback_d70"])
 def test_T_exponents_from_first_phase(oz, case):
     """T's row exponents come from the first phase's epilogue (exponent-code
     maxima combined with atomic max) when every T row takes whole 32-column
@@ -111,18 +112,24 @@ def test_T_exponents_from_first_phase(oz, case):
     a pass over T.  Both give the oracle's bits, also with NaN / Inf inputs,
     zero rows and subnormal T."""
     ozaki, ctx, torch = oz
-    D, phys = {"fallback_d70": (70, 4), "nonfinite_long": (300, 1)}.get(case, (96, 3))
+    D, phys = (70, 4) if case == "fallback_d70" else (300, 1) if case.endswith(("2", "3", "long")) else (96, 3)
     L, R, psi = wl.heff_dense(D=D, kop=2, phys=phys, seed=7)
     if case == "nonfinite":
         psi[5, 1, 7] = np.nan
         psi[10, 0, 3] = np.inf
         L[1][3, :] = 0.0
-    if case == "nonfinite_long":
-        # psi's column exponents come from row chunks of 128: marks in the second and third
+    # psi's column exponents come from row chunks of 128 (300 rows: three chunks);
+    # with phys 1 a non-finite psi entry makes a whole column of T, hence every
+    # sigma entry, NaN
+    if case == "nan_chunk2":
         psi[140, 0, 9] = np.nan
+    if case == "inf_chunk3":
         psi[290, 0, 33] = -np.inf
+    if case == "chunks_long":
         psi[:, 0, 50] = 0.0
-        psi[260, 0, 60] = 1e-300
+        psi[:, 0, 60] *= 1e-300
+        psi[260, 0, 60] = 5e-300
+        psi[250, 0, 70] = 1e3
     if case == "subnormal_T":
         psi = psi * 2.0 ** -1000
         L = L * 2.0 ** -60
@@ -131,9 +138,14 @@ def test_T_exponents_from_first_phase(oz, case):
     sig = plan.apply(dpsi).cpu().numpy().reshape(psi.shape)
     ref = oracle.heff_dense(L, R, psi, S=5)
     assert_bitexact(sig, ref, case)
-    if case.startswith("nonfinite"):
+    if case == "nonfinite":
         assert np.isnan(ref).any() and not np.isnan(ref).all()
+    if case in ("nan_chunk2", "inf_chunk3"):
+        assert np.isnan(ref).all()
+    if case in ("nonfinite", "nan_chunk2", "inf_chunk3"):
         assert ctx.flags() & 1
+    if case == "chunks_long":
+        assert not np.isnan(ref).any()
     if case == "subnormal_T":
         T0 = L[0] @ psi.reshape(D, -1)
         assert np.abs(T0).max() < 2.0 ** -1022
