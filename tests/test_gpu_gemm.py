@@ -215,17 +215,24 @@ def test_fp64_mfma_large_tiles_within_gamma_bound(oz, transa, transb):
     assert np.all(err <= gam * mag * (1 + 1e-12) + 4 * u * np.abs(ref))
 
 
-def test_dgemm_full_size_sampled_rows(oz):
-    """n = 8192, S = 6: the launch the benchmark times, checked on sampled rows
-    (exponents are per row of A and per column of B, so rows are independent)."""
+@pytest.mark.parametrize("S,variant", [(6, -1), (7, 4)])
+def test_dgemm_full_size_sampled_rows(oz, S, variant):
+    """n = 8192: S = 6 with the default tile, and S = G = 7 on the 64 x 128
+    tile, the launch the benchmark times for its equal-error line; checked on
+    sampled rows (exponents are per row of A and per column of B, so rows are
+    independent)."""
     ozaki, ctx, torch = oz
     n = 8192
     A, B = wl.gemm_pair(n, U=10, seed=0)
-    Cd = ctx.dgemm(dev(torch, A), dev(torch, B), slices=6)
+    ctx.set_variant(S, 0, variant)
+    try:
+        Cd = ctx.dgemm(dev(torch, A), dev(torch, B), slices=S)
+    finally:
+        ctx.set_variant(S, 0, -1)
     rows = np.random.default_rng(1).choice(n, size=6, replace=False)
     got = Cd[torch.from_numpy(rows).cuda()].cpu().numpy()
-    ref = oracle.ozaki_dgemm(A[rows], B, 6)
-    assert_bitexact(got, ref, "n=8192 rows")
+    ref = oracle.ozaki_dgemm(A[rows], B, S)
+    assert_bitexact(got, ref, "n=8192 rows S=%d" % S)
 
 
 @pytest.mark.parametrize("S,G", [(2, 3), (4, 4), (5, 6), (6, 6), (8, 8), (7, 13)])
