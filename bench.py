@@ -600,8 +600,8 @@ def main():
     ap.add_argument("--stab-problems", type=int, default=6)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how it would shard)", file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
     import torch
     import oracle

@@ -54,7 +54,7 @@ extern "C" {
 #define OZ_ERR_ARG (-1)       /* invalid argument (message in ozaki_last_error) */
 #define OZ_ERR_WORKSPACE (-2) /* workspace missing or too small               */
 #define OZ_ERR_HIP (-3)       /* HIP runtime error (no device, launch failure) */
-#define OZ_ERR_UNSUPPORTED (-4) /* valid request this build does not provide  */
+#define OZ_ERR_UNSUPPORTED (-4) /* valid request this library does not provide*/
 #define OZ_ERR_STATE (-5)     /* object used in the wrong state               */
 #define OZ_ERR_NOMEM (-6)     /* device or host allocation failed             */
 

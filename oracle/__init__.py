@@ -227,7 +227,7 @@ def gemm(A, B, S: int = 0, G: int | None = None, **kw) -> np.ndarray:
 
 # ----------------------------------------------------------------------------
 # Automatic slice count (a reading of the library behaviour the paper names in
-# "Numerical procedure" without giving its rule; the rule is this build's own:
+# "Numerical procedure" without giving its rule; the rule is this library's own:
 # predicted relative Frobenius errors of the emulated and of a native FP64
 # product, the cheapest (S, G) whose prediction is no larger than native)
 # ----------------------------------------------------------------------------

@@ -541,7 +541,7 @@ def test_lanczos_invariant_subspace_and_stagnation():
     assert st == oracle.STAGNATED and abs(th - ev[0]) < 1e-5
 
 
-# ---- automatic slice count (this build's rule; the paper gives none) --------
+# ---- automatic slice count (the library's own rule; the paper gives none) --------
 def test_auto_slices_keep_native_accuracy():
     """The chosen (S, G) gives an emulated product whose error against the
     double-double reference is within 1.5x of the plain FP64 product's, and
