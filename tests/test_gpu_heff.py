@@ -302,6 +302,28 @@ def test_streamed_launch_bitexact(oz, cus):
         ctx.set_variant(6, 0, -1)
 
 
+@pytest.mark.parametrize("cus", [1, 100000])
+def test_streamed_tiny_sectors(oz, cus):
+    """Sectors of 1 to 40 states (single-K-block items, tile lists shorter
+    than the XCD count, so fewer than 8 queues) through the streamed kernel
+    and the producer-side exponents: the oracle's bits."""
+    ozaki, ctx, torch = oz
+    prob = wl.heff_sparse(n_sectors=6, n_triples=30, kop=3, median=6, sigma_log=1.2,
+                          lo_hi=(1, 40), density=0.5, reach=2, U=8, seed=3)
+    assert prob.dims.min() <= 2
+    ctx.set_heff_launch(cus)
+    try:
+        for S, G in [(6, 6), (3, 5)]:
+            plan, dpsi, keep = sparse_plan(ozaki, ctx, torch, prob, S, G)
+            assert plan.launches == (1, 1)
+            sig = wl.unflatten_sparse(prob, plan.apply(dpsi).cpu().numpy())
+            ref = oracle.heff_sparse(prob, S=S, G=G)
+            for b in prob.psi_blocks:
+                assert_bitexact(sig[b], ref[b], "tiny S=%d block %s" % (S, b))
+    finally:
+        ctx.set_heff_launch(-1)
+
+
 def test_launch_modes(oz):
     ozaki, ctx, torch = oz
     with pytest.raises(ozaki.OzakiError):
