@@ -580,10 +580,10 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
     for (int v = 0; v < pair_num_variants(); ++v)
         if (pair_variant_ok(G, v) && (fixed < 0 ? (ctx->autotune || v == pair_default_variant(G)) : v == fixed))
             cands.push_back(v);
-    // Autotuning: time each candidate (tile variant and tile order) on a
-    // prefix of its tile list, scaled by the prefix's share of the total
-    // cost; inputs are zeroed scratch (the timing does not depend on the
-    // values).
+    // Autotuning: time each candidate (tile variant, tile order, launch) on
+    // its whole tile list or an even sample of it, scaled by the sample's
+    // share of the total cost; inputs are zeroed scratch (the timing does
+    // not depend on the values).
     double bestL = -1, bestR = -1;
     void *tmp_sigma = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -615,15 +615,29 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
     int32_t last_key = -1;  // tile lists are built once per (variant, order) and shared by both launches
     TileDesc *dtl = nullptr, *dtr = nullptr;
     std::vector<int64_t> cl, cr;
+    std::vector<TileDesc> tl, tr;
     int32_t ntl = 0, ntr = 0;
+    // Timing sample: the equivalent of 64 tiles of 16 K blocks per CU, at
+    // least 8 and at most 64 tiles per CU, as groups of 8 consecutive list
+    // positions spread evenly over the list (a group keeps the XCD order's
+    // placement, and a longest-first list is sampled at every length).
+    const size_t cap = static_cast<size_t>(64) * ctx->num_cu;
+    const size_t floor_tiles = static_cast<size_t>(8) * ctx->num_cu;
+    TileDesc *tmp_tiles = nullptr;
+    if (tuning && (e = hipMalloc(&tmp_tiles, sizeof(TileDesc) * (cap + 8))) != hipSuccess) {
+        hipFree(tmp_sigma);
+        free_plan(P);
+        return hip_fail(e, "heff_plan_create: tuning buffer");
+    }
     for (auto [v, xcd, st] : runs) {
         const int32_t key = v * 2 + (xcd ? 1 : 0);
         if (key != last_key) {
-            std::vector<TileDesc> tl, tr;
+            tl.clear();
+            tr.clear();
             cl.clear();
             cr.clear();
             tiles_for(v, xcd, &tl, &tr, &cl, &cr);
-            if ((rc = upload(P, tl, &dtl)) || (rc = upload(P, tr, &dtr))) { if (tmp_sigma) hipFree(tmp_sigma); free_plan(P); return rc; }
+            if ((rc = upload(P, tl, &dtl)) || (rc = upload(P, tr, &dtr))) { if (tmp_sigma) hipFree(tmp_sigma); if (tmp_tiles) hipFree(tmp_tiles); free_plan(P); return rc; }
             ntl = static_cast<int32_t>(tl.size());
             ntr = static_cast<int32_t>(tr.size());
             last_key = key;
@@ -651,16 +665,33 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
                 const double mean_kb = items ? static_cast<double>(total) / items / (sh.bm * sh.bn) : 0.0;
                 if (ph == 1 || mean_kb > kStreamMaxMeanBlocks) continue;
             }
-            // 64 tiles per CU: whole lists of block-sparse batches, a few
-            // percent of large dense ones (a short prefix of a longest-first
-            // list holds only its longest items and misjudges launches whose
-            // gain is per item)
-            const int prefix = static_cast<int>(std::min<size_t>(cost.size(), static_cast<size_t>(64 * ctx->num_cu)));
-            int64_t part = 0;
-            for (int i = 0; i < prefix; ++i) part += cost[i];
+            const std::vector<TileDesc> &list = ph == 0 ? tl : tr;
             PairArgs a = ph == 0 ? P->argsL : P->argsR;
-            a.tiles = ph == 0 ? dtl : dtr;
-            a.ntiles = prefix;
+            const PairShape shp = pair_shape(S, G, v);
+            const double blocks_per_tile = items ? static_cast<double>(total) / items / (shp.bm * shp.bn) : 1.0;
+            const size_t n_sample = std::min(cap, std::max(floor_tiles, static_cast<size_t>(16.0 * cap / std::max(blocks_per_tile, 1.0))));
+            int64_t part = 0;
+            if (list.size() <= n_sample) {
+                a.tiles = ph == 0 ? dtl : dtr;
+                a.ntiles = static_cast<int32_t>(list.size());
+                part = total;
+            } else {
+                const size_t stride = (list.size() + n_sample - 1) / n_sample * 8;
+                std::vector<TileDesc> sample;
+                for (size_t g = 0; g < list.size(); g += stride)
+                    for (size_t j = g; j < std::min(g + 8, list.size()); ++j) {
+                        sample.push_back(list[j]);
+                        part += cost[j];
+                    }
+                if ((e = hipMemcpy(tmp_tiles, sample.data(), sizeof(TileDesc) * sample.size(), hipMemcpyHostToDevice)) != hipSuccess) {
+                    hipFree(tmp_sigma);
+                    hipFree(tmp_tiles);
+                    free_plan(P);
+                    return hip_fail(e, "heff_plan_create: tuning sample");
+                }
+                a.tiles = tmp_tiles;
+                a.ntiles = static_cast<int32_t>(sample.size());
+            }
             a.stream_cus = scus;
             if (ph == 1) a.out_base = static_cast<double *>(tmp_sigma);
             // a warm-up launch, then the faster of two timed ones
@@ -668,7 +699,7 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
             for (int rep = 0; rep < 3; ++rep) {
                 float r = 0.f;
                 hipEventRecord(ev0, s);
-                if ((e = launch_pair_grouped(S, G, v, a, s)) != hipSuccess) { hipFree(tmp_sigma); free_plan(P); return hip_fail(e, "heff_plan_create: tuning launch"); }
+                if ((e = launch_pair_grouped(S, G, v, a, s)) != hipSuccess) { hipFree(tmp_sigma); hipFree(tmp_tiles); free_plan(P); return hip_fail(e, "heff_plan_create: tuning launch"); }
                 hipEventRecord(ev1, s);
                 hipEventSynchronize(ev1);
                 hipEventElapsedTime(&r, ev0, ev1);
@@ -688,6 +719,7 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
         hipEventDestroy(ev1);
         hipStreamSynchronize(s);
         hipFree(tmp_sigma);
+        hipFree(tmp_tiles);
         // the timed launches of the first phase may have left maxima
         if (P->T_emax && (e = hipMemcpy(P->T_emax, emax_init.data(), sizeof(int32_t) * emax_init.size(),
                                         hipMemcpyHostToDevice)) != hipSuccess) { free_plan(P); return hip_fail(e, "heff_plan_create: reset"); }
