@@ -618,9 +618,11 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
     std::vector<TileDesc> tl, tr;
     int32_t ntl = 0, ntr = 0;
     // Timing sample: the equivalent of 64 tiles of 16 K blocks per CU, at
-    // least 8 and at most 64 tiles per CU, as groups of 8 consecutive list
-    // positions spread evenly over the list (a group keeps the XCD order's
-    // placement, and a longest-first list is sampled at every length).
+    // least 8 and at most 64 tiles per CU, as 8 windows of consecutive list
+    // positions spread evenly over the list.  A window keeps the XCD order's
+    // placement and the operand reuse between neighbouring tiles that the
+    // orders differ in; the spread samples a longest-first list at every
+    // length.
     const size_t cap = static_cast<size_t>(64) * ctx->num_cu;
     const size_t floor_tiles = static_cast<size_t>(8) * ctx->num_cu;
     TileDesc *tmp_tiles = nullptr;
@@ -676,13 +678,16 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
                 a.ntiles = static_cast<int32_t>(list.size());
                 part = total;
             } else {
-                const size_t stride = (list.size() + n_sample - 1) / n_sample * 8;
+                constexpr size_t kWindows = 8;
+                const size_t wlen = std::max<size_t>(n_sample / kWindows / 8 * 8, 8);
                 std::vector<TileDesc> sample;
-                for (size_t g = 0; g < list.size(); g += stride)
-                    for (size_t j = g; j < std::min(g + 8, list.size()); ++j) {
+                for (size_t w = 0; w < kWindows; ++w) {
+                    const size_t start = (w * list.size() / kWindows) / 8 * 8;
+                    for (size_t j = start; j < std::min(start + wlen, list.size()); ++j) {
                         sample.push_back(list[j]);
                         part += cost[j];
                     }
+                }
                 if ((e = hipMemcpy(tmp_tiles, sample.data(), sizeof(TileDesc) * sample.size(), hipMemcpyHostToDevice)) != hipSuccess) {
                     hipFree(tmp_sigma);
                     hipFree(tmp_tiles);
