@@ -444,6 +444,8 @@ __device__ __forceinline__ void pair_tile(const PairArgs &a, GetTerm get_term, i
 // start with an empty pipeline and the epilogue runs while that load is in
 // flight.  Same arithmetic as pair_tile, term by term.
 
+// One K block, as stage_step; on the item's last block the loads started
+// into `nxt` are the first block of the next item, if there is one.
 template <int S, int G, int WM, int WN, int MB, int NB, typename F, typename LP>
 __device__ __forceinline__ void stream_step(v16i (&acc)[G][MB][NB], F &f, const uint4 *cur, uint4 *nxt,
                                             const LP &lp, int kb, int nkb, bool has_next, const TermDesc &next,
