@@ -6,10 +6,12 @@ Headline (one JSON line on stdout): emulated-FP64 TFLOP/s (2 n^3 / wall time of
 one ozaki_dgemm call, exponents + slicing + pair GEMMs + recombination) for the
 square n = 8192 GEMM with N(0,1) 2^u entries, u in [-10, 10], at the smallest
 slice count whose error against the double-double reference is no larger than
-that of the native FP64 MFMA GEMM ("equal error").  The same line carries the
-per-slice table, the FP64 MFMA rate, the roofline of the dominant kernel (the
-int8 pair GEMM, timed with HIP events on its own stream), H_eff.psi applies/s
-and the CPU oracle timed on a bounded sample.
+that of the native FP64 MFMA GEMM ("equal error").  The last stdout line is a
+compact record (a few KB): the headline, the roofline of the dominant kernel
+(the int8 pair GEMM, timed with HIP events on its own stream), the CPU oracle
+timed on a bounded sample, the FP64 rates and errors, and the H_eff.psi
+applies/s and Davidson figures as scalars.  Every section's full tables go to
+the file named by --full-json; progress goes to stderr.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 8192] [--no-cpu]
 """
@@ -67,20 +69,25 @@ def gemm_section(args, ozaki, ctx, torch, oracle):
     log("[bench] double-double reference on %d sampled rows" % len(rows))
     t0 = time.perf_counter()
     hi, lo = oracle.dgemm_dd(A[rows], B)
+    absAB = np.abs(A[rows]) @ np.abs(B)
     log("[bench]   dd reference %.1f s" % (time.perf_counter() - t0))
     flops = 2.0 * n * n * n
     idx = torch.from_numpy(rows).cuda()
+
+    def errs(X):
+        x = X[idx].cpu().numpy()
+        return oracle.rel_frobenius(x, hi, lo), oracle.componentwise(x, hi, lo, absAB)
 
     results = []
     C = torch.empty((n, n), dtype=torch.float64, device="cuda")
     # native FP64 MFMA
     ctx.dgemm(dA, dB, slices=0, C=C)
-    err64 = oracle.rel_frobenius(C[idx].cpu().numpy(), hi, lo)
+    err64, cw64 = errs(C)
     ctx.set_timing(True)
     t = time_calls(lambda: ctx.dgemm(dA, dB, slices=0, C=C), args.steps, args.warmup, torch)
     ph = phase_means(ctx, ["fp64"])
     fp64 = {"slices": 0, "ms": t * 1e3, "tflops": flops / t / 1e12, "rel_frobenius": err64,
-            "kernel_ms": ph["fp64"][0], "frac_of_fp64_peak": flops / t / 1e12 / FP64_PEAK_TFLOPS}
+            "componentwise": cw64, "kernel_ms": ph["fp64"][0], "frac_of_fp64_peak": flops / t / 1e12 / FP64_PEAK_TFLOPS}
     log("[bench] fp64 mfma: %.3f ms  %.2f TFLOP/s  relF %.2e" % (t * 1e3, fp64["tflops"], err64))
 
     # a plain device copy of known size (1 GiB read + 1 GiB written): the
@@ -92,9 +99,9 @@ def gemm_section(args, ozaki, ctx, torch, oracle):
     del cal, cal2
     # external reference: the vendor FP64 GEMM behind torch.mm (rocBLAS / hipBLASLt)
     Ct = torch.mm(dA, dB)
-    err_t = oracle.rel_frobenius(Ct[idx].cpu().numpy(), hi, lo)
+    err_t, cw_t = errs(Ct)
     t = time_calls(lambda: torch.mm(dA, dB, out=Ct), args.steps, args.warmup, torch)
-    vendor = {"ms": t * 1e3, "tflops": flops / t / 1e12, "rel_frobenius": err_t,
+    vendor = {"ms": t * 1e3, "tflops": flops / t / 1e12, "rel_frobenius": err_t, "componentwise": cw_t,
               "frac_of_fp64_peak": flops / t / 1e12 / FP64_PEAK_TFLOPS,
               "note": "torch.mm float64 (vendor BLAS), timed as an external reference"}
     log("[bench] vendor fp64 (torch.mm): %.3f ms  %.2f TFLOP/s  relF %.2e" % (t * 1e3, vendor["tflops"], err_t))
@@ -113,7 +120,7 @@ def gemm_section(args, ozaki, ctx, torch, oracle):
             # pick the tile variant by timing them all on this GEMM (outside the timed region)
             variant, tune_ms = ctx.tune(dA, dB, slices=S, ndiag=G, C=C, workspace=ws)
         ctx.dgemm(dA, dB, slices=S, ndiag=G, C=C, workspace=ws)
-        err = oracle.rel_frobenius(C[idx].cpu().numpy(), hi, lo)
+        err, cw = errs(C)
         ctx.phase_times()
         t = time_calls(lambda: ctx.dgemm(dA, dB, slices=S, ndiag=G, C=C, workspace=ws),
                        args.steps, args.warmup, torch)
@@ -124,7 +131,7 @@ def gemm_section(args, ozaki, ctx, torch, oracle):
         r = {"slices": S, "ndiag": G, "pairs": P, "variant": variant,
              "tune_ms": {str(k): round(v, 4) for k, v in tune_ms.items()},
              "ms": t * 1e3, "tflops": flops / t / 1e12,
-             "rel_frobenius": err, "pair_kernel_ms": pair_ms, "slice_ms": slice_ms,
+             "rel_frobenius": err, "componentwise": cw, "pair_kernel_ms": pair_ms, "slice_ms": slice_ms,
              "int8_tops": P * flops / (pair_ms * 1e-3) / 1e12 if pair_ms else None}
         r["int8_frac"] = r["int8_tops"] / INT8_PEAK_TOPS if r["int8_tops"] else None
         # slicing: read A and B (8 B per element, twice: exponent pass + slice pass),
@@ -132,9 +139,9 @@ def gemm_section(args, ozaki, ctx, torch, oracle):
         r["slice_gbs"] = (2 * n * n * (16 + S)) / (slice_ms * 1e-3) / 1e9 if slice_ms else None
         r["slice_hbm_frac"] = r["slice_gbs"] / HBM_PEAK_GBS if slice_ms else None
         results.append(r)
-        log("[bench] S=%d G=%d P=%2d v%d: %.3f ms  %.2f TFLOP/s  relF %.2e  pair %.3f ms (%.1f%% int8 peak)"
-            " slice %.3f ms" % (S, G, P, variant, t * 1e3, r["tflops"], err, pair_ms or 0,
-                                100 * (r["int8_frac"] or 0), slice_ms or 0))
+        log("[bench] S=%d G=%d P=%2d v%d: %.3f ms  %.2f TFLOP/s  relF %.2e comp %.2e  pair %.3f ms "
+            "(%.1f%% int8 peak) slice %.3f ms" % (S, G, P, variant, t * 1e3, r["tflops"], err, cw, pair_ms or 0,
+                                                  100 * (r["int8_frac"] or 0), slice_ms or 0))
     ctx.set_timing(False)
     S_a, G_a, st = ctx.choose_slices(dA, dB)
     auto = {"slices": S_a, "ndiag": G_a, "predicted_error": st["predicted"],
@@ -559,9 +566,17 @@ def device_record(torch):
             "memory_gib": round(p.total_memory / 2 ** 30, 1)}
 
 
-def cpu_baseline(oracle, A, B, S, G, rows_count):
-    rows = sampled_rows(A.shape[0], rows_count, seed=2)
+def cpu_baseline(oracle, A, B, S, G, seconds):
+    """The oracle's emulated GEMM at the chosen (S, G) on a bounded sample of
+    rows of A (all of B), sized from a probe so that the timed run takes about
+    ``seconds``; the rate is scaled as 2 * rows * n^2 / time."""
     n = A.shape[0]
+    probe = sampled_rows(n, 8, seed=2)
+    t0 = time.perf_counter()
+    oracle.ozaki_dgemm(A[probe], B, S, G)
+    per_row = (time.perf_counter() - t0) / len(probe)
+    count = int(min(max(seconds / max(per_row, 1e-9), 8), n))
+    rows = sampled_rows(n, count, seed=2)
     t0 = time.perf_counter()
     oracle.ozaki_dgemm(A[rows], B, S, G)
     t = time.perf_counter() - t0
@@ -577,8 +592,12 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=8192)
-    ap.add_argument("--err-rows", type=int, default=16)
-    ap.add_argument("--cpu-rows", type=int, default=256)
+    ap.add_argument("--err-rows", type=int, default=256,
+                    help="rows of the n = 8192 product checked against the double-double reference")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="target length of the timed CPU-oracle sample")
+    ap.add_argument("--full-json", default=os.path.join("gpurun_out", "bench_full.json"),
+                    help="file for the full record (every section's tables); '' to skip")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--sections", default="gemm,dense,sparse,davidson,stability,rdm,sweep",
                     help="comma list of gemm, dense, sparse, davidson, stability, rdm, sweep "
@@ -615,7 +634,7 @@ def main():
     cpu = None
     if not args.no_cpu:
         log("[bench] CPU oracle sample")
-        cpu = cpu_baseline(oracle, A, B, chosen["slices"], chosen["ndiag"], args.cpu_rows)
+        cpu = cpu_baseline(oracle, A, B, chosen["slices"], chosen["ndiag"], args.cpu_seconds)
     del A, B
     extra = {}
     if "dense" in sections:
@@ -651,6 +670,56 @@ def main():
         extra["rdm"] = rdm_section(args, ozaki, ctx, torch)
     if "sweep" in sections:
         extra["gemm_sweep"] = sweep_section(args, ozaki, ctx, torch, oracle)
+    roofline = {"bound": "mfma", "achieved": chosen["int8_tops"], "peak": INT8_PEAK_TOPS,
+                "unit": "TFLOP/s", "frac": chosen["int8_frac"],
+                "traffic": pair_traffic(gemm["n"], chosen["slices"], chosen["ndiag"], chosen["variant"]),
+                "kernel": "k_pair_single variant %d: pairs * 2n^3 int8 ops / mean kernel time "
+                          "(HIP events on its stream)" % chosen["variant"],
+                "algorithmic_bytes": pair_bytes(gemm["n"], chosen["slices"]),
+                "kernel_ms": chosen["pair_kernel_ms"]}
+    full = {
+        "config": {"n": gemm["n"], "U": 10, "slices": chosen["slices"], "ndiag": chosen["ndiag"],
+                   "variant": chosen["variant"], "rows_for_error": gemm["rows_for_error"]},
+        "roofline": roofline,
+        "fp64_mfma": gemm["fp64"],
+        "vendor_fp64": gemm["vendor_fp64"],
+        "emulated_per_slices": gemm["emulated"],
+        "at_1e-12": gemm["at_1e-12"],
+        "automatic_width": gemm["auto"],
+        "cpu_baseline": cpu,
+        "device": device_record(torch),
+    }
+    full.update(extra)
+    if args.full_json:
+        d = os.path.dirname(args.full_json)
+        if d:
+            os.makedirs(d, exist_ok=True)
+        with open(args.full_json, "w") as fh:
+            json.dump(full, fh, indent=1)
+        log("[bench] full record written to %s" % args.full_json)
+
+    def heff_scalar(key):
+        sec = extra.get(key)
+        if not sec:
+            return None
+        s6 = [r for r in sec["emulated"] if r["slices"] == 6]
+        if not s6:
+            return None
+        r = s6[0]
+        return {"slices": 6, "applies_per_s": round(r["applies_per_s"], 3), "ms": round(r["ms"], 3),
+                "tflops": round(r["tflops"], 2), "int8_frac_pair_phases": r["int8_frac_pair_phases"],
+                "fp64_applies_per_s": round(sec["fp64"]["applies_per_s"], 3),
+                "rel_err_vs_fp64": r["rel_frobenius_vs_fp64"]}
+
+    dav = None
+    if "davidson" in extra:
+        runs = extra["davidson"]["runs"]
+        r6 = [r for r in runs if r["slices"] == 6]
+        r0 = [r for r in runs if r["slices"] == 0]
+        if r6 and r0:
+            dav = {"D": extra["davidson"]["D"], "slices": 6, "ms_per_iteration": round(r6[0]["ms_per_iteration"], 3),
+                   "iterations": r6[0]["iterations"], "energy_error_vs_fp64": r6[0]["energy_error_vs_fp64"],
+                   "fp64_ms_per_iteration": round(r0[0]["ms_per_iteration"], 3)}
     line = {
         "metric": "Emulated-FP64 TFLOP/s vs native FP64 MFMA at equal error; H_eff.psi applies/s",
         "value": chosen["tflops"],
@@ -662,36 +731,32 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int8",
+        "dtype": "fp64-emulated (int8 slices, int32 accumulation, fp64 recombination)",
         "data": "synthetic",
-        "config": {"workload": "emulated DGEMM n=%d, entries N(0,1)*2^u, u in [-10,10], seed 0; "
-                               "slices=%d ndiag=%d (equal error with FP64 MFMA)"
-                               % (gemm["n"], chosen["slices"], chosen["ndiag"]),
-                   "n": gemm["n"], "slices": chosen["slices"], "ndiag": chosen["ndiag"]},
-        "roofline": {"bound": "mfma", "achieved": chosen["int8_tops"], "peak": INT8_PEAK_TOPS,
-                     "unit": "TFLOP/s", "frac": chosen["int8_frac"],
-                     "traffic": pair_traffic(gemm["n"], chosen["slices"], chosen["ndiag"], chosen["variant"]),
-                     "kernel": "int8 pair GEMM k_pair_single (variant %d); achieved = pairs * 2n^3 int8 "
-                               "ops / mean kernel time (HIP events on its stream)" % chosen["variant"],
-                     "algorithmic_bytes": pair_bytes(gemm["n"], chosen["slices"]),
-                     "kernel_ms": chosen["pair_kernel_ms"]},
-        "fp64_mfma": gemm["fp64"],
-        "vendor_fp64": gemm["vendor_fp64"],
+        "config": {"workload": "emulated DGEMM n=%d, entries N(0,1)*2^u, u in [-10,10], seed 0; S=%d G=%d, "
+                               "the fastest width at equal error with FP64 MFMA (%d sampled rows vs "
+                               "double-double)" % (gemm["n"], chosen["slices"], chosen["ndiag"],
+                                                   gemm["rows_for_error"]),
+                   "n": gemm["n"], "slices": chosen["slices"], "ndiag": chosen["ndiag"],
+                   "variant": chosen["variant"]},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "error": {"emulated_rel_frobenius": chosen["rel_frobenius"], "emulated_componentwise": chosen["componentwise"],
+                  "fp64_rel_frobenius": gemm["fp64"]["rel_frobenius"],
+                  "fp64_componentwise": gemm["fp64"]["componentwise"],
+                  "vendor_rel_frobenius": gemm["vendor_fp64"]["rel_frobenius"]},
+        "fp64_mfma_tflops": gemm["fp64"]["tflops"],
+        "vendor_fp64_tflops": gemm["vendor_fp64"]["tflops"],
         "speedup_vs_fp64": gemm["fp64"]["ms"] / chosen["ms"],
         "speedup_vs_vendor_fp64": gemm["vendor_fp64"]["ms"] / chosen["ms"],
-        "emulated_per_slices": gemm["emulated"],
-        "at_1e-12": gemm["at_1e-12"],
-        "automatic_width": gemm["auto"],
-        "cpu_baseline": cpu,
-        "device": device_record(torch),
-        "paper_context": "The paper prints no absolute throughput for the emulated DGEMM or H_eff (its "
-                         "figures are not available). In text, on DGX B200 with NVIDIA's pre-release "
-                         "cuBLAS emulation: eager mode makes the H_eff diagonalisation markedly slower "
-                         "for S >= 3 than native FP64, performant mode recovers the native profile and "
-                         "slightly improves on it at large D; native FP64 peak of the diagonalisation on "
-                         "B200 is 10-15% below H100 at large D. Context only, not a target.",
+        "at_1e-12": None if gemm["at_1e-12"] is None else
+        {"slices": gemm["at_1e-12"]["slices"], "ndiag": gemm["at_1e-12"]["ndiag"],
+         "tflops": gemm["at_1e-12"]["tflops"], "rel_frobenius": gemm["at_1e-12"]["rel_frobenius"]},
+        "heff_dense": heff_scalar("heff_dense"),
+        "heff_sparse": heff_scalar("heff_sparse"),
+        "davidson": dav,
+        "full_record": args.full_json or None,
     }
-    line.update(extra)
     print(json.dumps(line), flush=True)
 
 

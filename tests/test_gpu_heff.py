@@ -164,6 +164,27 @@ def test_dense_d2048_sampled_rows(oz):
     assert_bitexact(got, ref, "D=2048 rows")
 
 
+@pytest.mark.timeout(1200)
+def test_dense_benchmark_shape_sampled_rows(oz):
+    """The benchmark's dense workload itself: D = 2048, phys 16, Kop = 64,
+    S = 6 (a 64-term ordered sigma accumulation per tile), with the plan's
+    timed launch choice.  Two rows alpha' (all j, beta') from the oracle."""
+    ozaki, ctx, torch = oz
+    print("[test] dense D=2048 Kop=64 phys=16 S=6: generating", flush=True)
+    L, R, psi = wl.heff_dense(D=2048, kop=64, phys=16, seed=0)
+    plan, dpsi, keep = dense_plan(ozaki, ctx, torch, L, R, psi, 6)
+    print("[test] plan variants %s launches %s; applying" % (plan.variants, plan.launches), flush=True)
+    sig = plan.apply(dpsi).reshape(2048, 16, 2048)
+    rows = [1037, 2047]
+    got = sig[rows].cpu().numpy()
+    plan.close()
+    del sig, dpsi, keep
+    torch.cuda.empty_cache()
+    print("[test] oracle rows %s" % rows, flush=True)
+    ref = oracle.heff_dense_rows(L, R, psi, rows, S=6)
+    assert_bitexact(got, ref, "D=2048 Kop=64 rows")
+
+
 def small_sparse(seed):
     return wl.heff_sparse(n_sectors=9, n_triples=80, kop=5, median=60, sigma_log=0.7,
                           lo_hi=(7, 150), density=0.35, reach=2, U=12, seed=seed)
@@ -205,8 +226,10 @@ def test_sparse_fp64(oz):
 @pytest.mark.parametrize("launch", [-1, 0, 100000])
 def test_sparse_full_size_sampled_blocks(oz, launch):
     """The 40-sector, 2000-triple batch; sigma blocks depend only on their own
-    triples, so the oracle recomputes a few blocks alone.  Timed launch
-    choice, one workgroup per tile, and the streamed kernel on every CU."""
+    triples, so the oracle recomputes a few blocks alone: the three with the
+    fewest triples and the three with the most (the longest ordered
+    accumulation chains).  Timed launch choice, one workgroup per tile, and
+    the streamed kernel on every CU."""
     ozaki, ctx, torch = oz
     prob = wl.heff_sparse()
     ctx.set_heff_launch(launch)
@@ -220,7 +243,9 @@ def test_sparse_full_size_sampled_blocks(oz, launch):
     counts = {}
     for t in prob.triples:
         counts[(t[1], t[4])] = counts.get((t[1], t[4]), 0) + 1
-    pick = sorted(counts, key=lambda b: counts[b])[:3]
+    order = sorted(counts, key=lambda b: (counts[b], b))
+    pick = order[:3] + order[-3:]
+    assert counts[pick[-1]] >= 20
     for b in pick:
         sub = wl.HeffSparse(dims=prob.dims, psi_blocks=[b], psi=prob.psi, L=prob.L, R=prob.R,
                             triples=[t for t in prob.triples if (t[1], t[4]) == b])
