@@ -331,7 +331,17 @@ int heff_plan_destroy(heff_plan plan);
  * two classical Gram-Schmidt passes, one matvec).  Synchronises the stream
  * to fill *info (theta, residual norm, iteration, basis size, status) and
  * returns OZ_OK while running, or OZ_CONVERGED / OZ_STAGNATED / OZ_MAX_ITER.
- * davidson_get_vector copies the current Ritz vector (unit norm). */
+ * The Rayleigh-Ritz solve of a step is issued at the end of the step before
+ * (davidson_create issues the first), so a step reads (theta, rho) from a
+ * pinned buffer, decides, and, when it continues, issues the correction,
+ * the basis update, the matvec and the next Rayleigh-Ritz solve as one
+ * replay of a graph captured per (basis size, Ritz buffer), then
+ * synchronises once.  Replayed and directly issued steps give the same
+ * bits.  Phase timing (ozaki_ctx_set_timing) issues the launches directly.
+ * davidson_get_vector copies the Ritz vector of the theta the last step
+ * reported (unit norm).
+ * davidson_set_graphs: enable (default) or disable the graph replay;
+ * davidson_graph_count: graphs the solver holds. */
 typedef struct {
     double theta, resnorm;
     int32_t iter, m, status;
@@ -341,6 +351,8 @@ int davidson_create(ozaki_ctx ctx, davidson *out, heff_plan H, const double *hdi
                     const double *x0, int m_max, double tol, int max_iter, void *stream);
 int davidson_step(davidson dav, davidson_info *info, void *stream);
 int davidson_get_vector(davidson dav, double *x_out, void *stream);
+int davidson_set_graphs(davidson dav, int enable);
+int davidson_graph_count(davidson dav);
 int davidson_destroy(davidson dav);
 
 /* ---- Lanczos eigensolver (lowest eigenpair) ------------------------- */

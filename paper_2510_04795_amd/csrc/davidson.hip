@@ -15,6 +15,7 @@
 // All reductions use a fixed partition and a fixed tree, so a run is
 // bit-reproducible.  The host reads (theta, rho) once per step.
 #include <cmath>
+#include <type_traits>
 #include <vector>
 
 #include "runtime.h"
@@ -246,6 +247,18 @@ __global__ void k_collapse_g(double *G, int ldg, int mmax, const double *theta) 
     if (threadIdx.x == 0) G[0] = *theta;
 }
 
+// dst = src (the collapse of the basis to the Ritz pair)
+__global__ void k_copy(const double *__restrict__ src, double *__restrict__ dst, int64_t n) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        dst[i] = src[i];
+}
+
+// (theta, rho^2) into the pinned host buffer the step reads after its sync
+__global__ void k_publish(const double *__restrict__ scal, double *host) {
+    if (threadIdx.x < 2) host[threadIdx.x] = scal[threadIdx.x];
+}
+
 unsigned grid_n(int64_t n) {
     const int64_t g = ceil_div(n, 256);
     return static_cast<unsigned>(g < 1 ? 1 : (g > 4096 ? 4096 : g));
@@ -261,12 +274,22 @@ struct davidson_s {
     double tol = 0;
     std::vector<void *> allocs;
     double *V = nullptr, *W = nullptr, *G = nullptr, *hdiag = nullptr;
-    double *x = nullptr, *hx = nullptr, *r = nullptr, *t = nullptr;
+    // Ritz vectors of two consecutive Rayleigh-Ritz solves: xs[cur] is the
+    // latest, xs[rep] the one whose theta the last step reported
+    double *xs[2] = {nullptr, nullptr};
+    int cur = 0, rep = 0;
+    double *hx = nullptr, *r = nullptr, *t = nullptr;
     double *y = nullptr, *coef = nullptr, *partial = nullptr, *scal = nullptr;  // scal: theta, rho2, nrm2
     int *gate = nullptr;
-    double *host = nullptr;  // pinned: theta, rho2
+    double *host = nullptr;  // pinned: theta, rho2 of the latest Rayleigh-Ritz solve
     int m = 0, iter = 0, status = OZ_OK;
     std::vector<double> hist;
+    // Replay: the launches that follow a step's decision (correction, basis
+    // update, matvec, next Rayleigh-Ritz) depend only on the basis size and
+    // on which Ritz buffer is current, so each (m, cur) is captured once.
+    bool use_graphs = true;
+    hipStream_t cap = nullptr;
+    std::vector<hipGraphExec_t> graphs;  // index 2 m + cur
 };
 
 namespace {
@@ -279,6 +302,9 @@ int dalloc(davidson d, size_t bytes, void **p) {
 }
 
 void dfree(davidson d) {
+    for (auto g : d->graphs)
+        if (g) hipGraphExecDestroy(g);
+    if (d->cap) hipStreamDestroy(d->cap);
     for (void *p : d->allocs) hipFree(p);
     if (d->host) hipHostFree(d->host);
     delete d;
@@ -295,10 +321,9 @@ hipError_t dots(davidson d, const double *A, int64_t lda, int rows, const double
 }
 
 // V[m] := normalised, orthogonalised t; W[m] = H V[m]; new column of G.
-int expand(davidson d, hipStream_t s) {
+int expand(davidson d, int m, hipStream_t s) {
     hipError_t e;
     const int64_t n = d->n;
-    const int m = d->m;
     double *nrm2 = d->scal + 2;
     for (int pass = 0; pass < 2; ++pass) {
         if ((e = dots(d, d->V, n, m, d->t, d->coef, 1, nullptr, 0, nullptr, s)) != hipSuccess) return hip_fail(e, "davidson: projection");
@@ -320,7 +345,69 @@ int expand(davidson d, hipStream_t s) {
     // G[i][m] = G[m][i] = V[i] . W[m], i <= m
     if ((e = dots(d, d->V, n, m + 1, wm, d->G + m, d->m_max, d->G + static_cast<int64_t>(m) * d->m_max, 1, nullptr, s)) != hipSuccess)
         return hip_fail(e, "davidson: projected column");
-    d->m = m + 1;
+    return OZ_OK;
+}
+
+// Rayleigh-Ritz on the first m basis vectors, the Ritz pair into x_out (and
+// hx, r), rho^2, and (theta, rho^2) published to the pinned host buffer.
+int rayleigh_ritz(davidson d, int m, double *x_out, hipStream_t s) {
+    const int64_t n = d->n;
+    double *theta = d->scal, *rho2 = d->scal + 1;
+    hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(256), 0, s, d->G, d->m_max, m, d->y, theta);
+    const int nb = dot_blocks(n);
+    hipLaunchKernelGGL(k_ritz, dim3(nb), dim3(kDotThreads), 0, s, d->V, d->W, n, m, d->y, theta, x_out, d->hx, d->r,
+                       d->partial);
+    hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(kDotThreads), 0, s, d->partial, nb, rho2, 1, nullptr, 0, nullptr);
+    hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, s, d->scal, d->host);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? OZ_OK : hip_fail(e, "davidson: Rayleigh-Ritz");
+}
+
+// Everything a continuing step does after its decision, for basis size m and
+// current Ritz buffer c: correction, collapse when the basis is full,
+// orthogonalisation and matvec, then the next Rayleigh-Ritz into xs[c ^ 1].
+int step_tail(davidson d, int m, int c, hipStream_t s) {
+    const int64_t n = d->n;
+    const double *theta = d->scal;
+    hipLaunchKernelGGL(k_precond, dim3(grid_n(n)), dim3(256), 0, s, d->r, d->hdiag, theta, d->t, n);
+    if (m == d->m_max) {
+        hipLaunchKernelGGL(k_copy, dim3(grid_n(n)), dim3(256), 0, s, d->xs[c], d->V, n);
+        hipLaunchKernelGGL(k_copy, dim3(grid_n(n)), dim3(256), 0, s, d->hx, d->W, n);
+        hipLaunchKernelGGL(k_collapse_g, dim3(1), dim3(256), 0, s, d->G, d->m_max, d->m_max, theta);
+        m = 1;
+    }
+    int rc = expand(d, m, s);
+    if (rc != OZ_OK) return rc;
+    return rayleigh_ritz(d, m + 1, d->xs[c ^ 1], s);
+}
+
+// step_tail from a captured graph (captured the first time (m, c) is seen),
+// or issued directly when phases are being timed or graphs are off.
+int run_tail(davidson d, int m, int c, hipStream_t s) {
+    hipError_t e;
+    if (!d->use_graphs || d->ctx->timing) return step_tail(d, m, c, s);
+    hipGraphExec_t &g = d->graphs[2 * m + c];
+    if (!g) {
+        if (!d->cap && (e = hipStreamCreateWithFlags(&d->cap, hipStreamNonBlocking)) != hipSuccess)
+            return hip_fail(e, "davidson: capture stream");
+        if ((e = hipStreamBeginCapture(d->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+            return hip_fail(e, "davidson: begin capture");
+        const int rc = step_tail(d, m, c, d->cap);
+        hipGraph_t graph = nullptr;
+        e = hipStreamEndCapture(d->cap, &graph);
+        if (rc != OZ_OK) {
+            if (graph) hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_fail(e, "davidson: end capture");
+        e = hipGraphInstantiate(&g, graph, nullptr, nullptr, 0);
+        hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            g = nullptr;
+            return hip_fail(e, "davidson: instantiate");
+        }
+    }
+    if ((e = hipGraphLaunch(g, s)) != hipSuccess) return hip_fail(e, "davidson: graph launch");
     return OZ_OK;
 }
 
@@ -351,12 +438,13 @@ int davidson_create(ozaki_ctx ctx, davidson *out, heff_plan H, const double *hdi
     void *p;
 #define OZ_DA(field, bytes) \
     if ((rc = dalloc(d, (bytes), &p)) != OZ_OK) { dfree(d); return rc; } \
-    d->field = static_cast<decltype(d->field)>(p);
+    d->field = static_cast<std::remove_reference_t<decltype(d->field)>>(p);
     OZ_DA(V, sizeof(double) * m_max * n)
     OZ_DA(W, sizeof(double) * m_max * n)
     OZ_DA(G, sizeof(double) * m_max * m_max)
     OZ_DA(hdiag, sizeof(double) * n)
-    OZ_DA(x, sizeof(double) * n)
+    OZ_DA(xs[0], sizeof(double) * n)
+    OZ_DA(xs[1], sizeof(double) * n)
     OZ_DA(hx, sizeof(double) * n)
     OZ_DA(r, sizeof(double) * n)
     OZ_DA(t, sizeof(double) * n)
@@ -391,8 +479,11 @@ int davidson_create(ozaki_ctx ctx, davidson *out, heff_plan H, const double *hdi
     hipLaunchKernelGGL(k_scale_into, dim3(grid_n(n)), dim3(256), 0, s, x0, nrm2, d->V, n);
     if ((rc = heff_apply(H, d->V, d->W, s)) != OZ_OK) { dfree(d); return rc; }
     dots(d, d->V, n, 1, d->W, d->G, 1, nullptr, 0, nullptr, s);
+    // the first step's Rayleigh-Ritz solve (every later one ends the step before)
+    if ((rc = rayleigh_ritz(d, 1, d->xs[0], s)) != OZ_OK) { dfree(d); return rc; }
     if ((e = hipStreamSynchronize(s)) != hipSuccess) { dfree(d); return hip_fail(e, "davidson_create: sync"); }
     d->m = 1;
+    d->graphs.assign(2 * static_cast<size_t>(m_max + 1), nullptr);
     *out = d;
     return OZ_OK;
 }
@@ -406,20 +497,13 @@ int davidson_step(davidson d, davidson_info *info, void *stream) {
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e;
     if ((e = hipSetDevice(d->ctx->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
-    const int64_t n = d->n;
-    double *theta = d->scal, *rho2 = d->scal + 1;
-    // Rayleigh-Ritz, Ritz pair and residual
-    hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(256), 0, s, d->G, d->m_max, d->m, d->y, theta);
-    const int nb = dot_blocks(n);
-    hipLaunchKernelGGL(k_ritz, dim3(nb), dim3(kDotThreads), 0, s, d->V, d->W, n, d->m, d->y, theta, d->x, d->hx, d->r,
-                       d->partial);
-    hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(kDotThreads), 0, s, d->partial, nb, rho2, 1, nullptr, 0, nullptr);
-    if ((e = hipMemcpyAsync(d->host, d->scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess ||
-        (e = hipStreamSynchronize(s)) != hipSuccess)
-        return hip_fail(e, "davidson_step: Rayleigh-Ritz");
+    // the Rayleigh-Ritz solve on the current basis ended the previous step
+    // (or davidson_create): its theta and rho^2 are in the pinned buffer
     d->iter += 1;
+    const double theta = d->host[0];
     const double rho = std::sqrt(d->host[1]);
     d->hist.push_back(rho);
+    d->rep = d->cur;
     int status = OZ_OK;
     const size_t w = 20;
     if (rho <= d->tol) {
@@ -438,26 +522,38 @@ int davidson_step(davidson d, davidson_info *info, void *stream) {
     }
     if (status == OZ_OK && d->iter >= d->max_iter) status = OZ_MAX_ITER;
     if (status == OZ_OK) {
-        hipLaunchKernelGGL(k_precond, dim3(grid_n(n)), dim3(256), 0, s, d->r, d->hdiag, theta, d->t, n);
-        if (d->m == d->m_max) {
-            hipMemcpyAsync(d->V, d->x, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
-            hipMemcpyAsync(d->W, d->hx, sizeof(double) * n, hipMemcpyDeviceToDevice, s);
-            hipLaunchKernelGGL(k_collapse_g, dim3(1), dim3(256), 0, s, d->G, d->m_max, d->m_max, theta);
-            d->m = 1;
-        }
-        int rc = expand(d, s);
+        // correction, basis update, matvec and the next Rayleigh-Ritz solve:
+        // one graph replay and one synchronisation per step
+        const int m = d->m;
+        int rc = run_tail(d, m, d->cur, s);
         if (rc != OZ_OK) return rc;
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "davidson_step: sync");
+        d->m = (m == d->m_max ? 1 : m) + 1;
+        d->cur ^= 1;
     }
     d->status = status;
-    if (info) *info = davidson_info{d->host[0], rho, d->iter, d->m, status};
+    if (info) *info = davidson_info{theta, rho, d->iter, d->m, status};
     return status;
+}
+
+int davidson_set_graphs(davidson d, int enable) {
+    if (!d) return fail(OZ_ERR_ARG, "davidson_set_graphs: NULL solver");
+    d->use_graphs = enable != 0;
+    return OZ_OK;
+}
+
+int davidson_graph_count(davidson d) {
+    if (!d) return fail(OZ_ERR_ARG, "davidson_graph_count: NULL solver");
+    int k = 0;
+    for (auto g : d->graphs) k += g != nullptr;
+    return k;
 }
 
 int davidson_get_vector(davidson d, double *x_out, void *stream) {
     if (!d || !x_out) return fail(OZ_ERR_ARG, "davidson_get_vector: NULL argument");
     if (d->iter == 0) return fail(OZ_ERR_STATE, "davidson_get_vector: no step taken yet");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e = hipMemcpyAsync(x_out, d->x, sizeof(double) * d->n, hipMemcpyDeviceToDevice, s);
+    hipError_t e = hipMemcpyAsync(x_out, d->xs[d->rep], sizeof(double) * d->n, hipMemcpyDeviceToDevice, s);
     return e == hipSuccess ? OZ_OK : hip_fail(e, "davidson_get_vector");
 }
 

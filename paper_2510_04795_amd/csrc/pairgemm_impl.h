@@ -209,9 +209,39 @@ __device__ __forceinline__ void stage_step(v16i (&acc)[G][MB][NB], F &f, const u
     f = g;
 }
 
-// Exact diagonal sums of one tile for one term, accumulated over all K blocks.
+// One K block of the prefetching main loop.  On entry the fragments of block
+// kb are in `cur` (their reads may still be in flight) and the loads of
+// block kb + 1 into `rd` are in flight.  After the wait and the barrier
+// (block kb + 1 complete in `rd`, every wave's reads of `fill` done), the
+// fragments of block kb + 1 are read into `nxt`, the loads of block kb + 2
+// into `fill` are started (after the reads in program order, so no LDS read
+// is ever issued while a load into LDS is pending), and the MFMAs of block
+// kb run from registers: the matrix cores start right after the barrier,
+// and the LDS reads have the whole step to arrive.  The last step of a term
+// also reads a set of fragments (nothing is pending on `rd` then; the
+// values go unused), so every step is the same code and the accumulators
+// keep their registers.
+template <int S, int G, int WM, int WN, int MB, int NB, typename F, typename LP>
+__device__ __forceinline__ void prefetch_step(v16i (&acc)[G][MB][NB], F &cur, uint4 *fill, const uint4 *rd,
+                                           const LP &lp, int kb, int nkb, int wm, int wn, int half, int l32) {
+    if (kb + 1 < nkb) {
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    }
+    F nxt;
+    read_stage<S, G, WM, WN, MB, NB>(nxt, rd, wm, wn, half, l32);
+    if (kb + 2 < nkb) lp.issue(fill, kb + 2);
+    __builtin_amdgcn_sched_barrier(0);
+    mfma_pairs<true, S, G, MB, NB>(acc, cur);
+    mfma_pairs<false, S, G, MB, NB>(acc, cur);
+    __builtin_amdgcn_sched_barrier(0);
+    cur = nxt;
+}
+
+// Exact diagonal sums of one tile for one term, with the fragments read at
+// the start of each block (stage_step).
 template <int S, int G, int WM, int WN, int MB, int NB>
-__device__ __forceinline__ void pair_mainloop(v16i (&acc)[G][MB][NB], uint4 *lds0, uint4 *lds1,
+__device__ __forceinline__ void pair_mainloop_direct(v16i (&acc)[G][MB][NB], uint4 *lds0, uint4 *lds1,
                                               const TermDesc &T, int m0, int n0) {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -255,6 +285,70 @@ __device__ __forceinline__ void pair_mainloop(v16i (&acc)[G][MB][NB], uint4 *lds
     }
     if (kb < nkb) stage_step<S, G, WM, WN, MB, NB>(acc, f, lds0, lds1, lp, kb, nkb, wm, wn, half, l32);
     mfma_pairs<true, S, G, MB, NB>(acc, f);
+}
+
+// Exact diagonal sums of one tile for one term, with the fragments read one
+// block ahead (prefetch_step).
+template <int S, int G, int WM, int WN, int MB, int NB>
+__device__ __forceinline__ void pair_mainloop_prefetch(v16i (&acc)[G][MB][NB], uint4 *lds0, uint4 *lds1,
+                                              const TermDesc &T, int m0, int n0) {
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform per wave
+    const int wm = wave / WN;
+    const int wn = wave % WN;
+    const int half = lane >> 5;
+    const int l32 = lane & 31;
+    const int nkb = T.kblocks;
+
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) acc[g][mb][nb] = v16i{};
+    if (nkb == 0) return;
+
+    LoadPlan<S, G, WM, WN, MB, NB> lp;
+    lp.init(T.A, T.B, T.a_rows_p, T.b_rows_p, m0, n0, wave, lane);
+    // a previous term of this block (accumulating mode) may still read the stages
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    lp.issue(lds0, 0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    Frags<S, G, MB, NB> f;
+    read_stage<S, G, WM, WN, MB, NB>(f, lds0, wm, wn, half, l32);
+    if (1 < nkb) lp.issue(lds1, 1);
+    // Blocks are taken two at a time (stage 0, stage 1) so each LDS stage is
+    // its own object; the loop has a single exit and an odd last block is
+    // peeled.
+    int kb = 0;
+    for (; kb + 2 <= nkb; kb += 2) {
+        prefetch_step<S, G, WM, WN, MB, NB>(acc, f, lds0, lds1, lp, kb, nkb, wm, wn, half, l32);
+        prefetch_step<S, G, WM, WN, MB, NB>(acc, f, lds1, lds0, lp, kb + 1, nkb, wm, wn, half, l32);
+    }
+    if (kb < nkb) prefetch_step<S, G, WM, WN, MB, NB>(acc, f, lds0, lds1, lp, kb, nkb, wm, wn, half, l32);
+}
+
+// Registers of one wave: accumulators, one or two fragment sets, the running
+// sigma of the accumulating mode and about 24 for addresses and counters.
+// The prefetching loop holds two fragment sets; it is used where they fit
+// the 256 registers of a wave at two waves per SIMD, else the direct loop.
+template <int S, int G, int MB, int NB, int MODE>
+__host__ __device__ constexpr bool use_prefetch() {
+    return 16 * G * MB * NB + 2 * 4 * (S < G ? S : G) * (MB + NB) + (MODE == kModeAccum ? 32 * MB * NB : 0) + 24 <=
+           256;
+}
+
+// Exact diagonal sums of one tile for one term, accumulated over all K blocks.
+template <int S, int G, int WM, int WN, int MB, int NB, int MODE>
+__device__ __forceinline__ void pair_mainloop(v16i (&acc)[G][MB][NB], uint4 *lds0, uint4 *lds1,
+                                              const TermDesc &T, int m0, int n0) {
+    if constexpr (use_prefetch<S, G, MB, NB, MODE>())
+        pair_mainloop_prefetch<S, G, WM, WN, MB, NB>(acc, lds0, lds1, T, m0, n0);
+    else
+        pair_mainloop_direct<S, G, WM, WN, MB, NB>(acc, lds0, lds1, T, m0, n0);
 }
 
 // FP64 value of one output element from its diagonal sums (plus int64 carries).
@@ -347,7 +441,7 @@ __device__ __forceinline__ void pair_tile(const PairArgs &a, GetTerm get_term, i
     for (int ti = tb; ti < tend; ++ti) {
         const TermDesc T = get_term(ti);
         v16i acc[G][MB][NB];
-        pair_mainloop<S, G, WM, WN, MB, NB>(acc, lds0, lds1, T, m0, n0);
+        pair_mainloop<S, G, WM, WN, MB, NB, MODE>(acc, lds0, lds1, T, m0, n0);
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
             const int j = n0 + (wn * NB + nb) * 32 + l32;

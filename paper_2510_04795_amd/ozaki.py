@@ -101,6 +101,8 @@ _sig("heff_plan_destroy", _i32, [_ptr])
 _sig("davidson_create", _i32, [_ptr, ctypes.POINTER(_ptr), _ptr, _ptr, _ptr, _i32, _dbl, _i32, _ptr])
 _sig("davidson_step", _i32, [_ptr, ctypes.POINTER(DavidsonInfo), _ptr])
 _sig("davidson_get_vector", _i32, [_ptr, _ptr, _ptr])
+_sig("davidson_set_graphs", _i32, [_ptr, _i32])
+_sig("davidson_graph_count", _i32, [_ptr])
 _sig("davidson_destroy", _i32, [_ptr])
 _sig("lanczos_create", _i32, [_ptr, ctypes.POINTER(_ptr), _ptr, _ptr, _i32, _dbl, _i32, _ptr])
 _sig("lanczos_step", _i32, [_ptr, ctypes.POINTER(DavidsonInfo), _ptr])
@@ -125,7 +127,7 @@ EXPORTED = [
     "ozaki_pair_products", "heff_plan_create", "heff_apply", "heff_plan_set_graphs",
     "heff_plan_graph_count", "heff_vector_length", "heff_flops",
     "heff_plan_destroy", "davidson_create", "davidson_step", "davidson_get_vector",
-    "davidson_destroy", "lanczos_create", "lanczos_step", "lanczos_get_vector", "lanczos_destroy",
+    "davidson_set_graphs", "davidson_graph_count", "davidson_destroy", "lanczos_create", "lanczos_step", "lanczos_get_vector", "lanczos_destroy",
     "rdm_eig_create", "rdm_eig_solve", "rdm_eig_destroy", "ozaki_renormalize_workspace_bytes",
     "ozaki_renormalize",
 ]
@@ -526,6 +528,13 @@ class Davidson:
                "davidson_get_vector")
         return out
 
+    def set_graphs(self, enable: bool):
+        _check(_lib.davidson_set_graphs(self.handle, 1 if enable else 0), "davidson_set_graphs")
+
+    @property
+    def graph_count(self) -> int:
+        return _check(_lib.davidson_graph_count(self.handle), "davidson_graph_count")
+
     def run(self, stream=None):
         """Iterate until a terminal status; returns (theta, status, iterations, residual)."""
         while True:
@@ -591,7 +600,7 @@ class Lanczos:
 
 class RdmEig:
     """Eigenpairs of a symmetric positive semidefinite matrix (a reduced
-    density matrix) by one-sided block Jacobi on the device; the GEMMs run
+    density matrix) by two-sided block Jacobi on the device; the GEMMs run
     emulated (slices >= 2) or in native FP64 (slices = 0)."""
 
     def __init__(self, ctx: Context, n: int, slices: int = 0, ndiag: int = 0):

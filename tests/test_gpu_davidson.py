@@ -71,6 +71,34 @@ def test_matches_oracle_davidson(oz, S):
     assert abs(its - its_ref) <= 2
 
 
+@pytest.mark.parametrize("S,m_max", [(0, 32), (6, 32), (5, 4)])
+def test_graph_replay_matches_direct(oz, S, m_max):
+    """Steps replayed from the per-(basis size, Ritz buffer) graphs give the
+    directly issued steps' bits: theta and residual of every step, the basis
+    size, the status and the Ritz vector reported after every step (with a
+    restart of a four-vector basis included)."""
+    ozaki, ctx, torch = oz
+    prob = wl.davidson_problem(D=24, kop=6, seed=3)
+    runs = []
+    for graphs in (False, True):
+        dav, keep = solver(ozaki, ctx, torch, prob, S, m_max=m_max, tol=1e-10)
+        dav.set_graphs(graphs)
+        hist = []
+        while True:
+            info = dav.step()
+            hist.append((info.theta, info.resnorm, info.m, info.status, dav.vector().cpu().numpy().tobytes()))
+            if info.status != ozaki.OZ_OK:
+                break
+        runs.append((hist, dav.graph_count))
+        dav.close()
+    (h0, n0), (h1, n1) = runs
+    assert n0 == 0 and n1 > 0
+    assert len(h0) == len(h1) > 3
+    for a, b in zip(h0, h1):
+        assert a[:4] == b[:4] and a[4] == b[4]
+    assert h1[-1][3] in (ozaki.OZ_CONVERGED, ozaki.OZ_STAGNATED)
+
+
 def test_restart_small_basis(oz):
     ozaki, ctx, torch = oz
     prob = wl.davidson_problem(D=12, kop=6)
