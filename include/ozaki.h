@@ -133,6 +133,24 @@ int ozaki_dgemm(ozaki_ctx ctx, char transa, char transb, int64_t M, int64_t N, i
                 double beta, double *C, int64_t ldc, int slices, int ndiag,
                 void *workspace, size_t workspace_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * ozaki_dgemm with the same arguments, arithmetic and results, whose
+ * workspace is a library-held device buffer of OZ_STATIC_WORKSPACE_BYTES on
+ * each GPU (held from the library's load on that GPU until the process
+ * ends; its address is looked up by ozaki_ctx_create).  The call allocates
+ * nothing and does not synchronise.  Products that need more workspace than
+ * that (ozaki_dgemm_workspace_bytes; e.g. square n = 2048 needs 57 MiB at
+ * S = 7 and 64 MiB at S = 8) fail with OZ_ERR_WORKSPACE before anything is
+ * launched.  Nothing in the buffer must start at zero: every call writes
+ * what it reads.  All calls on one GPU share the buffer, so calls whose
+ * execution overlaps on one GPU (other streams, other host threads) race:
+ * order them, e.g. issue them on one stream.  Errors as ozaki_dgemm. */
+#define OZ_STATIC_WORKSPACE_BYTES (96ull << 20)
+int ozaki_dgemm_static(ozaki_ctx ctx, char transa, char transb, int64_t M, int64_t N, int64_t K,
+                       double alpha, const double *A, int64_t lda, const double *B, int64_t ldb,
+                       double beta, double *C, int64_t ldc, int slices, int ndiag, void *stream);
+
 /* ---- emulation modes: mantissa width, automatic width, dispatch ------ */
 /* The paper's library lets the user give the mantissa width, or finds the
  * width that keeps native FP64 accuracy itself, and uses emulation eagerly

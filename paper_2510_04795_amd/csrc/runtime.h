@@ -16,6 +16,7 @@ struct ozaki_ctx_s {
     int num_cu = 0;
     uint32_t *d_flags = nullptr;  // sticky OZ_FLAG_* bits on the device
     void *scratch = nullptr;      // grow-only scratch of the debug entry points
+    void *static_ws = nullptr;    // this device's copy of the static workspace (ozaki_dgemm_static)
     size_t scratch_bytes = 0;
     // tile variant of the pair GEMM per (S, G); -1 = library default
     int variant[9][16];

@@ -4,17 +4,43 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "../../include/ozaki.h"
 #include "internal.h"
 #include "runtime.h"
 
+// Workspace of ozaki_dgemm_static: one copy per GPU, held until the process
+// ends.  Host code never uses this name as an address: the device address of
+// each GPU's copy comes from hipGetSymbolAddress (static_scratch below).
+static __device__ __align__(256) unsigned char scratch[OZ_STATIC_WORKSPACE_BYTES];
+
 namespace oz {
 
 namespace {
 thread_local std::string g_last_error;
+
+// Device address of `scratch` per device, looked up once per device (with
+// that device current) by the first ozaki_ctx_create on it.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t static_scratch(int device, void **out) {
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = p;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
 }
+}  // namespace
 
 int fail(int code, const char *fmt, ...) {
     char buf[512];
@@ -137,6 +163,10 @@ int ozaki_ctx_create(ozaki_ctx *out, int device) {
         return hip_fail(e, "hipGetDeviceProperties");
     }
     c->num_cu = prop.multiProcessorCount;
+    if ((e = static_scratch(device, &c->static_ws)) != hipSuccess) {
+        delete c;
+        return hip_fail(e, "ozaki_ctx_create: address of the static workspace");
+    }
     if ((e = hipMalloc(&c->d_flags, sizeof(uint32_t))) != hipSuccess) {
         delete c;
         return hip_fail(e, "hipMalloc(flags)");
@@ -425,6 +455,27 @@ int ozaki_dgemm(ozaki_ctx ctx, char transa, char transb, int64_t M, int64_t N, i
     e = launch_pair_single(slices, G, var, a, tiles_m, s);
     phase(ctx, OZ_PHASE_PAIR, t1, mark(ctx, s));
     return e == hipSuccess ? OZ_OK : hip_fail(e, "ozaki_dgemm: pair GEMM launch");
+}
+
+int ozaki_dgemm_static(ozaki_ctx ctx, char transa, char transb, int64_t M, int64_t N, int64_t K,
+                       double alpha, const double *A, int64_t lda, const double *B, int64_t ldb,
+                       double beta, double *C, int64_t ldc, int slices, int ndiag, void *stream) {
+    if (!ctx) return fail(OZ_ERR_ARG, "ozaki_dgemm_static: ctx is NULL");
+    if (!ctx->static_ws) return fail(OZ_ERR_STATE, "ozaki_dgemm_static: no static workspace on this device");
+    // the same checks as ozaki_dgemm decide the workspace size; anything
+    // they reject is reported by ozaki_dgemm itself below
+    size_t need = 0;
+    if (slices >= 2 && slices <= 8 && M >= 0 && N >= 0 && K >= 0) {
+        const int G = resolve_ndiag(slices, ndiag);
+        if (valid_sg(slices, G)) need = gemm_workspace(M, N, K, slices, G).total;
+    }
+    if (need > OZ_STATIC_WORKSPACE_BYTES)
+        return fail(OZ_ERR_WORKSPACE,
+                    "ozaki_dgemm_static: the product needs %zu bytes of workspace, above the static %llu "
+                    "(use ozaki_dgemm with a workspace of ozaki_dgemm_workspace_bytes)",
+                    need, static_cast<unsigned long long>(OZ_STATIC_WORKSPACE_BYTES));
+    return ozaki_dgemm(ctx, transa, transb, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, slices, ndiag,
+                       ctx->static_ws, OZ_STATIC_WORKSPACE_BYTES, stream);
 }
 
 int ozaki_split(ozaki_ctx ctx, int by_columns, int64_t rows, int64_t cols, const double *X,

@@ -17,6 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libozaki.so")
 
 OZ_OK, OZ_CONVERGED, OZ_STAGNATED, OZ_MAX_ITER = 0, 1, 2, 3
+OZ_STATIC_WORKSPACE_BYTES = 96 << 20
 OZ_FLAG_NONFINITE = 1
 OZ_EXP_NONFINITE = -(2 ** 31)
 PHASES = {1: "slice", 2: "pair", 3: "fp64", 4: "heff_L", 5: "heff_R", 6: "heff_aux"}
@@ -83,6 +84,8 @@ _sig("ozaki_max_exact_k", _i64, [_i32, _i32])
 _sig("ozaki_dgemm_workspace_bytes", _sz, [_i64, _i64, _i64, _i32, _i32])
 _sig("ozaki_dgemm", _i32, [_ptr, ctypes.c_char, ctypes.c_char, _i64, _i64, _i64, _dbl, _ptr, _i64,
                            _ptr, _i64, _dbl, _ptr, _i64, _i32, _i32, _ptr, _sz, _ptr])
+_sig("ozaki_dgemm_static", _i32, [_ptr, ctypes.c_char, ctypes.c_char, _i64, _i64, _i64, _dbl, _ptr, _i64,
+                                  _ptr, _i64, _dbl, _ptr, _i64, _i32, _i32, _ptr])
 _sig("ozaki_dgemm_auto_workspace_bytes", _sz, [_i64, _i64, _i64])
 _sig("ozaki_choose_slices", _i32, [_ptr, ctypes.c_char, ctypes.c_char, _i64, _i64, _i64, _ptr, _i64, _ptr,
                                    _i64, _ptr, _sz, _ptr, _ptr, _ptr, _ptr])
@@ -122,7 +125,7 @@ EXPORTED = [
     "ozaki_pair_variants", "ozaki_ctx_set_variant", "ozaki_ctx_get_variant",
     "ozaki_ctx_set_autotune", "ozaki_ctx_set_heff_launch", "ozaki_dgemm_tune", "heff_plan_variants",
     "heff_plan_launches", "ozaki_slices_for_bits", "ozaki_pair_count",
-    "ozaki_max_exact_k", "ozaki_dgemm_workspace_bytes", "ozaki_dgemm", "ozaki_split",
+    "ozaki_max_exact_k", "ozaki_dgemm_workspace_bytes", "ozaki_dgemm", "ozaki_dgemm_static", "ozaki_split",
     "ozaki_choose_slices", "ozaki_dgemm_auto_workspace_bytes", "ozaki_dgemm_auto",
     "ozaki_pair_products", "heff_plan_create", "heff_apply", "heff_plan_set_graphs",
     "heff_plan_graph_count", "heff_vector_length", "heff_flops",
@@ -303,6 +306,25 @@ class Context:
                                 K, alpha, A.data_ptr(), _ld(A, "A"), B.data_ptr(), _ld(B, "B"),
                                 beta, C.data_ptr(), _ld(C, "C"), slices, ndiag, wptr, wlen,
                                 _stream(stream)), "ozaki_dgemm")
+        return C
+
+    def dgemm_static(self, A, B, C, slices: int = 6, ndiag: int = 0, alpha: float = 1.0, beta: float = 0.0,
+                     transa: str = "N", transb: str = "N", stream=None):
+        """ozaki_dgemm_static: as dgemm, with the library's static per-GPU
+        workspace; C (the output) is passed in, nothing is allocated."""
+        _dev_f64(A, "A")
+        _dev_f64(B, "B")
+        _dev_f64(C, "C")
+        ta, tb = transa.upper() == "T", transb.upper() == "T"
+        M = A.size(1) if ta else A.size(0)
+        K = A.size(0) if ta else A.size(1)
+        N = B.size(0) if tb else B.size(1)
+        if (B.size(1) if tb else B.size(0)) != K or tuple(C.shape) != (M, N):
+            raise ValueError("operand shapes do not match")
+        _check(_lib.ozaki_dgemm_static(self.handle, transa.upper().encode(), transb.upper().encode(), M, N,
+                                       K, alpha, A.data_ptr(), _ld(A, "A"), B.data_ptr(), _ld(B, "B"),
+                                       beta, C.data_ptr(), _ld(C, "C"), slices, ndiag, _stream(stream)),
+               "ozaki_dgemm_static")
         return C
 
     def renormalize(self, U, ops, slices: int = 6, ndiag: int = 0, outs=None, workspace=None, stream=None):
