@@ -339,23 +339,26 @@ def heff_section(args, ozaki, ctx, torch, name, layout, Lf, Rf, pf, triples, sli
         got = sig[torch.from_numpy(dd_ref[0]).cuda()].cpu().numpy()
         return float(np.max(np.abs(got - dd_ref[1])) / np.max(np.abs(dd_ref[1])))
 
-    plan, tplan, keep = heff_flat_plan(ozaki, ctx, torch, layout, Lf, Rf, triples, 0)
-    sig64 = plan.apply(dpsi)
-    t = time_calls(lambda: plan.apply(dpsi, sig64), args.heff_steps, 1, torch)
-    out["flops_per_apply"] = plan.flops
-    out["fp64"] = {"ms": t * 1e3, "applies_per_s": 1.0 / t, "tflops": plan.flops / t / 1e12,
-                   "frac_of_fp64_peak": plan.flops / t / 1e12 / FP64_PEAK_TFLOPS, "plan_s": tplan,
-                   "rel_err_vs_dd_sampled": dd_err(sig64)}
-    log("[bench] %s fp64: %.3f ms/apply  %.2f TFLOP/s  vs dd %s" % (name, t * 1e3, plan.flops / t / 1e12,
-                                                                    out["fp64"]["rel_err_vs_dd_sampled"]))
-    nrm = torch.linalg.vector_norm(sig64).item()
-    plan.close()
-    del keep
+    sig64, nrm = None, None
+    if not args.heff_no_fp64:
+        plan, tplan, keep = heff_flat_plan(ozaki, ctx, torch, layout, Lf, Rf, triples, 0)
+        sig64 = plan.apply(dpsi)
+        t = time_calls(lambda: plan.apply(dpsi, sig64), args.heff_steps, 1, torch)
+        out["flops_per_apply"] = plan.flops
+        out["fp64"] = {"ms": t * 1e3, "applies_per_s": 1.0 / t, "tflops": plan.flops / t / 1e12,
+                       "frac_of_fp64_peak": plan.flops / t / 1e12 / FP64_PEAK_TFLOPS, "plan_s": tplan,
+                       "rel_err_vs_dd_sampled": dd_err(sig64)}
+        log("[bench] %s fp64: %.3f ms/apply  %.2f TFLOP/s  vs dd %s" % (name, t * 1e3, plan.flops / t / 1e12,
+                                                                        out["fp64"]["rel_err_vs_dd_sampled"]))
+        nrm = torch.linalg.vector_norm(sig64).item()
+        plan.close()
+        del keep
     res = []
     for (S, G) in slices_list:
         plan, tplan, keep = heff_flat_plan(ozaki, ctx, torch, layout, Lf, Rf, triples, S, G)
+        out["flops_per_apply"] = plan.flops
         sig = plan.apply(dpsi)
-        err = torch.linalg.vector_norm(sig - sig64).item() / nrm
+        err = None if sig64 is None else torch.linalg.vector_norm(sig - sig64).item() / nrm
         # warm applies replay the plan's captured graph
         t = time_calls(lambda: plan.apply(dpsi, sig), args.heff_steps, 1, torch)
         # phase split: the same launches issued directly, with events between phases
@@ -380,7 +383,7 @@ def heff_section(args, ozaki, ctx, torch, name, layout, Lf, Rf, pf, triples, sli
              "int8_frac_pair_phases": (P * plan.flops / ((phs.get("heff_L", 0) + phs.get("heff_R", 0)) * 1e-3)
                                        / 1e12 / INT8_PEAK_TOPS) if phs else None}
         res.append(r)
-        log("[bench] %s S=%d G=%d: %.3f ms/apply  %.2f TFLOP/s  err vs fp64 %.2e  vs dd %s  phases %s  "
+        log("[bench] %s S=%d G=%d: %.3f ms/apply  %.2f TFLOP/s  err vs fp64 %s  vs dd %s  phases %s  "
             "variants %s streamed %s"
             % (name, S, G, t * 1e3, r["tflops"], err, r["rel_err_vs_dd_sampled"],
                {k: round(v, 3) for k, v in phs.items()}, plan.variants, plan.launches))
@@ -388,6 +391,10 @@ def heff_section(args, ozaki, ctx, torch, name, layout, Lf, Rf, pf, triples, sli
         del keep
     out["emulated"] = res
     return out
+
+
+def heff_slices(args):
+    return [(int(v), int(v)) for v in args.heff_slices.split(",")]
 
 
 def davidson_section(args, ozaki, ctx, torch):
@@ -600,8 +607,8 @@ def main():
                     help="file for the full record (every section's tables); '' to skip")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--sections", default="gemm,dense,sparse,davidson,stability,rdm,sweep",
-                    help="comma list of gemm, dense, sparse, davidson, stability, rdm, sweep "
-                         "(the GEMM section always runs)")
+                    help="comma list of gemm, dense, sparse, davidson, stability, rdm, sweep; without gemm "
+                         "(profiling runs) the last line holds the sections' records, not the headline")
     ap.add_argument("--gemm-configs", default="",
                     help="comma list of S:G for the GEMM section (default: S = 4..8, G in {S, S+1})")
     ap.add_argument("--variant", type=int, default=-1,
@@ -609,6 +616,12 @@ def main():
     ap.add_argument("--heff-d", type=int, default=2048)
     ap.add_argument("--heff-kop", type=int, default=64)
     ap.add_argument("--heff-steps", type=int, default=3)
+    ap.add_argument("--heff-slices", default="6,7,8", help="comma list of S (G = S) for the H_eff sections")
+    ap.add_argument("--heff-no-fp64", action="store_true", help="skip the FP64 H_eff plans (profiling runs)")
+    ap.add_argument("--heff-variant", type=int, default=-1,
+                    help="fixed pair-GEMM tile variant for the H_eff plans, with plan timing off (profiling runs)")
+    ap.add_argument("--heff-launch", type=int, default=-1,
+                    help="H_eff grouped launch: -1 timed choice, 0 one workgroup per tile, k > 0 streamed on k CUs")
     ap.add_argument("--dd-samples", type=int, default=3,
                     help="(i, j) pairs of the dense sigma checked against double-double (4 columns each)")
     ap.add_argument("--dav-d", type=int, default=1024)
@@ -629,13 +642,20 @@ def main():
     ctx = ozaki.Context(0)
     sections = set(args.sections.split(","))
     from paper_2510_04795_amd import workloads as wl
-    gemm, (A, B) = gemm_section(args, ozaki, ctx, torch, oracle)
-    chosen = gemm["chosen"]
-    cpu = None
-    if not args.no_cpu:
-        log("[bench] CPU oracle sample")
-        cpu = cpu_baseline(oracle, A, B, chosen["slices"], chosen["ndiag"], args.cpu_seconds)
-    del A, B
+    if args.heff_variant >= 0:
+        ctx.set_autotune(False)
+        for S, _ in heff_slices(args):
+            ctx.set_variant(S, S, args.heff_variant)
+    ctx.set_heff_launch(args.heff_launch)
+    gemm = None
+    if "gemm" in sections:
+        gemm, (A, B) = gemm_section(args, ozaki, ctx, torch, oracle)
+        chosen = gemm["chosen"]
+        cpu = None
+        if not args.no_cpu:
+            log("[bench] CPU oracle sample")
+            cpu = cpu_baseline(oracle, A, B, chosen["slices"], chosen["ndiag"], args.cpu_seconds)
+        del A, B
     extra = {}
     if "dense" in sections:
         log("[bench] generating dense two-site problem D=%d Kop=%d phys=16" % (args.heff_d, args.heff_kop))
@@ -653,7 +673,7 @@ def main():
         del L, R, psi
         extra["heff_dense"] = heff_section(
             args, ozaki, ctx, torch, "dense D=%d Kop=%d phys=16" % (args.heff_d, args.heff_kop),
-            layout, Lf, Rf, pf, triples, [(6, 6), (7, 7), (8, 8)], dd_ref=dd_ref)
+            layout, Lf, Rf, pf, triples, heff_slices(args), dd_ref=dd_ref)
         del Lf, Rf, pf
     if "sparse" in sections:
         log("[bench] generating block-sparse batch (40 sectors, 2000 triples)")
@@ -661,7 +681,7 @@ def main():
         layout, Lf, Rf, pf, triples = wl.flatten_sparse(prob)
         extra["heff_sparse"] = heff_section(
             args, ozaki, ctx, torch, "block-sparse 40 sectors, %d triples" % len(triples),
-            layout, Lf, Rf, pf, triples, [(6, 6), (7, 7), (8, 8)])
+            layout, Lf, Rf, pf, triples, heff_slices(args))
     if "davidson" in sections:
         extra["davidson"] = davidson_section(args, ozaki, ctx, torch)
     if "stability" in sections:
@@ -670,6 +690,9 @@ def main():
         extra["rdm"] = rdm_section(args, ozaki, ctx, torch)
     if "sweep" in sections:
         extra["gemm_sweep"] = sweep_section(args, ozaki, ctx, torch, oracle)
+    if gemm is None:
+        print(json.dumps({"sections": sorted(sections), "records": extra}), flush=True)
+        return
     roofline = {"bound": "mfma", "achieved": chosen["int8_tops"], "peak": INT8_PEAK_TOPS,
                 "unit": "TFLOP/s", "frac": chosen["int8_frac"],
                 "traffic": pair_traffic(gemm["n"], chosen["slices"], chosen["ndiag"], chosen["variant"]),
@@ -708,7 +731,7 @@ def main():
         r = s6[0]
         return {"slices": 6, "applies_per_s": round(r["applies_per_s"], 3), "ms": round(r["ms"], 3),
                 "tflops": round(r["tflops"], 2), "int8_frac_pair_phases": r["int8_frac_pair_phases"],
-                "fp64_applies_per_s": round(sec["fp64"]["applies_per_s"], 3),
+                "fp64_applies_per_s": round(sec["fp64"]["applies_per_s"], 3) if "fp64" in sec else None,
                 "rel_err_vs_fp64": r["rel_frobenius_vs_fp64"]}
 
     dav = None
