@@ -557,6 +557,75 @@ def rdm_section(args, ozaki, ctx, torch):
     return out
 
 
+def oracle_section(args, oracle):
+    """The CPU oracle timed beside the H_eff and Davidson workloads, on the
+    host's cores (bounded samples, each stated):
+      dense   full emulated O4 (S = 6) of the dense recipe at D = 256, Kop = 64,
+              phys 16, and one row alpha' of the D = 2048 benchmark shape;
+      sparse  full emulated O4 (S = 6) and FP64 O4 of the 40-sector batch, or
+              its first triples when the whole batch would exceed the budget;
+      davidson  FP64 Davidson at D = 16 (to convergence) and one FP64 matvec
+              of the D = 1024, Kop = 32 operator (the per-iteration cost)."""
+    from paper_2510_04795_amd import workloads as wl
+    out = {"cores": oracle.num_threads(), "cpu_model": cpu_model()}
+    t0 = time.perf_counter()
+    L, R, psi = wl.heff_dense(D=256, kop=64, phys=16)
+    t1 = time.perf_counter()
+    oracle.heff_dense(L, R, psi, S=6)
+    t = time.perf_counter() - t1
+    fl = 64.0 * 64 * 256 ** 3
+    out["dense_d256_kop64_s6"] = {"s": t, "tflops": fl / t / 1e12, "flops": fl, "sample": "full O4, D=256 Kop=64 phys=16"}
+    log("[bench] oracle dense D=256 Kop=64 S=6: %.1f s (%.4f TFLOP/s)" % (t, fl / t / 1e12))
+    del L, R, psi
+    L, R, psi = wl.heff_dense(D=args.heff_d, kop=args.heff_kop, phys=16)
+    t1 = time.perf_counter()
+    oracle.heff_dense_rows(L, R, psi, [args.heff_d // 2], S=6)
+    t = time.perf_counter() - t1
+    fl_row = 2.0 * args.heff_kop * 16 * args.heff_d * (args.heff_d * args.heff_d + args.heff_d)
+    out["dense_benchmark_row_s6"] = {"s": t, "rows": 1, "flops": fl_row, "tflops": fl_row / t / 1e12,
+                                     "full_apply_s_extrapolated": t * args.heff_d,
+                                     "sample": "one row alpha' (all j, beta') of D=%d Kop=%d phys=16, incl. the "
+                                               "column split of Psi" % (args.heff_d, args.heff_kop)}
+    log("[bench] oracle dense D=%d one row S=6: %.1f s (x%d rows = %.0f s per apply)"
+        % (args.heff_d, t, args.heff_d, t * args.heff_d))
+    del L, R, psi
+    prob = wl.heff_sparse()
+    tri = list(prob.triples)
+    for S in (6, 0):
+        t1 = time.perf_counter()
+        n_used = 0
+        sub_t = []
+        for k in range(0, len(tri), 100):
+            sub = wl.HeffSparse(dims=prob.dims, psi_blocks=prob.psi_blocks, psi=prob.psi, L=prob.L, R=prob.R,
+                                triples=tri[k:k + 100])
+            oracle.heff_sparse(sub, S=S)
+            n_used = k + 100
+            if time.perf_counter() - t1 > args.oracle_seconds:
+                break
+        t = time.perf_counter() - t1
+        frac = min(n_used, len(tri)) / len(tri)
+        key = "sparse_s6" if S else "sparse_fp64"
+        out[key] = {"s": t, "triples": min(n_used, len(tri)), "full_apply_s_extrapolated": t / frac,
+                    "sample": "O4 over the first %d of %d triples (each 100-triple slice from zero sigma)"
+                              % (min(n_used, len(tri)), len(tri))}
+        log("[bench] oracle sparse %s: %d triples in %.1f s (full apply ~%.1f s)"
+            % ("S=6" if S else "FP64", min(n_used, len(tri)), t, t / frac))
+    prob16 = wl.davidson_problem(D=16, kop=32)
+    t1 = time.perf_counter()
+    th, _, st, its, _ = oracle.davidson(oracle.heff_matvec(prob16.L, prob16.R, prob16.delta), prob16.hdiag, prob16.x0)
+    out["davidson_d16_fp64"] = {"s": time.perf_counter() - t1, "iterations": its, "status": st, "energy": th}
+    prob = wl.davidson_problem(D=args.dav_d, kop=32)
+    mv = oracle.heff_matvec(prob.L, prob.R, prob.delta)
+    t1 = time.perf_counter()
+    mv(prob.x0.ravel())
+    t = time.perf_counter() - t1
+    out["davidson_d1024_fp64_matvec"] = {"s": t, "sample": "one FP64 matvec of D=%d Kop=32 (one Davidson iteration's "
+                                                           "dominant cost)" % args.dav_d}
+    log("[bench] oracle Davidson D=16: %d iterations; FP64 matvec D=%d: %.2f s" % (its, args.dav_d, t))
+    out["total_s"] = time.perf_counter() - t0
+    return out
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -606,8 +675,10 @@ def main():
     ap.add_argument("--full-json", default=os.path.join("gpurun_out", "bench_full.json"),
                     help="file for the full record (every section's tables); '' to skip")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--sections", default="gemm,dense,sparse,davidson,stability,rdm,sweep",
-                    help="comma list of gemm, dense, sparse, davidson, stability, rdm, sweep; without gemm "
+    ap.add_argument("--oracle-seconds", type=float, default=10.0,
+                    help="budget of each bounded oracle sample in the oracle section")
+    ap.add_argument("--sections", default="gemm,dense,sparse,davidson,stability,rdm,sweep,oracle",
+                    help="comma list of gemm, dense, sparse, davidson, stability, rdm, sweep, oracle; without gemm "
                          "(profiling runs) the last line holds the sections' records, not the headline")
     ap.add_argument("--gemm-configs", default="",
                     help="comma list of S:G for the GEMM section (default: S = 4..8, G in {S, S+1})")
@@ -690,6 +761,8 @@ def main():
         extra["rdm"] = rdm_section(args, ozaki, ctx, torch)
     if "sweep" in sections:
         extra["gemm_sweep"] = sweep_section(args, ozaki, ctx, torch, oracle)
+    if "oracle" in sections and not args.no_cpu:
+        extra["oracle_timings"] = oracle_section(args, oracle)
     if gemm is None:
         print(json.dumps({"sections": sorted(sections), "records": extra}), flush=True)
         return

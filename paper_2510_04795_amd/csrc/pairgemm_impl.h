@@ -34,6 +34,14 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 typedef __attribute__((address_space(3))) void lds_void;
 
+}  // namespace pair
+}  // namespace oz
+
+#include "asm_steps.h"
+
+namespace oz {
+namespace pair {
+
 // WM x WN waves per block, each owning MB x NB blocks of 32 x 32 outputs.
 template <int S, int G, int WM, int WN, int MB, int NB>
 struct Cfg {
@@ -44,6 +52,15 @@ struct Cfg {
     static constexpr int STAGE = 2 * S * (BM + BN);     // uint4 per LDS stage
     static constexpr int A_SEG = 2 * S * BM / 64;       // 64-row wave loads for A
     static constexpr int SEGS = 2 * S * (BM + BN) / 64; // all wave loads per stage
+    static constexpr int STAGE_BYTES = STAGE * 16;
+    // loads every wave issues per stage (some waves issue one more)
+    static constexpr int NL_MIN = SEGS / NW;
+    // s_waitcnt immediates: vmcnt(n) (bits 3:0 and 15:14) with lgkmcnt(0)
+    // (bits 11:8) and expcnt at its maximum (bits 6:4)
+    static constexpr int wait_vm(int n) { return (n & 15) | (((n >> 4) & 3) << 14) | (7 << 4); }
+    static constexpr int WAIT_ALL = wait_vm(0);
+    static constexpr int WAIT_NEWEST = wait_vm(NL_MIN);      // one block's loads may stay in flight
+    static constexpr int WAIT_NEWER2 = wait_vm(2 * NL_MIN);  // two blocks' loads may stay in flight
 };
 
 // Direct-to-LDS loads of one packed K block: the stage holds 2S runs of BM
@@ -314,12 +331,14 @@ __device__ __forceinline__ void pair_mainloop_prefetch(v16i (&acc)[G][MB][NB], u
     // a previous term of this block (accumulating mode) may still read the stages
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+    // blocks 0 and 1 load together (one latency); the first step then finds
+    // block 1 complete
     lp.issue(lds0, 0);
+    if (1 < nkb) lp.issue(lds1, 1);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     Frags<S, G, MB, NB> f;
     read_stage<S, G, WM, WN, MB, NB>(f, lds0, wm, wn, half, l32);
-    if (1 < nkb) lp.issue(lds1, 1);
     // Blocks are taken two at a time (stage 0, stage 1) so each LDS stage is
     // its own object; the loop has a single exit and an odd last block is
     // peeled.
@@ -331,21 +350,147 @@ __device__ __forceinline__ void pair_mainloop_prefetch(v16i (&acc)[G][MB][NB], u
     if (kb < nkb) prefetch_step<S, G, WM, WN, MB, NB>(acc, f, lds0, lds1, lp, kb, nkb, wm, wn, half, l32);
 }
 
-// Registers of one wave: accumulators, one or two fragment sets, the running
-// sigma of the accumulating mode and about 24 for addresses and counters.
-// The prefetching loop holds two fragment sets; it is used where they fit
-// the 256 registers of a wave at two waves per SIMD, else the direct loop.
-template <int S, int G, int MB, int NB, int MODE>
+// ---- per-tile main loop: a ring of three LDS stages ------------------------
+// For waves that own one 32 x 32 block (tiles of 8 or 16 waves): step kb
+//
+//   waits until block kb + 1 has landed (this wave's loads: vmcnt, leaving
+//   block kb + 2's loads in flight), barrier (every wave's share of block
+//   kb + 1 is in LDS, and every wave has its fragments of block kb, so block
+//   kb's stage is free);
+//   starts the loads of block kb + 3 into block kb's stage;
+//   runs AsmStep: the MFMAs of block kb from registers, each fragment
+//   register refilled with block kb + 1's fragment once its last MFMA has
+//   issued (one set of fragment registers), the reads waited for at its end.
+//
+// A block's loads have two steps to arrive instead of one: the reads inside
+// AsmStep are invisible to the compiler, which therefore does not order them
+// behind the direct-to-LDS loads still in flight (with compiler-visible LDS
+// reads it waits for every such load first).  The barrier is the bare
+// s_barrier: the waits it needs are the explicit ones above (the barrier of
+// __syncthreads would first wait for every load in flight).  Reads of a
+// stage only happen once its block is complete in every wave; loads into a
+// stage only start once every wave has read it.
+template <int S, int G, int WM, int WN, int MB, int NB, int MODE>
+__host__ __device__ constexpr bool use_ring();
+
+template <int S, int G, int WM, int WN, int MB, int NB>
+struct RingAddr {
+    using C = Cfg<S, G, WM, WN, MB, NB>;
+    static constexpr int OA = 2 * C::BM * 16;  // bytes between the runs of consecutive A slices
+    static constexpr int OB = 2 * C::BN * 16;
+    // LDS byte addresses of this lane's A and B fragments of slice 0 in a stage
+    __device__ __forceinline__ static unsigned a(const uint4 *stage, int wm, int half, int l32) {
+        return static_cast<unsigned>(reinterpret_cast<uintptr_t>(stage + half * C::BM + wm * 32 + l32));
+    }
+    __device__ __forceinline__ static unsigned b(const uint4 *stage, int wn, int half, int l32) {
+        return static_cast<unsigned>(reinterpret_cast<uintptr_t>(stage + 2 * S * C::BM + half * C::BN + wn * 32 + l32));
+    }
+};
+
+template <int S, int G, int WM, int WN, int MB, int NB, typename F, typename LP>
+__device__ __forceinline__ void ring_step(v16i (&acc)[G][MB][NB], F &cur, uint4 *fill, const uint4 *rd,
+                                          const LP &lp, int kb, int nkb, int wm, int wn, int half, int l32) {
+    using C = Cfg<S, G, WM, WN, MB, NB>;
+    using RA = RingAddr<S, G, WM, WN, MB, NB>;
+    if (kb + 1 < nkb) {
+        if (kb + 2 < nkb)
+            __builtin_amdgcn_s_waitcnt(C::WAIT_NEWEST);
+        else
+            __builtin_amdgcn_s_waitcnt(C::WAIT_ALL);
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        if (kb + 3 < nkb) lp.issue(fill, kb + 3);
+    }
+    // the last step reads a stage no load is pending on; the values go unused
+    AsmStep<S, G>::template run<RA::OA, RA::OB>(acc, cur, RA::a(rd, wm, half, l32), RA::b(rd, wn, half, l32));
+}
+
+template <int S, int G, int WM, int WN, int MB, int NB>
+__device__ __forceinline__ void pair_mainloop_ring(v16i (&acc)[G][MB][NB], uint4 *lds0, uint4 *lds1, uint4 *lds2,
+                                                   const TermDesc &T, int m0, int n0) {
+    using C = Cfg<S, G, WM, WN, MB, NB>;
+    using RA = RingAddr<S, G, WM, WN, MB, NB>;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform per wave
+    const int wm = wave / WN;
+    const int wn = wave % WN;
+    const int half = lane >> 5;
+    const int l32 = lane & 31;
+    const int nkb = T.kblocks;
+
+#pragma unroll
+    for (int g = 0; g < G; ++g) acc[g][0][0] = v16i{};
+    if (nkb == 0) return;
+
+    LoadPlan<S, G, WM, WN, MB, NB> lp;
+    lp.init(T.A, T.B, T.a_rows_p, T.b_rows_p, m0, n0, wave, lane);
+    // a previous term of this block (accumulating mode) may still read the stages
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    lp.issue(lds0, 0);
+    if (1 < nkb) lp.issue(lds1, 1);
+    if (2 < nkb) lp.issue(lds2, 2);
+    if (2 < nkb)
+        __builtin_amdgcn_s_waitcnt(C::WAIT_NEWER2);
+    else if (1 < nkb)
+        __builtin_amdgcn_s_waitcnt(C::WAIT_NEWEST);
+    else
+        __builtin_amdgcn_s_waitcnt(C::WAIT_ALL);
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    Frags<S, G, MB, NB> f;
+    AsmStep<S, G>::template read<RA::OA, RA::OB>(f, RA::a(lds0, wm, half, l32), RA::b(lds0, wn, half, l32));
+    // Blocks are taken three at a time so each stage keeps its own object;
+    // the loop has a single exit and the last nkb % 3 blocks are peeled.
+    int kb = 0;
+    for (; kb + 3 <= nkb; kb += 3) {
+        ring_step<S, G, WM, WN, MB, NB>(acc, f, lds0, lds1, lp, kb, nkb, wm, wn, half, l32);
+        ring_step<S, G, WM, WN, MB, NB>(acc, f, lds1, lds2, lp, kb + 1, nkb, wm, wn, half, l32);
+        ring_step<S, G, WM, WN, MB, NB>(acc, f, lds2, lds0, lp, kb + 2, nkb, wm, wn, half, l32);
+    }
+    if (kb < nkb) ring_step<S, G, WM, WN, MB, NB>(acc, f, lds0, lds1, lp, kb, nkb, wm, wn, half, l32);
+    if (kb + 1 < nkb) ring_step<S, G, WM, WN, MB, NB>(acc, f, lds1, lds2, lp, kb + 1, nkb, wm, wn, half, l32);
+    // the accumulators were last written by matrix-core instructions inside
+    // asm blocks: wait states before ordinary instructions read them
+    asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 7" ::: "memory");
+}
+
+// Registers of one wave: accumulators, fragments, the running sigma of the
+// accumulating mode and about 24 for addresses and counters, within 256 per
+// wave at two waves per SIMD (128 at four).  The prefetching loop holds two
+// fragment sets; the ring one set plus four spare fragments.
+template <int S, int G, int WM, int WN, int MB, int NB, int MODE>
+__host__ __device__ constexpr int wave_budget_left(int frag_sets, int spares) {
+    return (WM * WN >= 16 ? 128 : 256) -
+           (16 * G * MB * NB + frag_sets * 4 * (S < G ? S : G) * (MB + NB) + 4 * spares +
+            (MODE == kModeAccum ? 32 * MB * NB : 0) + 24);
+}
+
+template <int S, int G, int WM, int WN, int MB, int NB, int MODE>
 __host__ __device__ constexpr bool use_prefetch() {
-    return 16 * G * MB * NB + 2 * 4 * (S < G ? S : G) * (MB + NB) + (MODE == kModeAccum ? 32 * MB * NB : 0) + 24 <=
-           256;
+    return wave_budget_left<S, G, WM, WN, MB, NB, MODE>(2, 0) >= 0;
+}
+
+// The ring of three stages where its conditions hold: one 32 x 32 block per
+// wave, 8 waves (the workgroup holds its compute unit alone anyway), three
+// stages within 156 KiB of LDS and the register budget (with 24 registers
+// more in hand for the accumulating mode, whose term loop keeps more live:
+// at S = G = 7 it spills without them).
+template <int S, int G, int WM, int WN, int MB, int NB, int MODE>
+__host__ __device__ constexpr bool use_ring() {
+    return AsmStep<S, G>::available && MB == 1 && NB == 1 && WM * WN == 8 &&
+           3 * Cfg<S, G, WM, WN, MB, NB>::STAGE_BYTES <= 156 * 1024 &&
+           wave_budget_left<S, G, WM, WN, MB, NB, MODE>(1, 4) >= (MODE == kModeAccum ? 24 : 0);
 }
 
 // Exact diagonal sums of one tile for one term, accumulated over all K blocks.
 template <int S, int G, int WM, int WN, int MB, int NB, int MODE>
-__device__ __forceinline__ void pair_mainloop(v16i (&acc)[G][MB][NB], uint4 *lds0, uint4 *lds1,
+__device__ __forceinline__ void pair_mainloop(v16i (&acc)[G][MB][NB], uint4 *lds0, uint4 *lds1, uint4 *lds2,
                                               const TermDesc &T, int m0, int n0) {
-    if constexpr (use_prefetch<S, G, MB, NB, MODE>())
+    if constexpr (use_ring<S, G, WM, WN, MB, NB, MODE>())
+        pair_mainloop_ring<S, G, WM, WN, MB, NB>(acc, lds0, lds1, lds2, T, m0, n0);
+    else if constexpr (use_prefetch<S, G, WM, WN, MB, NB, MODE>())
         pair_mainloop_prefetch<S, G, WM, WN, MB, NB>(acc, lds0, lds1, T, m0, n0);
     else
         pair_mainloop_direct<S, G, WM, WN, MB, NB>(acc, lds0, lds1, T, m0, n0);
@@ -419,7 +564,7 @@ __device__ __forceinline__ void emax_block(const OutDesc &out, const long long (
 template <int S, int G, int WM, int WN, int MB, int NB, int MODE, bool EMAX = false, typename GetTerm>
 __device__ __forceinline__ void pair_tile(const PairArgs &a, GetTerm get_term, int tb, int te,
                                           const OutDesc &out, int m0, int n0, uint4 *lds0,
-                                          uint4 *lds1) {
+                                          uint4 *lds1, uint4 *lds2) {
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wm = wave / WN;
@@ -441,7 +586,7 @@ __device__ __forceinline__ void pair_tile(const PairArgs &a, GetTerm get_term, i
     for (int ti = tb; ti < tend; ++ti) {
         const TermDesc T = get_term(ti);
         v16i acc[G][MB][NB];
-        pair_mainloop<S, G, WM, WN, MB, NB, MODE>(acc, lds0, lds1, T, m0, n0);
+        pair_mainloop<S, G, WM, WN, MB, NB, MODE>(acc, lds0, lds1, lds2, T, m0, n0);
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
             const int j = n0 + (wn * NB + nb) * 32 + l32;
@@ -821,12 +966,13 @@ __global__ __launch_bounds__(64 * WM * WN) void k_pair_single(PairArgs a, int ti
     using C = Cfg<S, G, WM, WN, MB, NB>;
     __shared__ uint4 lds0[C::STAGE];
     __shared__ uint4 lds1[C::STAGE];
+    __shared__ uint4 lds2[use_ring<S, G, WM, WN, MB, NB, MODE>() ? C::STAGE : 1];
     int tm, tn;
     constexpr int group = C::BM >= 2 * C::BN ? 4 : 8;
     tile_coords(blockIdx.x, tiles_m, a.tiles_n, group, tm, tn);
     const TermDesc term = a.term;
     pair_tile<S, G, WM, WN, MB, NB, MODE>(a, [&](int) { return term; }, 0, 1, a.out, tm * C::BM,
-                                          tn * C::BN, lds0, lds1);
+                                          tn * C::BN, lds0, lds1, lds2);
 }
 
 // One block per listed tile (the list is in the XCD order the plan builds).
@@ -835,13 +981,14 @@ __global__ __launch_bounds__(64 * WM * WN) void k_pair_grouped(PairArgs a) {
     using C = Cfg<S, G, WM, WN, MB, NB>;
     __shared__ uint4 lds0[C::STAGE];
     __shared__ uint4 lds1[C::STAGE];
+    __shared__ uint4 lds2[use_ring<S, G, WM, WN, MB, NB, MODE>() ? C::STAGE : 1];
     const TileDesc td = a.tiles[blockIdx.x];
     if (td.out < 0) return;  // padding of the XCD order
     OutDesc od = a.outs[td.out];
     if (a.out_base) od.C = a.out_base + reinterpret_cast<intptr_t>(od.C);
     const TermDesc *terms = a.terms;
     pair_tile<S, G, WM, WN, MB, NB, MODE, MODE == kModeGemm>(a, [&](int i) { return terms[i]; }, td.term_begin,
-                                                            td.term_end, od, td.m0, td.n0, lds0, lds1);
+                                                            td.term_end, od, td.m0, td.n0, lds0, lds1, lds2);
 }
 
 // Per-(S, G) tile shape: as wide as the accumulators allow.
