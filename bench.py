@@ -380,13 +380,15 @@ def heff_section(args, ozaki, ctx, torch, name, layout, Lf, Rf, pf, triples, sli
              "rel_err_vs_dd_sampled": dd_err(sig),
              "cold_ms": (t + tplan) * 1e3, "phase_ms": phs,
              "tile_variants": list(plan.variants), "streamed_launches": list(plan.launches),
+             "chunks": plan.chunks, "plan_bytes": plan.bytes[0], "plan_T_bytes": plan.bytes[1],
              "int8_frac_pair_phases": (P * plan.flops / ((phs.get("heff_L", 0) + phs.get("heff_R", 0)) * 1e-3)
                                        / 1e12 / INT8_PEAK_TOPS) if phs else None}
         res.append(r)
         log("[bench] %s S=%d G=%d: %.3f ms/apply  %.2f TFLOP/s  err vs fp64 %s  vs dd %s  phases %s  "
-            "variants %s streamed %s"
+            "variants %s streamed %s  chunks %d  plan %.2f GiB (T %.2f GiB)"
             % (name, S, G, t * 1e3, r["tflops"], err, r["rel_err_vs_dd_sampled"],
-               {k: round(v, 3) for k, v in phs.items()}, plan.variants, plan.launches))
+               {k: round(v, 3) for k, v in phs.items()}, plan.variants, plan.launches, plan.chunks,
+               plan.bytes[0] / 2 ** 30, plan.bytes[1] / 2 ** 30))
         plan.close()
         del keep
     out["emulated"] = res

@@ -222,6 +222,14 @@ int ozaki_ctx_set_autotune(ozaki_ctx ctx, int enable);
  * most 16 K blocks (the streamed kernel saves a fixed cost per item), else 0.
  * Results are bit-identical in every mode.  OZ_ERR_ARG for mode < -1. */
 int ozaki_ctx_set_heff_launch(ozaki_ctx ctx, int mode);
+/* Device bytes that heff plans created afterwards may use for the
+ * intermediates T_u = L psi of the first products (FP64 values, and their
+ * slices and exponents when emulated); 0 (default) = 8 GiB.  A plan cuts its
+ * triple list into contiguous chunks whose distinct first products fit
+ * (always at least one triple per chunk) and runs them in order within each
+ * apply; sigma tiles continue across chunks from their stored values, so
+ * the result is bit-identical for every budget. */
+int ozaki_ctx_set_heff_budget(ozaki_ctx ctx, size_t bytes);
 /* Time every built variant of this GEMM (alpha = 1, beta = 0 into C, one
  * warm-up and three timed calls each) and fix the fastest for (slices,
  * ndiag) in the context.  ms_out (host, nullable, one slot per variant) gets
@@ -300,13 +308,15 @@ typedef struct {
  * int8 slices of every L and R block once (the operators are fixed during a
  * Davidson run); slices = 0 uses the native FP64 MFMA path.  triples is a
  * host array.  The plan owns every buffer it needs, so heff_apply never
- * allocates.  Synchronises `stream`. */
+ * allocates; the intermediates T take at most the context's heff budget
+ * (ozaki_ctx_set_heff_budget) plus one first product.  Synchronises
+ * `stream`. */
 int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *layout,
                      const double *L_data, const double *R_data, int32_t n_triples,
                      const heff_triple *triples, const double *diag, int slices, int ndiag,
                      void *stream);
 /* sigma = H_eff psi (sigma overwritten; psi and sigma must not overlap).
- * One grouped launch per phase; enqueue only.
+ * One grouped launch per phase and chunk of the triple list; enqueue only.
  * Replay: the first apply with a given (psi, sigma) pair captures the
  * plan's launch sequence into a HIP graph (on a private stream; this creates
  * the graph, which takes host and driver resources) and later applies with
@@ -331,6 +341,11 @@ int heff_plan_variants(heff_plan plan, int32_t *first, int32_t *second);
 int heff_plan_launches(heff_plan plan, int32_t *first, int32_t *second);
 /* Total elements of psi for the plan's layout. */
 int64_t heff_vector_length(heff_plan plan);
+/* Number of chunks the plan's triple list runs in (ozaki_ctx_set_heff_budget). */
+int heff_plan_chunks(heff_plan plan);
+/* Device bytes the plan holds (all its allocations); *T_bytes (nullable)
+ * gets the part that holds the intermediates T. */
+int64_t heff_plan_bytes(heff_plan plan, int64_t *T_bytes);
 /* FP64-equivalent flops of one heff_apply (2 m n k summed over all GEMMs). */
 double heff_flops(heff_plan plan);
 int heff_plan_destroy(heff_plan plan);

@@ -142,9 +142,11 @@ __device__ __forceinline__ void dgemm_tile(const Dgemm64Args &a, GetTerm get_ter
     // sigma = fma(alpha_t, c_t, sigma) after every term in list order (the
     // block owns its tile, each thread re-reads only what it wrote), so the
     // FP64 rounding is that of separately summed terms without keeping a
-    // second register tile.
+    // second register tile.  The sum starts from +0, or from the stored value
+    // when the output continues a term list split over launches (out.cont).
     const int tend = (MODE == kModeAccum) ? te : tb + 1;
     if (MODE == kModeAccum && tb == te) {
+        if (out.cont) return;  // nothing to add to the stored sum
 #pragma unroll
         for (int mb = 0; mb < NB; ++mb)
 #pragma unroll
@@ -223,7 +225,7 @@ __device__ __forceinline__ void dgemm_tile(const Dgemm64Args &a, GetTerm get_ter
                     if (MODE == kModeGemm)
                         *p = (a.beta == 0.0) ? T.alpha * c : fma(T.alpha, c, a.beta * *p);
                     else
-                        *p = fma(T.alpha, c, ti == tb ? 0.0 : *p);
+                        *p = fma(T.alpha, c, (ti == tb && !out.cont) ? 0.0 : *p);
                 }
     }
 }

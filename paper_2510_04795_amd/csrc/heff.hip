@@ -14,10 +14,15 @@
 //    view of T_u) in list order, sigma = fma(alpha, c, sigma) from +0, so the
 //    result does not depend on scheduling and needs no atomics;
 //  * emulated mode: the int8 slices of every L and R block are made once here;
-//    psi and T are sliced on every apply (psi by columns, T by rows).
-// Apply = 7 launches whatever the block count: exponents + slices of psi,
-// grouped first product, exponents + slices of T, grouped second product,
-// diagonal term.  Nothing is allocated or synchronised, so it can be captured.
+//    psi and T are sliced on every apply (psi by columns, T by rows);
+//  * the intermediates T_u live in a buffer of bounded size: the triple list
+//    is cut into contiguous chunks whose distinct first products fit it
+//    (ozaki_ctx_set_heff_budget), and the chunks run one after the other;
+//    a sigma tile that already summed triples in an earlier chunk continues
+//    from its stored value, so the sum is the same fma chain in list order.
+// Apply = psi's exponents and slices, then per chunk: grouped first product,
+// exponents + slices of its T, grouped second product; then the diagonal
+// term.  Nothing is allocated or synchronised, so it can be captured.
 #include <algorithm>
 #include <map>
 #include <tuple>
@@ -26,6 +31,20 @@
 #include "runtime.h"
 
 using namespace oz;
+
+// One chunk of the triple list: its first products write into the shared T
+// buffer, whose slices and exponents are shared too (chunks run in order).
+struct HeffChunk {
+    // emulated path
+    SliceBlock *T_blocks = nullptr;
+    SliceTask *T_etasks = nullptr, *T_stasks = nullptr;
+    int n_T_etasks = 0, n_T_stasks = 0;
+    bool fuse_T = false;      // T's exponents from the first phase's maxima
+    int64_t T_e_total = 0;
+    PairArgs argsL{}, argsR{};
+    // FP64 path
+    Dgemm64Args d64L{}, d64R{};
+};
 
 struct heff_plan_s {
     ozaki_ctx ctx = nullptr;
@@ -40,20 +59,16 @@ struct heff_plan_s {
     int n_psi_etasks = 0, n_psi_stasks = 0;
     int32_t *psi_e = nullptr;
     int8_t *psi_p = nullptr;
-    double *T = nullptr;
-    SliceBlock *T_blocks = nullptr;
-    SliceTask *T_etasks = nullptr, *T_stasks = nullptr;
-    int n_T_etasks = 0, n_T_stasks = 0;
+    double *T = nullptr;         // shared by the chunks
     int32_t *T_e = nullptr;
     int8_t *T_p = nullptr;
-    int32_t *T_emax = nullptr;  // exponent-code maxima left by the first phase (null: T read again)
-    int64_t T_e_total = 0;
+    int32_t *T_emax = nullptr;   // exponent-code maxima left by the first phase
     int32_t *psi_emax = nullptr;  // exponent-code maxima of psi's split column pass
     int64_t psi_e_total = 0;
-    PairArgs argsL{}, argsR{};
     int varL = -1, varR = -1;   // tile variants of the two grouped phases
-    // FP64 path
-    Dgemm64Args d64L{}, d64R{};
+    std::vector<HeffChunk> chunks;
+    size_t T_bytes = 0;         // T buffer, its slices and exponents
+    size_t bytes = 0;           // every device allocation of the plan
     // Replay: one instantiated graph of the apply sequence per (psi, sigma)
     // pair, captured on a private stream the first time the pair is seen.
     struct GraphSlot {
@@ -78,6 +93,7 @@ int upload(heff_plan p, const std::vector<T> &v, T **out) {
     hipError_t e = hipMalloc(&d, sizeof(T) * v.size());
     if (e != hipSuccess) return fail(OZ_ERR_NOMEM, "heff_plan_create: %zu bytes: %s", sizeof(T) * v.size(), hipGetErrorString(e));
     p->allocs.push_back(d);
+    p->bytes += sizeof(T) * v.size();
     if ((e = hipMemcpy(d, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(e, "heff_plan_create: upload");
     *out = static_cast<T *>(d);
@@ -90,6 +106,7 @@ int alloc(heff_plan p, size_t bytes, void **out) {
     hipError_t e = hipMalloc(out, bytes);
     if (e != hipSuccess) return fail(OZ_ERR_NOMEM, "heff_plan_create: %zu bytes: %s", bytes, hipGetErrorString(e));
     p->allocs.push_back(*out);
+    p->bytes += bytes;
     return OZ_OK;
 }
 
@@ -267,13 +284,11 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
     }
     if ((L->n_L_blocks > 0 && !L_data) || (L->n_R_blocks > 0 && !R_data)) return fail(OZ_ERR_ARG, "heff_plan_create: L_data / R_data NULL");
 
-    // distinct left products and the triples of every sigma block
+    // distinct left products and the triple list's sigma blocks
     std::map<std::tuple<int, int, int, int>, int> u_of;
-    struct U { int op, lo, li, ri, Lb, psib; int64_t t_off; };
+    struct U { int op, lo, li, ri, Lb, psib; };
     std::vector<U> us;
-    std::vector<std::vector<int>> by_sigma(L->n_psi_blocks);
-    std::vector<int> tri_u(n_triples), tri_R(n_triples);
-    int64_t t_total = 0;
+    std::vector<int> tri_u(n_triples), tri_R(n_triples), tri_sigma(n_triples);
     double flops = 0;
     for (int t = 0; t < n_triples; ++t) {
         const heff_triple &tr = triples[t];
@@ -286,15 +301,13 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
         auto uk = std::make_tuple(tr.op, tr.lo, tr.li, tr.ri);
         auto it = u_of.find(uk);
         if (it == u_of.end()) {
-            U u{tr.op, tr.lo, tr.li, tr.ri, L_of[lk], psi_of[{tr.li, tr.ri}], t_total};
-            t_total += ld[tr.lo] * p * rd[tr.ri];
+            us.push_back(U{tr.op, tr.lo, tr.li, tr.ri, L_of[lk], psi_of[{tr.li, tr.ri}]});
             flops += 2.0 * ld[tr.lo] * ld[tr.li] * (p * rd[tr.ri]);
-            it = u_of.emplace(uk, static_cast<int>(us.size())).first;
-            us.push_back(u);
+            it = u_of.emplace(uk, static_cast<int>(us.size()) - 1).first;
         }
         tri_u[t] = it->second;
         tri_R[t] = R_of[rk];
-        by_sigma[psi_of[{tr.lo, tr.ro}]].push_back(t);
+        tri_sigma[t] = psi_of[{tr.lo, tr.ro}];
         flops += 2.0 * (ld[tr.lo] * p) * rd[tr.ri] * rd[tr.ro];
         if (ld[tr.lo] * p > INT32_MAX / 2 || p * rd[tr.ri] > INT32_MAX / 2)
             return fail(OZ_ERR_ARG, "heff_plan_create: block too large");
@@ -302,29 +315,82 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
             return fail(OZ_ERR_UNSUPPORTED, "heff_plan_create: inner dimension above the exact int32 range");
     }
 
-    // Distinct first products ordered by their psi block, then L block: the
-    // per-XCD parts of the first phase's tile list then keep the products
-    // that read one psi block together (1-3 % less time in that phase on the
-    // block-sparse batch).  Results do not depend on this order.
+    // Chunks: contiguous ranges of the triple list whose distinct first
+    // products fit the T budget (FP64 values, and slices when emulated); a
+    // first product used in two chunks is computed in both.  Within a chunk
+    // the first products are ordered by psi block, then L block: the per-XCD
+    // parts of the first phase's tile list then keep the products that read
+    // one psi block together (1-3 % less time in that phase on the
+    // block-sparse batch).  Results depend on neither the chunks nor the order.
+    const size_t budget = ctx->heff_budget ? ctx->heff_budget : kHeffDefaultBudget;
+    auto u_elems = [&](int u) { return ld[us[u].lo] * p * rd[us[u].ri]; };
+    auto u_bytes = [&](int u) {
+        const int64_t rows = ld[us[u].lo] * p, cols = rd[us[u].ri];
+        return static_cast<size_t>(8 * rows * cols) +
+               (S ? static_cast<size_t>(S) * round_up(rows, kRowQ) * round_up(cols, kKB) + 8 * round_up(rows, kRowQ) : 0);
+    };
+    struct HostChunk {
+        int t0, t1;
+        std::vector<int> us;        // global first-product indices
+        std::vector<int64_t> t_off; // element offset of each in the shared T buffer
+        int64_t t_total = 0;
+    };
+    std::vector<HostChunk> hc;
     {
-        std::vector<int> perm(us.size());
-        for (size_t k = 0; k < perm.size(); ++k) perm[k] = static_cast<int>(k);
-        std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) {
-            return std::make_pair(us[a].psib, us[a].Lb) < std::make_pair(us[b].psib, us[b].Lb);
-        });
-        std::vector<int> inv(us.size());
-        std::vector<U> sorted;
-        int64_t off = 0;
-        for (size_t k = 0; k < perm.size(); ++k) {
-            U x = us[perm[k]];
-            x.t_off = off;
-            off += ld[x.lo] * p * rd[x.ri];
-            sorted.push_back(x);
-            inv[perm[k]] = static_cast<int>(k);
+        std::vector<char> in_chunk(us.size(), 0);
+        size_t bytes = 0;
+        HostChunk cur{0, 0, {}, {}, 0};
+        for (int t = 0; t < n_triples; ++t) {
+            const int u = tri_u[t];
+            if (!in_chunk[u] && !cur.us.empty() && bytes + u_bytes(u) > budget) {
+                cur.t1 = t;
+                for (int x : cur.us) in_chunk[x] = 0;
+                hc.push_back(cur);
+                cur = HostChunk{t, t, {}, {}, 0};
+                bytes = 0;
+            }
+            if (!in_chunk[u]) {
+                in_chunk[u] = 1;
+                cur.us.push_back(u);
+                bytes += u_bytes(u);
+            }
         }
-        for (auto &u : tri_u) u = inv[u];
-        us.swap(sorted);
+        cur.t1 = n_triples;
+        hc.push_back(cur);  // one chunk at least: it zeroes the sigma blocks no triple reaches
+        for (auto &c : hc) {
+            std::stable_sort(c.us.begin(), c.us.end(), [&](int a, int b) {
+                return std::make_pair(us[a].psib, us[a].Lb) < std::make_pair(us[b].psib, us[b].Lb);
+            });
+            for (int u : c.us) {
+                c.t_off.push_back(c.t_total);
+                c.t_total += u_elems(u);
+            }
+        }
     }
+    // sigma blocks per chunk: those with triples in it (continuing when an
+    // earlier chunk had triples for them), and in the first chunk also the
+    // blocks no triple reaches (zeroed)
+    std::vector<int> n_trip(L->n_psi_blocks, 0);
+    for (int t = 0; t < n_triples; ++t) ++n_trip[tri_sigma[t]];
+    struct SigmaPart { int b; bool cont; std::vector<int> trips; };
+    std::vector<std::vector<SigmaPart>> parts(hc.size());
+    {
+        std::vector<char> seen(L->n_psi_blocks, 0);
+        for (size_t c = 0; c < hc.size(); ++c) {
+            std::vector<std::vector<int>> by(L->n_psi_blocks);
+            for (int t = hc[c].t0; t < hc[c].t1; ++t) by[tri_sigma[t]].push_back(t);
+            for (int b = 0; b < L->n_psi_blocks; ++b) {
+                if (!by[b].empty()) {
+                    parts[c].push_back(SigmaPart{b, seen[b] != 0, by[b]});
+                    seen[b] = 1;
+                } else if (c == 0 && n_trip[b] == 0) {
+                    parts[c].push_back(SigmaPart{b, false, {}});
+                }
+            }
+        }
+    }
+    int64_t t_max = 1;
+    for (auto &c : hc) t_max = std::max(t_max, c.t_total);
 
     hipError_t e;
     if ((e = hipSetDevice(ctx->device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
@@ -336,87 +402,99 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
     P->n = n;
     P->flops = flops;
     P->diag = diag;
+    P->chunks.resize(hc.size());
     int rc = OZ_OK;
     void *mem = nullptr;
-    if ((rc = alloc(P, sizeof(double) * std::max<int64_t>(t_total, 1), &mem))) { free_plan(P); return rc; }
+    if ((rc = alloc(P, sizeof(double) * t_max, &mem))) { free_plan(P); return rc; }
     P->T = static_cast<double *>(mem);
+    P->T_bytes = sizeof(double) * t_max;
 
     if (S == 0) {
-        // tile edge per phase: 128, or 64 when the 128 tiles would not give
-        // every compute unit two workgroups
-        int64_t nL = 0, nR = 0;
-        for (size_t u = 0; u < us.size(); ++u)
-            nL += ceil_div(ld[us[u].lo], 128) * ceil_div(p * rd[us[u].ri], 128);
-        for (int b = 0; b < L->n_psi_blocks; ++b)
-            nR += ceil_div(ld[L->psi_lr[2 * b]] * p, 128) * ceil_div(rd[L->psi_lr[2 * b + 1]], 128);
-        const int bmL = dgemm_tile_for(nL, ctx->num_cu), bmR = dgemm_tile_for(nR, ctx->num_cu);
-        const PairShape sh{bmL, bmL}, shR{bmR, bmR};
-        // first product: T_u = L Psi  (op(B) = B, B offsets relative to psi)
-        std::vector<Term64> termsL;
-        std::vector<OutDesc> outsL;
-        std::vector<std::vector<TileWork>> wl(us.size());
-        for (size_t u = 0; u < us.size(); ++u) {
-            const U &x = us[u];
-            const int64_t M = ld[x.lo], N = p * rd[x.ri], K = ld[x.li];
-            Term64 tm{};
-            tm.A = L_data + L->L_offset[x.Lb];
-            tm.lda = K;
-            tm.B = reinterpret_cast<const double *>(static_cast<intptr_t>(L->psi_offset[x.psib]));
-            tm.ldb = N;
-            tm.K = static_cast<int32_t>(K);
-            tm.alpha = 1.0;
-            termsL.push_back(tm);
-            outsL.push_back(OutDesc{P->T + x.t_off, N, static_cast<int32_t>(M), static_cast<int32_t>(N)});
-            walk_output(M, N, sh, [&](int64_t m0, int64_t n0) {
-                return TileWork{TileDesc{static_cast<int32_t>(u), static_cast<int32_t>(u + 1), static_cast<int32_t>(m0),
-                                         static_cast<int32_t>(n0), static_cast<int32_t>(u), 0}, K};
-            }, &wl[u]);
-        }
-        // second product: sigma' = sum alpha T'_u R^T  (op(B) = R^T)
-        std::vector<Term64> termsR;
-        std::vector<OutDesc> outsR;
-        std::vector<std::vector<TileWork>> wr(L->n_psi_blocks);
-        for (int b = 0; b < L->n_psi_blocks; ++b) {
-            const int lo = L->psi_lr[2 * b], ro = L->psi_lr[2 * b + 1];
-            const int64_t M = ld[lo] * p, N = rd[ro];
-            const int tb = static_cast<int>(termsR.size());
-            int64_t cost = 0;
-            for (int t : by_sigma[b]) {
-                const U &x = us[tri_u[t]];
+        for (size_t c = 0; c < hc.size(); ++c) {
+            const HostChunk &h = hc[c];
+            // tile edge per phase: 128, or 64 when the 128 tiles would not
+            // give every compute unit two workgroups
+            int64_t nL = 0, nR = 0;
+            for (int u : h.us) nL += ceil_div(ld[us[u].lo], 128) * ceil_div(p * rd[us[u].ri], 128);
+            for (const SigmaPart &sp : parts[c])
+                nR += ceil_div(ld[L->psi_lr[2 * sp.b]] * p, 128) * ceil_div(rd[L->psi_lr[2 * sp.b + 1]], 128);
+            const int bmL = dgemm_tile_for(nL, ctx->num_cu), bmR = dgemm_tile_for(nR, ctx->num_cu);
+            const PairShape sh{bmL, bmL}, shR{bmR, bmR};
+            // first product: T_u = L Psi  (op(B) = B, B offsets relative to psi)
+            std::vector<Term64> termsL;
+            std::vector<OutDesc> outsL;
+            std::vector<std::vector<TileWork>> wl(h.us.size());
+            for (size_t k = 0; k < h.us.size(); ++k) {
+                const U &x = us[h.us[k]];
+                const int64_t M = ld[x.lo], N = p * rd[x.ri], K = ld[x.li];
                 Term64 tm{};
-                tm.A = P->T + x.t_off;
-                tm.lda = rd[x.ri];
-                tm.B = R_data + L->R_offset[tri_R[t]];
-                tm.ldb = rd[x.ri];
-                tm.K = static_cast<int32_t>(rd[x.ri]);
-                tm.alpha = triples[t].alpha;
-                termsR.push_back(tm);
-                cost += rd[x.ri];
+                tm.A = L_data + L->L_offset[x.Lb];
+                tm.lda = K;
+                tm.B = reinterpret_cast<const double *>(static_cast<intptr_t>(L->psi_offset[x.psib]));
+                tm.ldb = N;
+                tm.K = static_cast<int32_t>(K);
+                tm.alpha = 1.0;
+                termsL.push_back(tm);
+                outsL.push_back(OutDesc{P->T + h.t_off[k], N, static_cast<int32_t>(M), static_cast<int32_t>(N)});
+                walk_output(M, N, sh, [&](int64_t m0, int64_t n0) {
+                    return TileWork{TileDesc{static_cast<int32_t>(k), static_cast<int32_t>(k + 1), static_cast<int32_t>(m0),
+                                             static_cast<int32_t>(n0), static_cast<int32_t>(k), 0}, K};
+                }, &wl[k]);
             }
-            const int te = static_cast<int>(termsR.size());
-            outsR.push_back(OutDesc{reinterpret_cast<double *>(static_cast<intptr_t>(L->psi_offset[b])), N,
-                                    static_cast<int32_t>(M), static_cast<int32_t>(N)});
-            walk_output(M, N, shR, [&](int64_t m0, int64_t n0) {
-                return TileWork{TileDesc{tb, te, static_cast<int32_t>(m0), static_cast<int32_t>(n0), b, 0}, cost + 1};
-            }, &wr[b]);
+            // second product: sigma' (+)= sum alpha T'_u R^T  (op(B) = R^T)
+            std::vector<int> local(us.size(), -1);
+            for (size_t k = 0; k < h.us.size(); ++k) local[h.us[k]] = static_cast<int>(k);
+            std::vector<Term64> termsR;
+            std::vector<OutDesc> outsR;
+            std::vector<std::vector<TileWork>> wr(parts[c].size());
+            for (size_t q = 0; q < parts[c].size(); ++q) {
+                const SigmaPart &sp = parts[c][q];
+                const int lo = L->psi_lr[2 * sp.b], ro = L->psi_lr[2 * sp.b + 1];
+                const int64_t M = ld[lo] * p, N = rd[ro];
+                const int tb = static_cast<int>(termsR.size());
+                int64_t cost = 0;
+                for (int t : sp.trips) {
+                    const int k = local[tri_u[t]];
+                    const U &x = us[tri_u[t]];
+                    Term64 tm{};
+                    tm.A = P->T + h.t_off[k];
+                    tm.lda = rd[x.ri];
+                    tm.B = R_data + L->R_offset[tri_R[t]];
+                    tm.ldb = rd[x.ri];
+                    tm.K = static_cast<int32_t>(rd[x.ri]);
+                    tm.alpha = triples[t].alpha;
+                    termsR.push_back(tm);
+                    cost += rd[x.ri];
+                }
+                const int te = static_cast<int>(termsR.size());
+                OutDesc o{reinterpret_cast<double *>(static_cast<intptr_t>(L->psi_offset[sp.b])), N,
+                          static_cast<int32_t>(M), static_cast<int32_t>(N)};
+                o.cont = sp.cont ? 1 : 0;
+                outsR.push_back(o);
+                walk_output(M, N, shR, [&](int64_t m0, int64_t n0) {
+                    return TileWork{TileDesc{tb, te, static_cast<int32_t>(m0), static_cast<int32_t>(n0), static_cast<int32_t>(q), 0},
+                                    cost + 1};
+                }, &wr[q]);
+            }
+            std::vector<TileDesc> tl, tr;
+            std::vector<int64_t> cl, cr;
+            xcd_order(wl, &tl, &cl);
+            xcd_order(wr, &tr, &cr);
+            TileDesc *dt;
+            Term64 *dm;
+            OutDesc *dout;
+            HeffChunk &ch = P->chunks[c];
+            if ((rc = upload(P, tl, &dt)) || (rc = upload(P, termsL, &dm)) || (rc = upload(P, outsL, &dout))) { free_plan(P); return rc; }
+            ch.d64L.tiles = dt; ch.d64L.terms = dm; ch.d64L.outs = dout;
+            ch.d64L.ntiles = static_cast<int32_t>(tl.size());
+            ch.d64L.mode = kModeGemm;
+            ch.d64L.tile = bmL;
+            if ((rc = upload(P, tr, &dt)) || (rc = upload(P, termsR, &dm)) || (rc = upload(P, outsR, &dout))) { free_plan(P); return rc; }
+            ch.d64R.tiles = dt; ch.d64R.terms = dm; ch.d64R.outs = dout;
+            ch.d64R.ntiles = static_cast<int32_t>(tr.size());
+            ch.d64R.mode = kModeAccum;
+            ch.d64R.tile = bmR;
         }
-        std::vector<TileDesc> tl, tr;
-        std::vector<int64_t> cl, cr;
-        xcd_order(wl, &tl, &cl);
-        xcd_order(wr, &tr, &cr);
-        TileDesc *dt;
-        Term64 *dm;
-        OutDesc *dout;
-        if ((rc = upload(P, tl, &dt)) || (rc = upload(P, termsL, &dm)) || (rc = upload(P, outsL, &dout))) { free_plan(P); return rc; }
-        P->d64L.tiles = dt; P->d64L.terms = dm; P->d64L.outs = dout;
-        P->d64L.ntiles = static_cast<int32_t>(tl.size());
-        P->d64L.mode = kModeGemm;
-        P->d64L.tile = bmL;
-        if ((rc = upload(P, tr, &dt)) || (rc = upload(P, termsR, &dm)) || (rc = upload(P, outsR, &dout))) { free_plan(P); return rc; }
-        P->d64R.tiles = dt; P->d64R.terms = dm; P->d64R.outs = dout;
-        P->d64R.ntiles = static_cast<int32_t>(tr.size());
-        P->d64R.mode = kModeAccum;
-        P->d64R.tile = bmR;
         *out = P;
         return OZ_OK;
     }
@@ -444,116 +522,156 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
         const int l = L->psi_lr[2 * b], r = L->psi_lr[2 * b + 1];
         Ps.add(L->psi_offset[b], p * rd[r], p * rd[r], ld[l], true, S, &P_eoff[b], &P_poff[b]);
     }
-    // T_u sliced by rows of the (left * phys) x right view
-    SliceSet Ts;
-    std::vector<int64_t> T_eoff(us.size()), T_poff(us.size());
-    for (size_t u = 0; u < us.size(); ++u) {
-        const U &x = us[u];
-        Ts.add(x.t_off, rd[x.ri], ld[x.lo] * p, rd[x.ri], false, S, &T_eoff[u], &T_poff[u]);
-    }
-    void *pe, *pp, *te_, *tp;
     if ((rc = upload(P, Ps.blocks, &P->psi_blocks)) || (rc = upload(P, Ps.etasks, &P->psi_etasks)) ||
-        (rc = upload(P, Ps.stasks, &P->psi_stasks)) || (rc = upload(P, Ts.blocks, &P->T_blocks)) ||
-        (rc = upload(P, Ts.etasks, &P->T_etasks)) || (rc = upload(P, Ts.stasks, &P->T_stasks)) ||
-        (rc = alloc(P, sizeof(int32_t) * std::max<int64_t>(Ps.e_total, 1), &pe)) ||
-        (rc = alloc(P, std::max<int64_t>(Ps.p_total, 256), &pp)) ||
-        (rc = alloc(P, sizeof(int32_t) * std::max<int64_t>(Ts.e_total, 1), &te_)) ||
-        (rc = alloc(P, std::max<int64_t>(Ts.p_total, 256), &tp))) { free_plan(P); return rc; }
+        (rc = upload(P, Ps.stasks, &P->psi_stasks))) { free_plan(P); return rc; }
+    void *pe, *pp;
+    if ((rc = alloc(P, sizeof(int32_t) * std::max<int64_t>(Ps.e_total, 1), &pe)) ||
+        (rc = alloc(P, std::max<int64_t>(Ps.p_total, 256), &pp))) { free_plan(P); return rc; }
     P->n_psi_etasks = static_cast<int>(Ps.etasks.size());
     P->n_psi_stasks = static_cast<int>(Ps.stasks.size());
-    P->n_T_etasks = static_cast<int>(Ts.etasks.size());
-    P->n_T_stasks = static_cast<int>(Ts.stasks.size());
     P->psi_e = static_cast<int32_t *>(pe);
     P->psi_p = static_cast<int8_t *>(pp);
-    P->T_e = static_cast<int32_t *>(te_);
-    P->T_p = static_cast<int8_t *>(tp);
-    // T's row exponents from its producer: every row of the (left * phys) x
-    // right view must take whole 32-column groups of the first product
-    // (phys = 1, or right dimensions that are multiples of 32).  Then the
-    // first phase's epilogue leaves exponent-code maxima in T_emax and a
-    // small kernel turns them into T_e, instead of a pass that reads T.
     if (Ps.e_total > 0) {
         const std::vector<int32_t> init(static_cast<size_t>(Ps.e_total), kEmaxZero);
         if ((rc = upload(P, init, &P->psi_emax))) { free_plan(P); return rc; }
         P->psi_e_total = Ps.e_total;
     }
-    bool fuse_T = Ts.e_total > 0;
-    for (const U &x : us) fuse_T = fuse_T && (p == 1 || rd[x.ri] % 32 == 0);
-    std::vector<int32_t> emax_init;
-    if (fuse_T) {
-        emax_init.assign(static_cast<size_t>(Ts.e_total), kEmaxZero);
-        if ((rc = upload(P, emax_init, &P->T_emax))) { free_plan(P); return rc; }
-        P->T_e_total = Ts.e_total;
+
+    // per chunk: T_u sliced by rows of the (left * phys) x right view into the
+    // shared slice buffer; the terms and outputs of both phases
+    struct HostLists {
+        SliceSet Ts;
+        std::vector<int64_t> T_eoff, T_poff;
+        std::vector<TermDesc> termsL, termsR;
+        std::vector<OutDesc> outsL, outsR;
+        std::vector<int> sigma_tb, sigma_te;
+        std::vector<int64_t> sigma_cost;
+    };
+    std::vector<HostLists> hl(hc.size());
+    int64_t Te_max = 1, Tp_max = 256;
+    for (size_t c = 0; c < hc.size(); ++c) {
+        const HostChunk &h = hc[c];
+        HostLists &x = hl[c];
+        x.T_eoff.resize(h.us.size());
+        x.T_poff.resize(h.us.size());
+        for (size_t k = 0; k < h.us.size(); ++k) {
+            const U &u = us[h.us[k]];
+            x.Ts.add(h.t_off[k], rd[u.ri], ld[u.lo] * p, rd[u.ri], false, S, &x.T_eoff[k], &x.T_poff[k]);
+        }
+        Te_max = std::max(Te_max, x.Ts.e_total);
+        Tp_max = std::max(Tp_max, x.Ts.p_total);
+    }
+    void *te_, *tp;
+    if ((rc = alloc(P, sizeof(int32_t) * Te_max, &te_)) || (rc = alloc(P, Tp_max, &tp))) { free_plan(P); return rc; }
+    P->T_e = static_cast<int32_t *>(te_);
+    P->T_p = static_cast<int8_t *>(tp);
+    P->T_bytes += sizeof(int32_t) * Te_max + Tp_max;
+    // T's row exponents from its producer when every row of the (left * phys)
+    // x right view takes whole 32-column groups of the first product (phys =
+    // 1, or right dimensions that are multiples of 32): the first phase's
+    // epilogue leaves exponent-code maxima in T_emax and a small kernel turns
+    // them into T_e, instead of a pass that reads T.
+    bool any_fuse = false;
+    for (size_t c = 0; c < hc.size(); ++c) {
+        bool f = hl[c].Ts.e_total > 0;
+        for (int u : hc[c].us) f = f && (p == 1 || rd[us[u].ri] % 32 == 0);
+        P->chunks[c].fuse_T = f;
+        any_fuse = any_fuse || f;
+    }
+    const std::vector<int32_t> emax_init(static_cast<size_t>(Te_max), kEmaxZero);
+    if (any_fuse && (rc = upload(P, emax_init, &P->T_emax))) { free_plan(P); return rc; }
+
+    for (size_t c = 0; c < hc.size(); ++c) {
+        const HostChunk &h = hc[c];
+        HostLists &x = hl[c];
+        HeffChunk &ch = P->chunks[c];
+        ch.T_e_total = x.Ts.e_total;
+        ch.n_T_etasks = static_cast<int>(x.Ts.etasks.size());
+        ch.n_T_stasks = static_cast<int>(x.Ts.stasks.size());
+        if ((rc = upload(P, x.Ts.blocks, &ch.T_blocks)) || (rc = upload(P, x.Ts.etasks, &ch.T_etasks)) ||
+            (rc = upload(P, x.Ts.stasks, &ch.T_stasks))) { free_plan(P); return rc; }
+        std::vector<int> local(us.size(), -1);
+        for (size_t k = 0; k < h.us.size(); ++k) {
+            local[h.us[k]] = static_cast<int>(k);
+            const U &u = us[h.us[k]];
+            const int64_t M = ld[u.lo], N = p * rd[u.ri], K = ld[u.li];
+            TermDesc tm{};
+            tm.A = Lp + L_poff[u.Lb];
+            tm.e = Le + L_eoff[u.Lb];
+            tm.a_rows_p = round_up(M, kRowQ);
+            tm.B = P->psi_p + P_poff[u.psib];
+            tm.f = P->psi_e + P_eoff[u.psib];
+            tm.b_rows_p = round_up(N, kRowQ);
+            tm.kblocks = static_cast<int32_t>(ceil_div(K, kKB));
+            tm.alpha = 1.0;
+            x.termsL.push_back(tm);
+            OutDesc o{P->T + h.t_off[k], N, static_cast<int32_t>(M), static_cast<int32_t>(N)};
+            if (ch.fuse_T) {
+                o.emax = P->T_emax + x.T_eoff[k];
+                o.ep = static_cast<int32_t>(p);
+                o.en = static_cast<int32_t>(rd[u.ri]);
+            }
+            x.outsL.push_back(o);
+        }
+        for (const SigmaPart &sp : parts[c]) {
+            const int lo = L->psi_lr[2 * sp.b], ro = L->psi_lr[2 * sp.b + 1];
+            const int64_t M = ld[lo] * p, N = rd[ro];
+            x.sigma_tb.push_back(static_cast<int>(x.termsR.size()));
+            int64_t cost = 0;
+            for (int t : sp.trips) {
+                const int k = local[tri_u[t]];
+                const U &u = us[tri_u[t]];
+                TermDesc tm{};
+                tm.A = P->T_p + x.T_poff[k];
+                tm.e = P->T_e + x.T_eoff[k];
+                tm.a_rows_p = round_up(M, kRowQ);
+                tm.B = Rp + R_poff[tri_R[t]];
+                tm.f = Re + R_eoff[tri_R[t]];
+                tm.b_rows_p = round_up(N, kRowQ);
+                tm.kblocks = static_cast<int32_t>(ceil_div(rd[u.ri], kKB));
+                tm.alpha = triples[t].alpha;
+                x.termsR.push_back(tm);
+                cost += tm.kblocks;
+            }
+            x.sigma_te.push_back(static_cast<int>(x.termsR.size()));
+            x.sigma_cost.push_back(cost);
+            OutDesc o{reinterpret_cast<double *>(static_cast<intptr_t>(L->psi_offset[sp.b])), N,
+                      static_cast<int32_t>(M), static_cast<int32_t>(N)};
+            o.cont = sp.cont ? 1 : 0;
+            x.outsR.push_back(o);
+        }
+        TermDesc *dmL, *dmR;
+        OutDesc *doL, *doR;
+        if ((rc = upload(P, x.termsL, &dmL)) || (rc = upload(P, x.outsL, &doL)) || (rc = upload(P, x.termsR, &dmR)) ||
+            (rc = upload(P, x.outsR, &doR))) { free_plan(P); return rc; }
+        ch.argsL.terms = dmL; ch.argsL.outs = doL; ch.argsL.mode = kModeGemm;
+        ch.argsR.terms = dmR; ch.argsR.outs = doR; ch.argsR.mode = kModeAccum;
+        // tile counters of the streamed launches (zero; every launch leaves them zero)
+        const std::vector<int32_t> zq(kStreamQueueInts, 0);
+        if ((rc = upload(P, zq, &ch.argsL.queue)) || (rc = upload(P, zq, &ch.argsR.queue))) { free_plan(P); return rc; }
     }
 
-    // terms and outputs (shared by every tile variant)
-    std::vector<TermDesc> termsL, termsR;
-    std::vector<OutDesc> outsL, outsR;
-    std::vector<int> sigma_tb(L->n_psi_blocks), sigma_te(L->n_psi_blocks);
-    std::vector<int64_t> sigma_cost(L->n_psi_blocks, 0);
-    for (size_t u = 0; u < us.size(); ++u) {
-        const U &x = us[u];
-        const int64_t M = ld[x.lo], N = p * rd[x.ri], K = ld[x.li];
-        TermDesc tm{};
-        tm.A = Lp + L_poff[x.Lb];
-        tm.e = Le + L_eoff[x.Lb];
-        tm.a_rows_p = round_up(M, kRowQ);
-        tm.B = P->psi_p + P_poff[x.psib];
-        tm.f = P->psi_e + P_eoff[x.psib];
-        tm.b_rows_p = round_up(N, kRowQ);
-        tm.kblocks = static_cast<int32_t>(ceil_div(K, kKB));
-        tm.alpha = 1.0;
-        termsL.push_back(tm);
-        OutDesc o{P->T + x.t_off, N, static_cast<int32_t>(M), static_cast<int32_t>(N)};
-        if (P->T_emax) {
-            o.emax = P->T_emax + T_eoff[u];
-            o.ep = static_cast<int32_t>(p);
-            o.en = static_cast<int32_t>(rd[x.ri]);
-        }
-        outsL.push_back(o);
-    }
-    for (int b = 0; b < L->n_psi_blocks; ++b) {
-        const int lo = L->psi_lr[2 * b], ro = L->psi_lr[2 * b + 1];
-        const int64_t M = ld[lo] * p, N = rd[ro];
-        sigma_tb[b] = static_cast<int>(termsR.size());
-        for (int t : by_sigma[b]) {
-            const int u = tri_u[t];
-            const U &x = us[u];
-            TermDesc tm{};
-            tm.A = P->T_p + T_poff[u];
-            tm.e = P->T_e + T_eoff[u];
-            tm.a_rows_p = round_up(M, kRowQ);
-            tm.B = Rp + R_poff[tri_R[t]];
-            tm.f = Re + R_eoff[tri_R[t]];
-            tm.b_rows_p = round_up(N, kRowQ);
-            tm.kblocks = static_cast<int32_t>(ceil_div(rd[x.ri], kKB));
-            tm.alpha = triples[t].alpha;
-            termsR.push_back(tm);
-            sigma_cost[b] += tm.kblocks;
-        }
-        sigma_te[b] = static_cast<int>(termsR.size());
-        outsR.push_back(OutDesc{reinterpret_cast<double *>(static_cast<intptr_t>(L->psi_offset[b])), N,
-                                static_cast<int32_t>(M), static_cast<int32_t>(N)});
-    }
-    // tile lists per variant, in XCD order (xcd) or longest tile first
-    auto tiles_for = [&](int v, bool xcd, std::vector<TileDesc> *tl, std::vector<TileDesc> *tr,
+    // tile lists of chunk c per variant, in XCD order (xcd) or longest tile first
+    auto tiles_for = [&](size_t c, int v, bool xcd, std::vector<TileDesc> *tl, std::vector<TileDesc> *tr,
                          std::vector<int64_t> *cl, std::vector<int64_t> *cr) {
+        const HostLists &x = hl[c];
         const PairShape sh = pair_shape(S, G, v);
-        std::vector<std::vector<TileWork>> wl(us.size()), wr(L->n_psi_blocks);
-        for (size_t u = 0; u < us.size(); ++u) {
-            const OutDesc &o = outsL[u];
-            const int64_t c = static_cast<int64_t>(termsL[u].kblocks) * sh.bm * sh.bn;
+        std::vector<std::vector<TileWork>> wl(x.outsL.size()), wr(x.outsR.size());
+        for (size_t u = 0; u < x.outsL.size(); ++u) {
+            const OutDesc &o = x.outsL[u];
+            const int64_t cst = static_cast<int64_t>(x.termsL[u].kblocks) * sh.bm * sh.bn;
             walk_output(o.M, o.N, sh, [&](int64_t m0, int64_t n0) {
                 return TileWork{TileDesc{static_cast<int32_t>(u), static_cast<int32_t>(u + 1), static_cast<int32_t>(m0),
-                                         static_cast<int32_t>(n0), static_cast<int32_t>(u), 0}, c};
+                                         static_cast<int32_t>(n0), static_cast<int32_t>(u), 0}, cst};
             }, &wl[u]);
         }
-        for (int b = 0; b < L->n_psi_blocks; ++b) {
-            const OutDesc &o = outsR[b];
-            const int64_t c = (sigma_cost[b] + 1) * sh.bm * sh.bn;
+        for (size_t q = 0; q < x.outsR.size(); ++q) {
+            const OutDesc &o = x.outsR[q];
+            const int64_t cst = (x.sigma_cost[q] + 1) * sh.bm * sh.bn;
             walk_output(o.M, o.N, sh, [&](int64_t m0, int64_t n0) {
-                return TileWork{TileDesc{sigma_tb[b], sigma_te[b], static_cast<int32_t>(m0), static_cast<int32_t>(n0), b, 0}, c};
-            }, &wr[b]);
+                return TileWork{TileDesc{x.sigma_tb[q], x.sigma_te[q], static_cast<int32_t>(m0), static_cast<int32_t>(n0),
+                                         static_cast<int32_t>(q), 0}, cst};
+            }, &wr[q]);
         }
         if (xcd) {
             xcd_order(wl, tl, cl);
@@ -563,27 +681,18 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
             longest_first(wr, tr, cr);
         }
     };
-    TermDesc *dmL, *dmR;
-    OutDesc *doL, *doR;
-    if ((rc = upload(P, termsL, &dmL)) || (rc = upload(P, outsL, &doL)) || (rc = upload(P, termsR, &dmR)) ||
-        (rc = upload(P, outsR, &doR))) { free_plan(P); return rc; }
-    P->argsL.terms = dmL; P->argsL.outs = doL; P->argsL.mode = kModeGemm;
-    P->argsR.terms = dmR; P->argsR.outs = doR; P->argsR.mode = kModeAccum;
-    {
-        // tile counters of the streamed launches (zero; every launch leaves them zero)
-        const std::vector<int32_t> zq(kStreamQueueInts, 0);
-        if ((rc = upload(P, zq, &P->argsL.queue)) || (rc = upload(P, zq, &P->argsR.queue))) { free_plan(P); return rc; }
-    }
 
     const int fixed = ctx->variant[S][G];
     std::vector<int> cands;
     for (int v = 0; v < pair_num_variants(); ++v)
         if (pair_variant_ok(G, v) && (fixed < 0 ? (ctx->autotune || v == pair_default_variant(G)) : v == fixed))
             cands.push_back(v);
-    // Autotuning: time each candidate (tile variant, tile order, launch) on
-    // its whole tile list or an even sample of it, scaled by the sample's
-    // share of the total cost; inputs are zeroed scratch (the timing does
-    // not depend on the values).
+    // Autotuning on the first chunk: time each candidate (tile variant, tile
+    // order, launch) on its whole tile list or an even sample of it, scaled
+    // by the sample's share of the total cost; inputs are zeroed scratch (the
+    // timing does not depend on the values).  Every chunk then uses the
+    // choice per phase.
+    HeffChunk &c0 = P->chunks[0];
     double bestL = -1, bestR = -1;
     void *tmp_sigma = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -592,8 +701,8 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
         if ((e = hipMalloc(&tmp_sigma, sizeof(double) * std::max<int64_t>(n, 1))) != hipSuccess) { free_plan(P); return hip_fail(e, "heff_plan_create: tuning buffer"); }
         hipMemsetAsync(P->psi_p, 0, std::max<int64_t>(Ps.p_total, 256), s);
         hipMemsetAsync(P->psi_e, 0, sizeof(int32_t) * std::max<int64_t>(Ps.e_total, 1), s);
-        hipMemsetAsync(P->T_p, 0, std::max<int64_t>(Ts.p_total, 256), s);
-        hipMemsetAsync(P->T_e, 0, sizeof(int32_t) * std::max<int64_t>(Ts.e_total, 1), s);
+        hipMemsetAsync(P->T_p, 0, Tp_max, s);
+        hipMemsetAsync(P->T_e, 0, sizeof(int32_t) * Te_max, s);
         hipEventCreate(&ev0);
         hipEventCreate(&ev1);
     }
@@ -612,6 +721,7 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
             if (!xcd && !tuning) break;
             for (bool st : launches) runs.push_back({v, xcd, st});
         }
+    Run chosenL = runs.front(), chosenR = runs.front();
     int32_t last_key = -1;  // tile lists are built once per (variant, order) and shared by both launches
     TileDesc *dtl = nullptr, *dtr = nullptr;
     std::vector<int64_t> cl, cr;
@@ -631,14 +741,16 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
         free_plan(P);
         return hip_fail(e, "heff_plan_create: tuning buffer");
     }
-    for (auto [v, xcd, st] : runs) {
+    for (auto run : runs) {
+        const int v = run.v;
+        const bool xcd = run.xcd, st = run.stream;
         const int32_t key = v * 2 + (xcd ? 1 : 0);
         if (key != last_key) {
             tl.clear();
             tr.clear();
             cl.clear();
             cr.clear();
-            tiles_for(v, xcd, &tl, &tr, &cl, &cr);
+            tiles_for(0, v, xcd, &tl, &tr, &cl, &cr);
             if ((rc = upload(P, tl, &dtl)) || (rc = upload(P, tr, &dtr))) { if (tmp_sigma) hipFree(tmp_sigma); if (tmp_tiles) hipFree(tmp_tiles); free_plan(P); return rc; }
             ntl = static_cast<int32_t>(tl.size());
             ntr = static_cast<int32_t>(tr.size());
@@ -646,16 +758,17 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
         }
         const int32_t scus = !st ? 0 : ctx->heff_launch > 0 ? std::min(ctx->heff_launch, ctx->num_cu) : ctx->num_cu;
         if (!tuning) {
-            P->argsL.tiles = dtl; P->argsL.ntiles = ntl; P->varL = v; P->argsL.stream_cus = scus;
-            P->argsR.tiles = dtr; P->argsR.ntiles = ntr; P->varR = v; P->argsR.stream_cus = scus;
+            c0.argsL.tiles = dtl; c0.argsL.ntiles = ntl; P->varL = v; c0.argsL.stream_cus = scus;
+            c0.argsR.tiles = dtr; c0.argsR.ntiles = ntr; P->varR = v; c0.argsR.stream_cus = scus;
+            chosenL = chosenR = run;
             break;
         }
         for (int ph = 0; ph < 2; ++ph) {
             const std::vector<int64_t> &cost = ph == 0 ? cl : cr;
             int64_t total = 0, items = 0;
-            for (auto c : cost) {
-                total += c;
-                items += c > 0;
+            for (auto cc : cost) {
+                total += cc;
+                items += cc > 0;
             }
             if (st && ctx->heff_launch < 0) {
                 // Timed choice: the streamed kernel saves a fixed cost per
@@ -668,7 +781,7 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
                 if (ph == 1 || mean_kb > kStreamMaxMeanBlocks) continue;
             }
             const std::vector<TileDesc> &list = ph == 0 ? tl : tr;
-            PairArgs a = ph == 0 ? P->argsL : P->argsR;
+            PairArgs a = ph == 0 ? c0.argsL : c0.argsR;
             const PairShape shp = pair_shape(S, G, v);
             const double blocks_per_tile = items ? static_cast<double>(total) / items / (shp.bm * shp.bn) : 1.0;
             const size_t n_sample = std::min(cap, std::max(floor_tiles, static_cast<size_t>(16.0 * cap / std::max(blocks_per_tile, 1.0))));
@@ -714,8 +827,8 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
             double &best = ph == 0 ? bestL : bestR;
             if (best < 0 || est < best) {
                 best = est;
-                if (ph == 0) { P->argsL.tiles = dtl; P->argsL.ntiles = ntl; P->varL = v; P->argsL.stream_cus = scus; }
-                else { P->argsR.tiles = dtr; P->argsR.ntiles = ntr; P->varR = v; P->argsR.stream_cus = scus; }
+                if (ph == 0) { c0.argsL.tiles = dtl; c0.argsL.ntiles = ntl; P->varL = v; c0.argsL.stream_cus = scus; chosenL = run; }
+                else { c0.argsR.tiles = dtr; c0.argsR.ntiles = ntr; P->varR = v; c0.argsR.stream_cus = scus; chosenR = run; }
             }
         }
     }
@@ -729,6 +842,18 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
         if (P->T_emax && (e = hipMemcpy(P->T_emax, emax_init.data(), sizeof(int32_t) * emax_init.size(),
                                         hipMemcpyHostToDevice)) != hipSuccess) { free_plan(P); return hip_fail(e, "heff_plan_create: reset"); }
     }
+    // the other chunks take the first chunk's choice per phase
+    for (size_t c = 1; c < hc.size(); ++c) {
+        HeffChunk &ch = P->chunks[c];
+        std::vector<TileDesc> l1, r1, l2, r2;
+        std::vector<int64_t> cl1, cr1, cl2, cr2;
+        tiles_for(c, chosenL.v, chosenL.xcd, &l1, &r1, &cl1, &cr1);
+        tiles_for(c, chosenR.v, chosenR.xcd, &l2, &r2, &cl2, &cr2);
+        TileDesc *d1, *d2;
+        if ((rc = upload(P, l1, &d1)) || (rc = upload(P, r2, &d2))) { free_plan(P); return rc; }
+        ch.argsL.tiles = d1; ch.argsL.ntiles = static_cast<int32_t>(l1.size()); ch.argsL.stream_cus = c0.argsL.stream_cus;
+        ch.argsR.tiles = d2; ch.argsR.ntiles = static_cast<int32_t>(r2.size()); ch.argsR.stream_cus = c0.argsR.stream_cus;
+    }
     if ((e = hipStreamSynchronize(s)) != hipSuccess) { free_plan(P); return hip_fail(e, "heff_plan_create: sync"); }
     *out = P;
     return OZ_OK;
@@ -741,17 +866,19 @@ int enqueue_apply(heff_plan P, const double *psi, double *sigma, hipStream_t s) 
     ozaki_ctx ctx = P->ctx;
     hipError_t e;
     if (P->S == 0) {
-        hipEvent_t t0 = mark(ctx, s);
-        Dgemm64Args a = P->d64L;
-        a.b_base = psi;
-        if ((e = launch_dgemm_grouped(false, a, s)) != hipSuccess) return hip_fail(e, "heff_apply: first product");
-        hipEvent_t t1 = mark(ctx, s);
-        phase(ctx, OZ_PHASE_HEFF_L, t0, t1);
-        Dgemm64Args b = P->d64R;
-        b.out_base = sigma;
-        if ((e = launch_dgemm_grouped(true, b, s)) != hipSuccess) return hip_fail(e, "heff_apply: second product");
-        hipEvent_t t2 = mark(ctx, s);
-        phase(ctx, OZ_PHASE_HEFF_R, t1, t2);
+        for (const HeffChunk &ch : P->chunks) {
+            hipEvent_t t0 = mark(ctx, s);
+            Dgemm64Args a = ch.d64L;
+            a.b_base = psi;
+            if ((e = launch_dgemm_grouped(false, a, s)) != hipSuccess) return hip_fail(e, "heff_apply: first product");
+            hipEvent_t t1 = mark(ctx, s);
+            phase(ctx, OZ_PHASE_HEFF_L, t0, t1);
+            Dgemm64Args b = ch.d64R;
+            b.out_base = sigma;
+            if ((e = launch_dgemm_grouped(true, b, s)) != hipSuccess) return hip_fail(e, "heff_apply: second product");
+            hipEvent_t t2 = mark(ctx, s);
+            phase(ctx, OZ_PHASE_HEFF_R, t1, t2);
+        }
     } else {
         hipEvent_t t0 = mark(ctx, s);
         if ((e = launch_exponents_grouped(P->psi_blocks, P->psi_etasks, P->n_psi_etasks, psi, P->psi_e, ctx->d_flags, s, P->psi_emax)) != hipSuccess ||
@@ -760,20 +887,23 @@ int enqueue_apply(heff_plan P, const double *psi, double *sigma, hipStream_t s) 
             return hip_fail(e, "heff_apply: slicing psi");
         hipEvent_t t1 = mark(ctx, s);
         phase(ctx, OZ_PHASE_HEFF_AUX, t0, t1);
-        if ((e = launch_pair_grouped(P->S, P->G, P->varL, P->argsL, s)) != hipSuccess) return hip_fail(e, "heff_apply: first product");
-        hipEvent_t t2 = mark(ctx, s);
-        phase(ctx, OZ_PHASE_HEFF_L, t1, t2);
-        if ((e = P->T_emax ? launch_emax_finish(P->T_emax, P->T_e, P->T_e_total, ctx->d_flags, s)
-                           : launch_exponents_grouped(P->T_blocks, P->T_etasks, P->n_T_etasks, P->T, P->T_e, ctx->d_flags, s)) != hipSuccess ||
-            (e = launch_slice_grouped(P->S, P->T_blocks, P->T_stasks, P->n_T_stasks, P->T, P->T_e, P->T_p, s)) != hipSuccess)
-            return hip_fail(e, "heff_apply: slicing T");
-        hipEvent_t t3 = mark(ctx, s);
-        phase(ctx, OZ_PHASE_HEFF_AUX, t2, t3);
-        PairArgs b = P->argsR;
-        b.out_base = sigma;
-        if ((e = launch_pair_grouped(P->S, P->G, P->varR, b, s)) != hipSuccess) return hip_fail(e, "heff_apply: second product");
-        hipEvent_t t4 = mark(ctx, s);
-        phase(ctx, OZ_PHASE_HEFF_R, t3, t4);
+        for (const HeffChunk &ch : P->chunks) {
+            hipEvent_t c0 = mark(ctx, s);
+            if ((e = launch_pair_grouped(P->S, P->G, P->varL, ch.argsL, s)) != hipSuccess) return hip_fail(e, "heff_apply: first product");
+            hipEvent_t c1 = mark(ctx, s);
+            phase(ctx, OZ_PHASE_HEFF_L, c0, c1);
+            if ((e = ch.fuse_T ? launch_emax_finish(P->T_emax, P->T_e, ch.T_e_total, ctx->d_flags, s)
+                               : launch_exponents_grouped(ch.T_blocks, ch.T_etasks, ch.n_T_etasks, P->T, P->T_e, ctx->d_flags, s)) != hipSuccess ||
+                (e = launch_slice_grouped(P->S, ch.T_blocks, ch.T_stasks, ch.n_T_stasks, P->T, P->T_e, P->T_p, s)) != hipSuccess)
+                return hip_fail(e, "heff_apply: slicing T");
+            hipEvent_t c2 = mark(ctx, s);
+            phase(ctx, OZ_PHASE_HEFF_AUX, c1, c2);
+            PairArgs b = ch.argsR;
+            b.out_base = sigma;
+            if ((e = launch_pair_grouped(P->S, P->G, P->varR, b, s)) != hipSuccess) return hip_fail(e, "heff_apply: second product");
+            hipEvent_t c3 = mark(ctx, s);
+            phase(ctx, OZ_PHASE_HEFF_R, c2, c3);
+        }
     }
     if (P->diag) {
         if ((e = launch_diag_axpy(P->diag, psi, sigma, P->n, s)) != hipSuccess) return hip_fail(e, "heff_apply: diagonal");
@@ -868,9 +998,20 @@ int heff_plan_variants(heff_plan P, int32_t *first, int32_t *second) {
 
 int heff_plan_launches(heff_plan P, int32_t *first, int32_t *second) {
     if (!P) return fail(OZ_ERR_ARG, "heff_plan_launches: plan is NULL");
-    if (first) *first = P->S ? (P->argsL.stream_cus > 0 ? 1 : 0) : -1;
-    if (second) *second = P->S ? (P->argsR.stream_cus > 0 ? 1 : 0) : -1;
+    if (first) *first = P->S ? (P->chunks[0].argsL.stream_cus > 0 ? 1 : 0) : -1;
+    if (second) *second = P->S ? (P->chunks[0].argsR.stream_cus > 0 ? 1 : 0) : -1;
     return OZ_OK;
+}
+
+int heff_plan_chunks(heff_plan P) {
+    if (!P) return fail(OZ_ERR_ARG, "heff_plan_chunks: plan is NULL");
+    return static_cast<int>(P->chunks.size());
+}
+
+int64_t heff_plan_bytes(heff_plan P, int64_t *T_bytes) {
+    if (!P) return fail(OZ_ERR_ARG, "heff_plan_bytes: plan is NULL");
+    if (T_bytes) *T_bytes = static_cast<int64_t>(P->T_bytes);
+    return static_cast<int64_t>(P->bytes);
 }
 
 double heff_flops(heff_plan P) { return P ? P->flops : 0.0; }

@@ -80,6 +80,11 @@ struct OutDesc {
     // en >= N), combined with atomic max
     int32_t *emax;
     int32_t ep, en;
+    // accumulating mode: 1 = the running sum starts from the stored C (a term
+    // list split over launches continues where the previous launch stopped),
+    // 0 = it starts from +0
+    int32_t cont;
+    int32_t pad_;
 };
 
 enum PairMode : int32_t {

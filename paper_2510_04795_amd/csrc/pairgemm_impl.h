@@ -579,7 +579,14 @@ __device__ __forceinline__ void pair_tile(const PairArgs &a, GetTerm get_term, i
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-            for (int r = 0; r < SIG; ++r) sig[mb][nb][r] = 0.0;
+            for (int r = 0; r < SIG; ++r) {
+                sig[mb][nb][r] = 0.0;
+                if (MODE == kModeAccum && out.cont) {
+                    const int i = m0 + (wm * MB + mb) * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                    const int j = n0 + (wn * NB + nb) * 32 + l32;
+                    if (i < out.M && j < out.N) sig[mb][nb][r] = out.C[static_cast<int64_t>(i) * out.ldc + j];
+                }
+            }
 
     // only the accumulating mode sums several terms into one tile
     const int tend = (MODE == kModeAccum) ? te : tb + 1;
@@ -833,7 +840,14 @@ __device__ __forceinline__ void stream_tiles(const PairArgs &a, GetTerm get_term
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-                for (int r = 0; r < SIG; ++r) sig[mb][nb][r] = 0.0;
+                for (int r = 0; r < SIG; ++r) {
+                    sig[mb][nb][r] = 0.0;
+                    if (MODE == kModeAccum && od.cont) {
+                        const int i = m0 + (wm * MB + mb) * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                        const int j = n0 + (wn * NB + nb) * 32 + l32;
+                        if (i < od.M && j < od.N) sig[mb][nb][r] = od.C[static_cast<int64_t>(i) * od.ldc + j];
+                    }
+                }
         for (int ti = td.term_begin; ti < te; ++ti) {
             const TermDesc T = get_term(ti);
             // the next item: this tile's next term, else the next tile's first

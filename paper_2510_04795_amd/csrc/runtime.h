@@ -22,6 +22,7 @@ struct ozaki_ctx_s {
     int variant[9][16];
     bool autotune = true;  // heff plans time the variants of their grouped phases
     int heff_launch = -1;  // grouped heff phases: -1 timed choice, 0 one workgroup per tile, k > 0 streamed on k CUs
+    size_t heff_budget = 0;  // bytes for a heff plan's intermediates T; 0 = kHeffDefaultBudget
     // phase timing (ozaki_ctx_set_timing)
     bool timing = false;
     std::vector<hipEvent_t> events;  // pool
@@ -33,6 +34,12 @@ struct ozaki_ctx_s {
 };
 
 namespace oz {
+
+// Default device bytes for the intermediates of a heff plan (T in FP64, its
+// slices and exponents): the triple list runs in chunks whose first products
+// fit.  The dense two-site problem at D = 2048 (Kop = 64, phys 16) needs
+// 0.9 GiB per operator pair at S = 6, so 8 GiB holds nine pairs at a time.
+constexpr size_t kHeffDefaultBudget = size_t(8) << 30;
 
 int fail(int code, const char *fmt, ...);
 int hip_fail(hipError_t e, const char *what);

@@ -275,6 +275,12 @@ int ozaki_ctx_set_autotune(ozaki_ctx ctx, int enable) {
     return OZ_OK;
 }
 
+int ozaki_ctx_set_heff_budget(ozaki_ctx ctx, size_t bytes) {
+    if (!ctx) return fail(OZ_ERR_ARG, "ozaki_ctx_set_heff_budget: ctx is NULL");
+    ctx->heff_budget = bytes;
+    return OZ_OK;
+}
+
 int ozaki_ctx_set_heff_launch(ozaki_ctx ctx, int mode) {
     if (!ctx) return fail(OZ_ERR_ARG, "ozaki_ctx_set_heff_launch: ctx is NULL");
     if (mode < -1) return fail(OZ_ERR_ARG, "ozaki_ctx_set_heff_launch: mode = %d", mode);

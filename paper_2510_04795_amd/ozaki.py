@@ -78,6 +78,7 @@ _sig("ozaki_dgemm_tune", _i32, [_ptr, ctypes.c_char, ctypes.c_char, _i64, _i64, 
 _sig("heff_plan_variants", _i32, [_ptr, _ptr, _ptr])
 _sig("heff_plan_launches", _i32, [_ptr, _ptr, _ptr])
 _sig("ozaki_ctx_set_heff_launch", _i32, [_ptr, _i32])
+_sig("ozaki_ctx_set_heff_budget", _i32, [_ptr, _sz])
 _sig("ozaki_slices_for_bits", _i32, [_i32])
 _sig("ozaki_pair_count", _i32, [_i32, _i32])
 _sig("ozaki_max_exact_k", _i64, [_i32, _i32])
@@ -99,6 +100,8 @@ _sig("heff_apply", _i32, [_ptr, _ptr, _ptr, _ptr])
 _sig("heff_plan_set_graphs", _i32, [_ptr, _i32])
 _sig("heff_plan_graph_count", _i32, [_ptr])
 _sig("heff_vector_length", _i64, [_ptr])
+_sig("heff_plan_chunks", _i32, [_ptr])
+_sig("heff_plan_bytes", _i64, [_ptr, _ptr])
 _sig("heff_flops", _dbl, [_ptr])
 _sig("heff_plan_destroy", _i32, [_ptr])
 _sig("davidson_create", _i32, [_ptr, ctypes.POINTER(_ptr), _ptr, _ptr, _ptr, _i32, _dbl, _i32, _ptr])
@@ -123,12 +126,12 @@ EXPORTED = [
     "ozaki_status_string", "ozaki_last_error", "ozaki_version", "ozaki_ctx_create",
     "ozaki_ctx_destroy", "ozaki_ctx_flags", "ozaki_ctx_set_timing", "ozaki_ctx_phase_times",
     "ozaki_pair_variants", "ozaki_ctx_set_variant", "ozaki_ctx_get_variant",
-    "ozaki_ctx_set_autotune", "ozaki_ctx_set_heff_launch", "ozaki_dgemm_tune", "heff_plan_variants",
+    "ozaki_ctx_set_autotune", "ozaki_ctx_set_heff_launch", "ozaki_ctx_set_heff_budget", "ozaki_dgemm_tune", "heff_plan_variants",
     "heff_plan_launches", "ozaki_slices_for_bits", "ozaki_pair_count",
     "ozaki_max_exact_k", "ozaki_dgemm_workspace_bytes", "ozaki_dgemm", "ozaki_dgemm_static", "ozaki_split",
     "ozaki_choose_slices", "ozaki_dgemm_auto_workspace_bytes", "ozaki_dgemm_auto",
     "ozaki_pair_products", "heff_plan_create", "heff_apply", "heff_plan_set_graphs",
-    "heff_plan_graph_count", "heff_vector_length", "heff_flops",
+    "heff_plan_graph_count", "heff_vector_length", "heff_plan_chunks", "heff_plan_bytes", "heff_flops",
     "heff_plan_destroy", "davidson_create", "davidson_step", "davidson_get_vector",
     "davidson_set_graphs", "davidson_graph_count", "davidson_destroy", "lanczos_create", "lanczos_step", "lanczos_get_vector", "lanczos_destroy",
     "rdm_eig_create", "rdm_eig_solve", "rdm_eig_destroy", "ozaki_renormalize_workspace_bytes",
@@ -252,6 +255,12 @@ class Context:
         -1 timed choice for the first phase when its items are short
         (default)."""
         _check(_lib.ozaki_ctx_set_heff_launch(self.handle, int(mode)), "ozaki_ctx_set_heff_launch")
+
+    def set_heff_budget(self, nbytes: int = 0):
+        """Device bytes later heff plans may use for their intermediates T
+        (0 = the library default of 8 GiB); the triple list runs in chunks
+        that fit, with bit-identical results."""
+        _check(_lib.ozaki_ctx_set_heff_budget(self.handle, int(nbytes)), "ozaki_ctx_set_heff_budget")
 
     def tune(self, A, B, slices: int, ndiag: int = 0, C=None, transa="N", transb="N",
              workspace=None, stream=None):
@@ -511,6 +520,17 @@ class HeffPlan:
     @property
     def graph_count(self) -> int:
         return _check(_lib.heff_plan_graph_count(self.handle), "heff_plan_graph_count")
+
+    @property
+    def chunks(self) -> int:
+        return _check(_lib.heff_plan_chunks(self.handle), "heff_plan_chunks")
+
+    @property
+    def bytes(self):
+        """(device bytes of the plan, of which the intermediates T)."""
+        t = ctypes.c_int64(0)
+        total = _check(_lib.heff_plan_bytes(self.handle, ctypes.byref(t)), "heff_plan_bytes")
+        return total, t.value
 
     def close(self):
         if getattr(self, "handle", None):

@@ -257,6 +257,45 @@ def test_sparse_full_size_sampled_blocks(oz, launch):
             assert np.all(sig[b] == 0)
 
 
+@pytest.mark.parametrize("S", [6, 0])
+def test_chunked_plans_match(oz, S):
+    """A small T budget cuts the triple list into chunks (first products
+    recomputed where two chunks use them, sigma tiles continuing from their
+    stored values): dense and block-sparse results are the oracle's bits
+    (emulated) or the unchunked plan's bits (FP64), with graphs replayed."""
+    ozaki, ctx, torch = oz
+    L, R, psi = wl.heff_dense(D=96, kop=7, phys=4, seed=17)
+    prob = small_sparse(23)
+    # the same first product used by two far-apart triples lands in two chunks
+    tri = list(prob.triples)
+    prob.triples = tri + [tri[3], tri[len(tri) // 2]]
+    try:
+        res = {}
+        for budget in (0, 1):   # 1 byte: one first product per chunk
+            ctx.set_heff_budget(budget)
+            plan, dpsi, keep = dense_plan(ozaki, ctx, torch, L, R, psi, S)
+            assert (plan.chunks == 1) if budget == 0 else (plan.chunks == 7)
+            a = plan.apply(dpsi).cpu().numpy()
+            b = plan.apply(dpsi).cpu().numpy()
+            assert_bitexact(a, b, "dense replay")
+            splan, spsi, skeep = sparse_plan(ozaki, ctx, torch, prob, S)
+            if budget:
+                assert splan.chunks > 10
+            sa = splan.apply(spsi).cpu().numpy()
+            res[budget] = (a, sa, plan.bytes[1], splan.bytes[1])
+        assert res[1][2] < res[0][2]
+        assert_bitexact(res[1][0], res[0][0], "dense chunked vs one chunk")
+        assert_bitexact(res[1][1], res[0][1], "sparse chunked vs one chunk")
+        if S:
+            assert_bitexact(res[1][0].reshape(psi.shape), oracle.heff_dense(L, R, psi, S=S), "dense oracle")
+            ref = oracle.heff_sparse(prob, S=S)
+            sig = wl.unflatten_sparse(prob, res[1][1])
+            for blk in prob.psi_blocks:
+                assert_bitexact(sig[blk], ref[blk], "sparse oracle block %s" % (blk,))
+    finally:
+        ctx.set_heff_budget(0)
+
+
 def test_plan_argument_errors(oz):
     ozaki, ctx, torch = oz
     L, R, psi = wl.heff_dense(D=8, kop=2, phys=1, seed=0)
