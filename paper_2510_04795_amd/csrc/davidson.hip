@@ -44,10 +44,22 @@ __device__ inline double block_sum(double v, double *sh) {
     return r;
 }
 
+// Rows of a launch counted on the device: with m non-null the rows are
+// *m + add (the grid covers the largest count, the rows past it return),
+// else the grid's.  The Davidson basis size lives on the device, so one
+// captured step serves every basis size.
+struct DevRows {
+    const int *m;
+    int add;
+    __device__ bool skip(int row) const { return m && row >= *m + add; }
+};
+
 // partial[row][blk] = sum over this block's share of A[row][i] * v[i]
 __global__ __launch_bounds__(kDotThreads) void k_dots_partial(const double *__restrict__ A, int64_t lda, const double *__restrict__ v,
-                                                              int64_t n, double *__restrict__ partial, const int *gate) {
+                                                              int64_t n, double *__restrict__ partial, const int *gate,
+                                                              DevRows rows) {
     if (gate && *gate == 0) return;
+    if (rows.skip(blockIdx.y)) return;
     __shared__ double sh[kDotThreads];
     const int row = blockIdx.y;
     const double *a = A + row * lda;
@@ -60,25 +72,30 @@ __global__ __launch_bounds__(kDotThreads) void k_dots_partial(const double *__re
 }
 
 // out[row * out_stride] = sum of the row's partials; optional mirror out2.
+// With rows.m set, out and out2 move by *rows.m times out_mscale / out2_mscale.
 __global__ __launch_bounds__(kDotThreads) void k_dots_final(const double *__restrict__ partial, int nblk, double *out, int64_t out_stride,
-                                                            double *out2, int64_t out2_stride, const int *gate) {
+                                                            double *out2, int64_t out2_stride, const int *gate,
+                                                            DevRows rows, int64_t out_mscale, int64_t out2_mscale) {
     if (gate && *gate == 0) return;
+    if (rows.skip(blockIdx.x)) return;
     __shared__ double sh[kDotThreads];
     const int row = blockIdx.x;
     double acc = 0.0;
     for (int b = threadIdx.x; b < nblk; b += blockDim.x) acc += partial[static_cast<int64_t>(row) * nblk + b];
     const double s = block_sum(acc, sh);
     if (threadIdx.x == 0) {
-        out[row * out_stride] = s;
-        if (out2) out2[row * out2_stride] = s;
+        const int64_t m = rows.m ? *rows.m : 0;
+        out[m * out_mscale + row * out_stride] = s;
+        if (out2) out2[m * out2_mscale + row * out2_stride] = s;
     }
 }
 
 // Lowest eigenpair of the symmetric m x m matrix G (leading dimension ldg) by
 // cyclic Jacobi with the round-robin pairing; writes theta and y (largest
 // |y_i| made positive).  One workgroup of 256 threads, m <= 64.
-__global__ __launch_bounds__(256) void k_jacobi(const double *__restrict__ G, int ldg, int m, double *__restrict__ y,
-                                                double *__restrict__ theta_out) {
+__global__ __launch_bounds__(256) void k_jacobi(const double *__restrict__ G, int ldg, int m_arg, const int *m_dev,
+                                                double *__restrict__ y, double *__restrict__ theta_out) {
+    const int m = m_dev ? *m_dev : m_arg;
     __shared__ double A[64][65];
     __shared__ double Vv[64][65];
     __shared__ double cs[32], sn[32];
@@ -175,9 +192,10 @@ __global__ __launch_bounds__(256) void k_jacobi(const double *__restrict__ G, in
 
 // x = V^T y, hx = W^T y, r = hx - theta x, partial sums of r^2.
 __global__ __launch_bounds__(kDotThreads) void k_ritz(const double *__restrict__ V, const double *__restrict__ W, int64_t n,
-                                                      int m, const double *__restrict__ y, const double *__restrict__ theta,
+                                                      const int *m_dev, const double *__restrict__ y, const double *__restrict__ theta,
                                                       double *__restrict__ x, double *__restrict__ hx, double *__restrict__ r,
                                                       double *__restrict__ partial) {
+    const int m = *m_dev;
     __shared__ double sh[kDotThreads];
     const double th = *theta;
     double acc = 0.0;
@@ -210,9 +228,10 @@ __global__ void k_precond(const double *__restrict__ r, const double *__restrict
 }
 
 // t -= V^T c  (c: m projection coefficients)
-__global__ void k_project(const double *__restrict__ V, int64_t n, int m, const double *__restrict__ c,
-                          double *__restrict__ t, const int *gate) {
+__global__ void k_project(const double *__restrict__ V, int64_t n, int m_arg, const int *m_dev,
+                          const double *__restrict__ c, double *__restrict__ t, const int *gate) {
     if (gate && *gate == 0) return;
+    const int m = m_dev ? *m_dev : m_arg;
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
         double s = 0.0;
@@ -232,26 +251,47 @@ __global__ void k_fallback(const double *__restrict__ nrm2, const double *__rest
         t[i] = r[i];
 }
 
+// out (moved by *m_dev rows of n when m_dev is set) = t / sqrt(nrm2); the
+// same values into out2 when it is set
 __global__ void k_scale_into(const double *__restrict__ t, const double *__restrict__ nrm2, double *__restrict__ out,
-                             int64_t n) {
+                             int64_t n, const int *m_dev = nullptr, double *__restrict__ out2 = nullptr) {
     const double inv = 1.0 / sqrt(*nrm2);
+    double *o = out + (m_dev ? static_cast<int64_t>(*m_dev) * n : 0);
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
-        out[i] = t[i] * inv;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const double v = t[i] * inv;
+        o[i] = v;
+        if (out2) out2[i] = v;
+    }
 }
 
-// collapse the basis to the Ritz pair: G = [theta], zero elsewhere
-__global__ void k_collapse_g(double *G, int ldg, int mmax, const double *theta) {
+// collapse the basis to the Ritz pair when it is full (*m_dev == mmax):
+// G = [theta], zero elsewhere, and the basis size becomes 1
+__global__ void k_collapse_g(double *G, int ldg, int mmax, const double *theta, int *m_dev) {
+    if (*m_dev != mmax) return;
     for (int i = threadIdx.x; i < mmax * mmax; i += blockDim.x) G[(i / mmax) * ldg + i % mmax] = 0.0;
     __syncthreads();
-    if (threadIdx.x == 0) G[0] = *theta;
+    if (threadIdx.x == 0) {
+        G[0] = *theta;
+        *m_dev = 1;
+    }
 }
 
-// dst = src (the collapse of the basis to the Ritz pair)
-__global__ void k_copy(const double *__restrict__ src, double *__restrict__ dst, int64_t n) {
+// dst (moved by *m_dev rows of n) = src; with full set, only when the basis
+// is full (*m_dev == full), into row 0 (the collapse to the Ritz pair)
+__global__ void k_copy_row(const double *__restrict__ src, double *__restrict__ dst, int64_t n, const int *m_dev,
+                           int full) {
+    const int m = *m_dev;
+    if (full && m != full) return;
+    double *d = dst + (full ? 0 : static_cast<int64_t>(m) * n);
     for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x)
-        dst[i] = src[i];
+        d[i] = src[i];
+}
+
+// *m_dev += 1 (the basis gained a vector)
+__global__ void k_bump(int *m_dev) {
+    if (threadIdx.x == 0) *m_dev += 1;
 }
 
 // (theta, rho^2) into the pinned host buffer the step reads after its sync
@@ -279,17 +319,20 @@ struct davidson_s {
     double *xs[2] = {nullptr, nullptr};
     int cur = 0, rep = 0;
     double *hx = nullptr, *r = nullptr, *t = nullptr;
+    double *mv_in = nullptr, *mv_out = nullptr;  // the matvec's fixed input and output
     double *y = nullptr, *coef = nullptr, *partial = nullptr, *scal = nullptr;  // scal: theta, rho2, nrm2
     int *gate = nullptr;
+    int *m_dev = nullptr;  // the basis size on the device (the host keeps m too)
     double *host = nullptr;  // pinned: theta, rho2 of the latest Rayleigh-Ritz solve
     int m = 0, iter = 0, status = OZ_OK;
     std::vector<double> hist;
     // Replay: the launches that follow a step's decision (correction, basis
-    // update, matvec, next Rayleigh-Ritz) depend only on the basis size and
-    // on which Ritz buffer is current, so each (m, cur) is captured once.
+    // update, matvec, next Rayleigh-Ritz) read the basis size from the
+    // device and use fixed matvec buffers, so they depend only on which Ritz
+    // buffer is current: two graphs serve every step.
     bool use_graphs = true;
     hipStream_t cap = nullptr;
-    std::vector<hipGraphExec_t> graphs;  // index 2 m + cur
+    hipGraphExec_t graphs[2] = {nullptr, nullptr};  // per current Ritz buffer
 };
 
 namespace {
@@ -314,85 +357,102 @@ void dfree(davidson d) {
 hipError_t dots(davidson d, const double *A, int64_t lda, int rows, const double *v, double *out,
                 int64_t out_stride, double *out2, int64_t out2_stride, const int *gate, hipStream_t s) {
     const int nb = dot_blocks(d->n);
-    hipLaunchKernelGGL(k_dots_partial, dim3(nb, rows), dim3(kDotThreads), 0, s, A, lda, v, d->n, d->partial, gate);
+    hipLaunchKernelGGL(k_dots_partial, dim3(nb, rows), dim3(kDotThreads), 0, s, A, lda, v, d->n, d->partial, gate,
+                       DevRows{nullptr, 0});
     hipLaunchKernelGGL(k_dots_final, dim3(rows), dim3(kDotThreads), 0, s, d->partial, nb, out, out_stride, out2,
-                       out2_stride, gate);
+                       out2_stride, gate, DevRows{nullptr, 0}, 0, 0);
     return hipGetLastError();
 }
 
-// V[m] := normalised, orthogonalised t; W[m] = H V[m]; new column of G.
-int expand(davidson d, int m, hipStream_t s) {
+// The same over *m_dev + add rows of A (the grid covers m_max + 1); out and
+// out2 move by *m_dev times out_mscale / out2_mscale.
+hipError_t dots_m(davidson d, const double *A, int64_t lda, int add, const double *v, double *out,
+                  int64_t out_stride, int64_t out_mscale, double *out2, int64_t out2_stride, int64_t out2_mscale,
+                  const int *gate, hipStream_t s) {
+    const int nb = dot_blocks(d->n);
+    const int rows = d->m_max + add;
+    hipLaunchKernelGGL(k_dots_partial, dim3(nb, rows), dim3(kDotThreads), 0, s, A, lda, v, d->n, d->partial, gate,
+                       DevRows{d->m_dev, add});
+    hipLaunchKernelGGL(k_dots_final, dim3(rows), dim3(kDotThreads), 0, s, d->partial, nb, out, out_stride, out2,
+                       out2_stride, gate, DevRows{d->m_dev, add}, out_mscale, out2_mscale);
+    return hipGetLastError();
+}
+
+// V[m] := normalised, orthogonalised t; W[m] = H V[m]; new column of G;
+// m += 1.  m is the device's basis size.
+int expand(davidson d, hipStream_t s) {
     hipError_t e;
     const int64_t n = d->n;
     double *nrm2 = d->scal + 2;
     for (int pass = 0; pass < 2; ++pass) {
-        if ((e = dots(d, d->V, n, m, d->t, d->coef, 1, nullptr, 0, nullptr, s)) != hipSuccess) return hip_fail(e, "davidson: projection");
-        hipLaunchKernelGGL(k_project, dim3(grid_n(n)), dim3(256), 0, s, d->V, n, m, d->coef, d->t, nullptr);
+        if ((e = dots_m(d, d->V, n, 0, d->t, d->coef, 1, 0, nullptr, 0, 0, nullptr, s)) != hipSuccess)
+            return hip_fail(e, "davidson: projection");
+        hipLaunchKernelGGL(k_project, dim3(grid_n(n)), dim3(256), 0, s, d->V, n, 0, d->m_dev, d->coef, d->t, nullptr);
     }
     if ((e = dots(d, d->t, n, 1, d->t, nrm2, 1, nullptr, 0, nullptr, s)) != hipSuccess) return hip_fail(e, "davidson: norm");
     hipLaunchKernelGGL(k_fallback, dim3(grid_n(n)), dim3(256), 0, s, nrm2, d->r, d->t, n, d->gate);
     for (int pass = 0; pass < 2; ++pass) {
-        dots(d, d->V, n, m, d->t, d->coef, 1, nullptr, 0, d->gate, s);
-        hipLaunchKernelGGL(k_project, dim3(grid_n(n)), dim3(256), 0, s, d->V, n, m, d->coef, d->t, d->gate);
+        dots_m(d, d->V, n, 0, d->t, d->coef, 1, 0, nullptr, 0, 0, d->gate, s);
+        hipLaunchKernelGGL(k_project, dim3(grid_n(n)), dim3(256), 0, s, d->V, n, 0, d->m_dev, d->coef, d->t, d->gate);
     }
     dots(d, d->t, n, 1, d->t, nrm2, 1, nullptr, 0, d->gate, s);
-    double *vm = d->V + static_cast<int64_t>(m) * n;
-    double *wm = d->W + static_cast<int64_t>(m) * n;
-    hipLaunchKernelGGL(k_scale_into, dim3(grid_n(n)), dim3(256), 0, s, d->t, nrm2, vm, n);
+    // V[m] and the matvec's input get the same values
+    hipLaunchKernelGGL(k_scale_into, dim3(grid_n(n)), dim3(256), 0, s, d->t, nrm2, d->V, n, d->m_dev, d->mv_in);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "davidson: orthogonalisation");
-    int rc = heff_apply(d->H, vm, wm, s);
+    int rc = heff_apply(d->H, d->mv_in, d->mv_out, s);
     if (rc != OZ_OK) return rc;
+    hipLaunchKernelGGL(k_copy_row, dim3(grid_n(n)), dim3(256), 0, s, d->mv_out, d->W, n, d->m_dev, 0);
     // G[i][m] = G[m][i] = V[i] . W[m], i <= m
-    if ((e = dots(d, d->V, n, m + 1, wm, d->G + m, d->m_max, d->G + static_cast<int64_t>(m) * d->m_max, 1, nullptr, s)) != hipSuccess)
+    if ((e = dots_m(d, d->V, n, 1, d->mv_out, d->G, d->m_max, 1, d->G, 1, d->m_max, nullptr, s)) != hipSuccess)
         return hip_fail(e, "davidson: projected column");
+    hipLaunchKernelGGL(k_bump, dim3(1), dim3(64), 0, s, d->m_dev);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "davidson: basis size");
     return OZ_OK;
 }
 
-// Rayleigh-Ritz on the first m basis vectors, the Ritz pair into x_out (and
-// hx, r), rho^2, and (theta, rho^2) published to the pinned host buffer.
-int rayleigh_ritz(davidson d, int m, double *x_out, hipStream_t s) {
+// Rayleigh-Ritz on the device's basis of m vectors, the Ritz pair into x_out
+// (and hx, r), rho^2, and (theta, rho^2) published to the pinned host buffer.
+int rayleigh_ritz(davidson d, double *x_out, hipStream_t s) {
     const int64_t n = d->n;
     double *theta = d->scal, *rho2 = d->scal + 1;
-    hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(256), 0, s, d->G, d->m_max, m, d->y, theta);
+    hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(256), 0, s, d->G, d->m_max, 0, d->m_dev, d->y, theta);
     const int nb = dot_blocks(n);
-    hipLaunchKernelGGL(k_ritz, dim3(nb), dim3(kDotThreads), 0, s, d->V, d->W, n, m, d->y, theta, x_out, d->hx, d->r,
-                       d->partial);
-    hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(kDotThreads), 0, s, d->partial, nb, rho2, 1, nullptr, 0, nullptr);
+    hipLaunchKernelGGL(k_ritz, dim3(nb), dim3(kDotThreads), 0, s, d->V, d->W, n, d->m_dev, d->y, theta, x_out, d->hx,
+                       d->r, d->partial);
+    hipLaunchKernelGGL(k_dots_final, dim3(1), dim3(kDotThreads), 0, s, d->partial, nb, rho2, 1, nullptr, 0, nullptr,
+                       DevRows{nullptr, 0}, 0, 0);
     hipLaunchKernelGGL(k_publish, dim3(1), dim3(64), 0, s, d->scal, d->host);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? OZ_OK : hip_fail(e, "davidson: Rayleigh-Ritz");
 }
 
-// Everything a continuing step does after its decision, for basis size m and
-// current Ritz buffer c: correction, collapse when the basis is full,
-// orthogonalisation and matvec, then the next Rayleigh-Ritz into xs[c ^ 1].
-int step_tail(davidson d, int m, int c, hipStream_t s) {
+// Everything a continuing step does after its decision, with current Ritz
+// buffer c: correction, collapse when the basis is full, orthogonalisation
+// and matvec, then the next Rayleigh-Ritz into xs[c ^ 1].
+int step_tail(davidson d, int c, hipStream_t s) {
     const int64_t n = d->n;
     const double *theta = d->scal;
     hipLaunchKernelGGL(k_precond, dim3(grid_n(n)), dim3(256), 0, s, d->r, d->hdiag, theta, d->t, n);
-    if (m == d->m_max) {
-        hipLaunchKernelGGL(k_copy, dim3(grid_n(n)), dim3(256), 0, s, d->xs[c], d->V, n);
-        hipLaunchKernelGGL(k_copy, dim3(grid_n(n)), dim3(256), 0, s, d->hx, d->W, n);
-        hipLaunchKernelGGL(k_collapse_g, dim3(1), dim3(256), 0, s, d->G, d->m_max, d->m_max, theta);
-        m = 1;
-    }
-    int rc = expand(d, m, s);
+    hipLaunchKernelGGL(k_copy_row, dim3(grid_n(n)), dim3(256), 0, s, d->xs[c], d->V, n, d->m_dev, d->m_max);
+    hipLaunchKernelGGL(k_copy_row, dim3(grid_n(n)), dim3(256), 0, s, d->hx, d->W, n, d->m_dev, d->m_max);
+    hipLaunchKernelGGL(k_collapse_g, dim3(1), dim3(256), 0, s, d->G, d->m_max, d->m_max, theta, d->m_dev);
+    int rc = expand(d, s);
     if (rc != OZ_OK) return rc;
-    return rayleigh_ritz(d, m + 1, d->xs[c ^ 1], s);
+    return rayleigh_ritz(d, d->xs[c ^ 1], s);
 }
 
-// step_tail from a captured graph (captured the first time (m, c) is seen),
-// or issued directly when phases are being timed or graphs are off.
-int run_tail(davidson d, int m, int c, hipStream_t s) {
+// step_tail from a captured graph (captured the first time c is seen), or
+// issued directly when phases are being timed or graphs are off.
+int run_tail(davidson d, int c, hipStream_t s) {
     hipError_t e;
-    if (!d->use_graphs || d->ctx->timing) return step_tail(d, m, c, s);
-    hipGraphExec_t &g = d->graphs[2 * m + c];
+    if (!d->use_graphs || d->ctx->timing) return step_tail(d, c, s);
+    hipGraphExec_t &g = d->graphs[c];
     if (!g) {
         if (!d->cap && (e = hipStreamCreateWithFlags(&d->cap, hipStreamNonBlocking)) != hipSuccess)
             return hip_fail(e, "davidson: capture stream");
         if ((e = hipStreamBeginCapture(d->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess)
             return hip_fail(e, "davidson: begin capture");
-        const int rc = step_tail(d, m, c, d->cap);
+        const int rc = step_tail(d, c, d->cap);
         hipGraph_t graph = nullptr;
         e = hipStreamEndCapture(d->cap, &graph);
         if (rc != OZ_OK) {
@@ -446,6 +506,9 @@ int davidson_create(ozaki_ctx ctx, davidson *out, heff_plan H, const double *hdi
     OZ_DA(xs[0], sizeof(double) * n)
     OZ_DA(xs[1], sizeof(double) * n)
     OZ_DA(hx, sizeof(double) * n)
+    OZ_DA(mv_in, sizeof(double) * n)
+    OZ_DA(mv_out, sizeof(double) * n)
+    OZ_DA(m_dev, sizeof(int) * 4)
     OZ_DA(r, sizeof(double) * n)
     OZ_DA(t, sizeof(double) * n)
     OZ_DA(y, sizeof(double) * 64)
@@ -479,11 +542,15 @@ int davidson_create(ozaki_ctx ctx, davidson *out, heff_plan H, const double *hdi
     hipLaunchKernelGGL(k_scale_into, dim3(grid_n(n)), dim3(256), 0, s, x0, nrm2, d->V, n);
     if ((rc = heff_apply(H, d->V, d->W, s)) != OZ_OK) { dfree(d); return rc; }
     dots(d, d->V, n, 1, d->W, d->G, 1, nullptr, 0, nullptr, s);
+    const int one = 1;
+    if ((e = hipMemcpyAsync(d->m_dev, &one, sizeof(int), hipMemcpyHostToDevice, s)) != hipSuccess) {
+        dfree(d);
+        return hip_fail(e, "davidson_create: basis size");
+    }
     // the first step's Rayleigh-Ritz solve (every later one ends the step before)
-    if ((rc = rayleigh_ritz(d, 1, d->xs[0], s)) != OZ_OK) { dfree(d); return rc; }
+    if ((rc = rayleigh_ritz(d, d->xs[0], s)) != OZ_OK) { dfree(d); return rc; }
     if ((e = hipStreamSynchronize(s)) != hipSuccess) { dfree(d); return hip_fail(e, "davidson_create: sync"); }
     d->m = 1;
-    d->graphs.assign(2 * static_cast<size_t>(m_max + 1), nullptr);
     *out = d;
     return OZ_OK;
 }
@@ -525,7 +592,7 @@ int davidson_step(davidson d, davidson_info *info, void *stream) {
         // correction, basis update, matvec and the next Rayleigh-Ritz solve:
         // one graph replay and one synchronisation per step
         const int m = d->m;
-        int rc = run_tail(d, m, d->cur, s);
+        int rc = run_tail(d, d->cur, s);
         if (rc != OZ_OK) return rc;
         if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "davidson_step: sync");
         d->m = (m == d->m_max ? 1 : m) + 1;
@@ -666,8 +733,10 @@ void lfree(lanczos l) {
 // out[i] = Q_i . v for i < rows, with the Davidson dot kernels
 hipError_t ldots(lanczos l, const double *Q, int rows, const double *v, double *out, hipStream_t s) {
     const int nb = dot_blocks(l->n);
-    hipLaunchKernelGGL(k_dots_partial, dim3(nb, rows), dim3(kDotThreads), 0, s, Q, l->n, v, l->n, l->partial, nullptr);
-    hipLaunchKernelGGL(k_dots_final, dim3(rows), dim3(kDotThreads), 0, s, l->partial, nb, out, 1, nullptr, 0, nullptr);
+    hipLaunchKernelGGL(k_dots_partial, dim3(nb, rows), dim3(kDotThreads), 0, s, Q, l->n, v, l->n, l->partial, nullptr,
+                       DevRows{nullptr, 0});
+    hipLaunchKernelGGL(k_dots_final, dim3(rows), dim3(kDotThreads), 0, s, l->partial, nb, out, 1, nullptr, 0, nullptr,
+                       DevRows{nullptr, 0}, 0, 0);
     return hipGetLastError();
 }
 
@@ -761,7 +830,7 @@ int lanczos_step(lanczos l, davidson_info *info, void *stream) {
         if ((e = ldots(l, l->Q, m, l->w, l->coef, s)) != hipSuccess) return hip_fail(e, "lanczos: projection");
         if (pass == 0 && (e = hipMemcpyAsync(l->host, l->coef, sizeof(double) * m, hipMemcpyDeviceToHost, s)) != hipSuccess)
             return hip_fail(e, "lanczos: coefficients");
-        hipLaunchKernelGGL(k_project, dim3(grid_n(n)), dim3(256), 0, s, l->Q, n, m, l->coef, l->w, nullptr);
+        hipLaunchKernelGGL(k_project, dim3(grid_n(n)), dim3(256), 0, s, l->Q, n, m, nullptr, l->coef, l->w, nullptr);
     }
     if ((e = ldots(l, l->w, 1, l->w, l->scal, s)) != hipSuccess) return hip_fail(e, "lanczos: norm");
     if ((e = hipMemcpyAsync(l->host + 64, l->scal, sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess ||
