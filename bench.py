@@ -240,7 +240,7 @@ def sweep_section(args, ozaki, ctx, torch, oracle):
             for (n, U) in cases]
 
 
-PAIR_SOURCES = ["internal.h", "pairgemm_impl.h", "pairgemm.hip"] + ["pairgemm_s%d.hip" % s for s in range(2, 9)]
+PAIR_SOURCES = ["internal.h", "asm_steps.h", "pairgemm_impl.h", "pairgemm.hip"] + ["pairgemm_s%d.hip" % s for s in range(2, 9)]
 COUNTERS_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
                              "pair_gemm_n8192_hbm_counters.txt")
 
@@ -381,14 +381,15 @@ def heff_section(args, ozaki, ctx, torch, name, layout, Lf, Rf, pf, triples, sli
              "cold_ms": (t + tplan) * 1e3, "phase_ms": phs,
              "tile_variants": list(plan.variants), "streamed_launches": list(plan.launches),
              "chunks": plan.chunks, "plan_bytes": plan.bytes[0], "plan_T_bytes": plan.bytes[1],
+             "phase_choice": {"L": list(plan.phase(0)), "R": list(plan.phase(1))},
              "int8_frac_pair_phases": (P * plan.flops / ((phs.get("heff_L", 0) + phs.get("heff_R", 0)) * 1e-3)
                                        / 1e12 / INT8_PEAK_TOPS) if phs else None}
         res.append(r)
         log("[bench] %s S=%d G=%d: %.3f ms/apply  %.2f TFLOP/s  err vs fp64 %s  vs dd %s  phases %s  "
-            "variants %s streamed %s  chunks %d  plan %.2f GiB (T %.2f GiB)"
+            "choice L %s R %s (variant:order:launch)  chunks %d  plan %.2f GiB (T %.2f GiB)"
             % (name, S, G, t * 1e3, r["tflops"], err, r["rel_err_vs_dd_sampled"],
-               {k: round(v, 3) for k, v in phs.items()}, plan.variants, plan.launches, plan.chunks,
-               plan.bytes[0] / 2 ** 30, plan.bytes[1] / 2 ** 30))
+               {k: round(v, 3) for k, v in phs.items()}, ":".join(map(str, plan.phase(0))),
+               ":".join(map(str, plan.phase(1))), plan.chunks, plan.bytes[0] / 2 ** 30, plan.bytes[1] / 2 ** 30))
         plan.close()
         del keep
     out["emulated"] = res
@@ -693,6 +694,9 @@ def main():
     ap.add_argument("--heff-no-fp64", action="store_true", help="skip the FP64 H_eff plans (profiling runs)")
     ap.add_argument("--heff-variant", type=int, default=-1,
                     help="fixed pair-GEMM tile variant for the H_eff plans, with plan timing off (profiling runs)")
+    ap.add_argument("--heff-fix", default="",
+                    help="fixed phase choices of the emulated H_eff plans, e.g. L=0:1:256,R=4:1:0 "
+                         "(variant:order:launch per phase, as the bench log prints them); nothing is timed")
     ap.add_argument("--heff-launch", type=int, default=-1,
                     help="H_eff grouped launch: -1 timed choice, 0 one workgroup per tile, k > 0 streamed on k CUs")
     ap.add_argument("--dd-samples", type=int, default=3,
@@ -720,6 +724,10 @@ def main():
         for S, _ in heff_slices(args):
             ctx.set_variant(S, S, args.heff_variant)
     ctx.set_heff_launch(args.heff_launch)
+    for item in filter(None, args.heff_fix.split(",")):
+        ph, spec = item.split("=")
+        v, o, l = (int(x) for x in spec.split(":"))
+        ctx.set_heff_phase({"L": 0, "R": 1}[ph], v, o, l)
     gemm = None
     if "gemm" in sections:
         gemm, (A, B) = gemm_section(args, ozaki, ctx, torch, oracle)

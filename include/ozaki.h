@@ -230,6 +230,16 @@ int ozaki_ctx_set_heff_launch(ozaki_ctx ctx, int mode);
  * apply; sigma tiles continue across chunks from their stored values, so
  * the result is bit-identical for every budget. */
 int ozaki_ctx_set_heff_budget(ozaki_ctx ctx, size_t bytes);
+/* Fix the choice of one grouped phase (0 = first product, 1 = second) for
+ * emulated heff plans created afterwards: tile variant (see
+ * ozaki_pair_variants; < 0 clears the fix), tile order (0 = cost-balanced
+ * contiguous parts per XCD, 1 = longest tile first) and launch (0 = one
+ * workgroup per tile, k > 0 = streamed on k compute units).  With both
+ * phases fixed a plan times nothing, which reproduces a timed plan's choice
+ * (heff_plan_phase) exactly, e.g. for profiling.  OZ_ERR_ARG for an unknown
+ * phase, variant, order or launch; a variant not built for the plan's
+ * (S, G) makes heff_plan_create fail with OZ_ERR_ARG. */
+int ozaki_ctx_set_heff_phase(ozaki_ctx ctx, int phase, int variant, int order, int launch);
 /* Time every built variant of this GEMM (alpha = 1, beta = 0 into C, one
  * warm-up and three timed calls each) and fix the fastest for (slices,
  * ndiag) in the context.  ms_out (host, nullable, one slot per variant) gets
@@ -341,6 +351,11 @@ int heff_plan_variants(heff_plan plan, int32_t *first, int32_t *second);
 int heff_plan_launches(heff_plan plan, int32_t *first, int32_t *second);
 /* Total elements of psi for the plan's layout. */
 int64_t heff_vector_length(heff_plan plan);
+/* The choice of grouped phase `phase` (0 = first product, 1 = second) in an
+ * emulated plan: tile variant, order (0 XCD parts, 1 longest tile first) and
+ * launch (0 one workgroup per tile, k > 0 streamed on k CUs); all -1 for a
+ * native FP64 plan. */
+int heff_plan_phase(heff_plan plan, int phase, int32_t *variant, int32_t *order, int32_t *launch);
 /* Number of chunks the plan's triple list runs in (ozaki_ctx_set_heff_budget). */
 int heff_plan_chunks(heff_plan plan);
 /* Device bytes the plan holds (all its allocations); *T_bytes (nullable)

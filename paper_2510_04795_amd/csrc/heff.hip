@@ -66,6 +66,7 @@ struct heff_plan_s {
     int32_t *psi_emax = nullptr;  // exponent-code maxima of psi's split column pass
     int64_t psi_e_total = 0;
     int varL = -1, varR = -1;   // tile variants of the two grouped phases
+    int choice[2][3] = {{-1, -1, -1}, {-1, -1, -1}};  // per phase: variant, order, launch
     std::vector<HeffChunk> chunks;
     size_t T_bytes = 0;         // T buffer, its slices and exponents
     size_t bytes = 0;           // every device allocation of the plan
@@ -696,7 +697,13 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
     double bestL = -1, bestR = -1;
     void *tmp_sigma = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    const bool tuning = cands.size() > 1 || ctx->autotune;
+    // both phases fixed by the context: nothing is timed
+    const bool fixed_phases = ctx->heff_fix[0][0] >= 0 && ctx->heff_fix[1][0] >= 0;
+    if (fixed_phases && (!pair_variant_ok(G, ctx->heff_fix[0][0]) || !pair_variant_ok(G, ctx->heff_fix[1][0]))) {
+        free_plan(P);
+        return fail(OZ_ERR_ARG, "heff_plan_create: fixed tile variant not built for ndiag %d", G);
+    }
+    const bool tuning = !fixed_phases && (cands.size() > 1 || ctx->autotune);
     if (tuning) {
         if ((e = hipMalloc(&tmp_sigma, sizeof(double) * std::max<int64_t>(n, 1))) != hipSuccess) { free_plan(P); return hip_fail(e, "heff_plan_create: tuning buffer"); }
         hipMemsetAsync(P->psi_p, 0, std::max<int64_t>(Ps.p_total, 256), s);
@@ -740,6 +747,22 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
         hipFree(tmp_sigma);
         free_plan(P);
         return hip_fail(e, "heff_plan_create: tuning buffer");
+    }
+    if (fixed_phases) {
+        runs.clear();
+        const int32_t cus[2] = {ctx->heff_fix[0][2] > 0 ? std::min(ctx->heff_fix[0][2], ctx->num_cu) : 0,
+                                ctx->heff_fix[1][2] > 0 ? std::min(ctx->heff_fix[1][2], ctx->num_cu) : 0};
+        chosenL = Run{ctx->heff_fix[0][0], ctx->heff_fix[0][1] == 0, cus[0] > 0};
+        chosenR = Run{ctx->heff_fix[1][0], ctx->heff_fix[1][1] == 0, cus[1] > 0};
+        std::vector<TileDesc> l1, r1, l2, r2;
+        std::vector<int64_t> cl1, cr1, cl2, cr2;
+        tiles_for(0, chosenL.v, chosenL.xcd, &l1, &r1, &cl1, &cr1);
+        tiles_for(0, chosenR.v, chosenR.xcd, &l2, &r2, &cl2, &cr2);
+        if ((rc = upload(P, l1, &dtl)) || (rc = upload(P, r2, &dtr))) { free_plan(P); return rc; }
+        c0.argsL.tiles = dtl; c0.argsL.ntiles = static_cast<int32_t>(l1.size()); c0.argsL.stream_cus = cus[0];
+        c0.argsR.tiles = dtr; c0.argsR.ntiles = static_cast<int32_t>(r2.size()); c0.argsR.stream_cus = cus[1];
+        P->varL = chosenL.v;
+        P->varR = chosenR.v;
     }
     for (auto run : runs) {
         const int v = run.v;
@@ -842,6 +865,12 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
         if (P->T_emax && (e = hipMemcpy(P->T_emax, emax_init.data(), sizeof(int32_t) * emax_init.size(),
                                         hipMemcpyHostToDevice)) != hipSuccess) { free_plan(P); return hip_fail(e, "heff_plan_create: reset"); }
     }
+    P->choice[0][0] = P->varL;
+    P->choice[0][1] = chosenL.xcd ? 0 : 1;
+    P->choice[0][2] = c0.argsL.stream_cus;
+    P->choice[1][0] = P->varR;
+    P->choice[1][1] = chosenR.xcd ? 0 : 1;
+    P->choice[1][2] = c0.argsR.stream_cus;
     // the other chunks take the first chunk's choice per phase
     for (size_t c = 1; c < hc.size(); ++c) {
         HeffChunk &ch = P->chunks[c];
@@ -1000,6 +1029,15 @@ int heff_plan_launches(heff_plan P, int32_t *first, int32_t *second) {
     if (!P) return fail(OZ_ERR_ARG, "heff_plan_launches: plan is NULL");
     if (first) *first = P->S ? (P->chunks[0].argsL.stream_cus > 0 ? 1 : 0) : -1;
     if (second) *second = P->S ? (P->chunks[0].argsR.stream_cus > 0 ? 1 : 0) : -1;
+    return OZ_OK;
+}
+
+int heff_plan_phase(heff_plan P, int phase, int32_t *variant, int32_t *order, int32_t *launch) {
+    if (!P) return fail(OZ_ERR_ARG, "heff_plan_phase: plan is NULL");
+    if (phase < 0 || phase > 1) return fail(OZ_ERR_ARG, "heff_plan_phase: phase = %d", phase);
+    if (variant) *variant = P->choice[phase][0];
+    if (order) *order = P->choice[phase][1];
+    if (launch) *launch = P->choice[phase][2];
     return OZ_OK;
 }
 

@@ -23,6 +23,10 @@ struct ozaki_ctx_s {
     bool autotune = true;  // heff plans time the variants of their grouped phases
     int heff_launch = -1;  // grouped heff phases: -1 timed choice, 0 one workgroup per tile, k > 0 streamed on k CUs
     size_t heff_budget = 0;  // bytes for a heff plan's intermediates T; 0 = kHeffDefaultBudget
+    // fixed choice per grouped phase of later emulated heff plans (variant < 0:
+    // timed): tile variant, order (0 XCD parts, 1 longest tile first), launch
+    // (0 one workgroup per tile, k > 0 streamed on k CUs)
+    int heff_fix[2][3] = {{-1, 0, 0}, {-1, 0, 0}};
     // phase timing (ozaki_ctx_set_timing)
     bool timing = false;
     std::vector<hipEvent_t> events;  // pool

@@ -79,6 +79,7 @@ _sig("heff_plan_variants", _i32, [_ptr, _ptr, _ptr])
 _sig("heff_plan_launches", _i32, [_ptr, _ptr, _ptr])
 _sig("ozaki_ctx_set_heff_launch", _i32, [_ptr, _i32])
 _sig("ozaki_ctx_set_heff_budget", _i32, [_ptr, _sz])
+_sig("ozaki_ctx_set_heff_phase", _i32, [_ptr, _i32, _i32, _i32, _i32])
 _sig("ozaki_slices_for_bits", _i32, [_i32])
 _sig("ozaki_pair_count", _i32, [_i32, _i32])
 _sig("ozaki_max_exact_k", _i64, [_i32, _i32])
@@ -101,6 +102,7 @@ _sig("heff_plan_set_graphs", _i32, [_ptr, _i32])
 _sig("heff_plan_graph_count", _i32, [_ptr])
 _sig("heff_vector_length", _i64, [_ptr])
 _sig("heff_plan_chunks", _i32, [_ptr])
+_sig("heff_plan_phase", _i32, [_ptr, _i32, _ptr, _ptr, _ptr])
 _sig("heff_plan_bytes", _i64, [_ptr, _ptr])
 _sig("heff_flops", _dbl, [_ptr])
 _sig("heff_plan_destroy", _i32, [_ptr])
@@ -126,12 +128,14 @@ EXPORTED = [
     "ozaki_status_string", "ozaki_last_error", "ozaki_version", "ozaki_ctx_create",
     "ozaki_ctx_destroy", "ozaki_ctx_flags", "ozaki_ctx_set_timing", "ozaki_ctx_phase_times",
     "ozaki_pair_variants", "ozaki_ctx_set_variant", "ozaki_ctx_get_variant",
-    "ozaki_ctx_set_autotune", "ozaki_ctx_set_heff_launch", "ozaki_ctx_set_heff_budget", "ozaki_dgemm_tune", "heff_plan_variants",
+    "ozaki_ctx_set_autotune", "ozaki_ctx_set_heff_launch", "ozaki_ctx_set_heff_budget",
+    "ozaki_ctx_set_heff_phase", "ozaki_dgemm_tune", "heff_plan_variants",
     "heff_plan_launches", "ozaki_slices_for_bits", "ozaki_pair_count",
     "ozaki_max_exact_k", "ozaki_dgemm_workspace_bytes", "ozaki_dgemm", "ozaki_dgemm_static", "ozaki_split",
     "ozaki_choose_slices", "ozaki_dgemm_auto_workspace_bytes", "ozaki_dgemm_auto",
     "ozaki_pair_products", "heff_plan_create", "heff_apply", "heff_plan_set_graphs",
-    "heff_plan_graph_count", "heff_vector_length", "heff_plan_chunks", "heff_plan_bytes", "heff_flops",
+    "heff_plan_graph_count", "heff_vector_length", "heff_plan_chunks", "heff_plan_bytes",
+    "heff_plan_phase", "heff_flops",
     "heff_plan_destroy", "davidson_create", "davidson_step", "davidson_get_vector",
     "davidson_set_graphs", "davidson_graph_count", "davidson_destroy", "lanczos_create", "lanczos_step", "lanczos_get_vector", "lanczos_destroy",
     "rdm_eig_create", "rdm_eig_solve", "rdm_eig_destroy", "ozaki_renormalize_workspace_bytes",
@@ -255,6 +259,14 @@ class Context:
         -1 timed choice for the first phase when its items are short
         (default)."""
         _check(_lib.ozaki_ctx_set_heff_launch(self.handle, int(mode)), "ozaki_ctx_set_heff_launch")
+
+    def set_heff_phase(self, phase: int, variant: int = -1, order: int = 0, launch: int = 0):
+        """Fix grouped phase `phase` (0 first product, 1 second) of later
+        emulated heff plans: tile variant (-1 clears), order (0 XCD parts,
+        1 longest tile first), launch (0 per tile, k > 0 streamed on k CUs).
+        With both phases fixed a plan times nothing."""
+        _check(_lib.ozaki_ctx_set_heff_phase(self.handle, int(phase), int(variant), int(order), int(launch)),
+               "ozaki_ctx_set_heff_phase")
 
     def set_heff_budget(self, nbytes: int = 0):
         """Device bytes later heff plans may use for their intermediates T
@@ -520,6 +532,13 @@ class HeffPlan:
     @property
     def graph_count(self) -> int:
         return _check(_lib.heff_plan_graph_count(self.handle), "heff_plan_graph_count")
+
+    def phase(self, phase: int):
+        """(variant, order, launch) of grouped phase `phase` (0 or 1)."""
+        v, o, l = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(_lib.heff_plan_phase(self.handle, int(phase), ctypes.byref(v), ctypes.byref(o), ctypes.byref(l)),
+               "heff_plan_phase")
+        return v.value, o.value, l.value
 
     @property
     def chunks(self) -> int:

@@ -296,6 +296,30 @@ def test_chunked_plans_match(oz, S):
         ctx.set_heff_budget(0)
 
 
+def test_fixed_phase_choice(oz):
+    """A plan with both phases fixed to a timed plan's choice reports that
+    choice and gives the same bits; an unbuilt variant is rejected."""
+    ozaki, ctx, torch = oz
+    prob = small_sparse(29)
+    plan, dpsi, keep = sparse_plan(ozaki, ctx, torch, prob, 6)
+    want = (plan.phase(0), plan.phase(1))
+    ref = plan.apply(dpsi).cpu().numpy()
+    try:
+        for ph in (0, 1):
+            ctx.set_heff_phase(ph, *want[ph])
+        plan2, _, keep2 = sparse_plan(ozaki, ctx, torch, prob, 6)
+        assert (plan2.phase(0), plan2.phase(1)) == want
+        assert_bitexact(plan2.apply(dpsi).cpu().numpy(), ref, "fixed phases")
+        ctx.set_heff_phase(0, 2, 0, 0)   # 128 x 128 tiles are not built at G = 6
+        with pytest.raises(ozaki.OzakiError):
+            sparse_plan(ozaki, ctx, torch, prob, 6)
+        with pytest.raises(ozaki.OzakiError):
+            ctx.set_heff_phase(2, 0, 0, 0)
+    finally:
+        ctx.set_heff_phase(0, -1)
+        ctx.set_heff_phase(1, -1)
+
+
 def test_plan_argument_errors(oz):
     ozaki, ctx, torch = oz
     L, R, psi = wl.heff_dense(D=8, kop=2, phys=1, seed=0)
