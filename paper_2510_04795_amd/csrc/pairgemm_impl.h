@@ -561,6 +561,19 @@ __device__ __forceinline__ void emax_block(const OutDesc &out, const long long (
     }
 }
 
+// The row exponents of one 32 x 32 block's recombination (the lane's 16
+// values, rows i0 + 8 (r / 4) + r % 4), loaded together before it starts.
+// Inside the recombination every value is kept apart from the next (so
+// only one is live at a time), which would also wait for each of these
+// loads in turn.
+__device__ __forceinline__ void row_exponents(int32_t (&ei)[16], const int32_t *e, int M, int i0, bool jok) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int i = i0 + 8 * (r >> 2) + (r & 3);
+        ei[r] = (jok && i < M) ? e[i] : 0;
+    }
+}
+
 template <int S, int G, int WM, int WN, int MB, int NB, int MODE, bool EMAX = false, typename GetTerm>
 __device__ __forceinline__ void pair_tile(const PairArgs &a, GetTerm get_term, int tb, int te,
                                           const OutDesc &out, int m0, int n0, uint4 *lds0,
@@ -603,6 +616,9 @@ __device__ __forceinline__ void pair_tile(const PairArgs &a, GetTerm get_term, i
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb) {
                 long long w8[8], mlo = 0, keep = 0, got = 0;
+                int32_t ei[16];
+                if constexpr (MODE != kModeQ && MODE != kModeQ64)
+                    row_exponents(ei, T.e, out.M, m0 + (wm * MB + mb) * 32 + 4 * half, jok);
 #pragma unroll
                 for (int rr = 0; rr < 16; ++rr) {
                     // with the fused maxima, values q and 8 + q in turn
@@ -636,7 +652,7 @@ __device__ __forceinline__ void pair_tile(const PairArgs &a, GetTerm get_term, i
 #pragma unroll
                             for (int g = 0; g < G; ++g) q[g] += a.Qw[g * a.qw_plane + idx];
                         }
-                        const double c = horner<G>(q, T.e[i], fj);
+                        const double c = horner<G>(q, ei[r], fj);
                         if (MODE == kModeGemm) {
                             double *p = out.C + static_cast<int64_t>(i) * out.ldc + j;
                             const double v = (a.beta == 0.0) ? T.alpha * c : fma(T.alpha, c, a.beta * *p);
@@ -888,6 +904,8 @@ __device__ __forceinline__ void stream_tiles(const PairArgs &a, GetTerm get_term
                 for (int mb = 0; mb < MB; ++mb) {
                     constexpr bool EMAX = MODE == kModeGemm;
                     long long w8[8], mlo = 0, keep = 0, got = 0;
+                    int32_t ei[16];
+                    row_exponents(ei, T.e, od.M, m0 + (wm * MB + mb) * 32 + 4 * half, jok);
 #pragma unroll
                     for (int rr = 0; rr < 16; ++rr) {
                         const int r = EMAX ? ((rr & 1) ? 8 + (rr >> 1) : (rr >> 1)) : rr;
@@ -898,7 +916,7 @@ __device__ __forceinline__ void stream_tiles(const PairArgs &a, GetTerm get_term
                             long long q[G];
 #pragma unroll
                             for (int g = 0; g < G; ++g) q[g] = acc[g][mb][nb][r];
-                            const double c = horner<G>(q, T.e[i], fj);
+                            const double c = horner<G>(q, ei[r], fj);
                             if (MODE == kModeGemm) {
                                 double *p = od.C + static_cast<int64_t>(i) * od.ldc + j;
                                 const double v = (a.beta == 0.0) ? T.alpha * c : fma(T.alpha, c, a.beta * *p);
