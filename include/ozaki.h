@@ -233,7 +233,8 @@ int ozaki_ctx_set_heff_budget(ozaki_ctx ctx, size_t bytes);
 /* Fix the choice of one grouped phase (0 = first product, 1 = second) for
  * emulated heff plans created afterwards: tile variant (see
  * ozaki_pair_variants; < 0 clears the fix), tile order (0 = cost-balanced
- * contiguous parts per XCD, 1 = longest tile first) and launch (0 = one
+ * contiguous parts per XCD, 1 = longest tile first, 2 = whole outputs to
+ * the least loaded XCD, heaviest first) and launch (0 = one
  * workgroup per tile, k > 0 = streamed on k compute units).  With both
  * phases fixed a plan times nothing, which reproduces a timed plan's choice
  * (heff_plan_phase) exactly, e.g. for profiling.  OZ_ERR_ARG for an unknown
@@ -352,7 +353,8 @@ int heff_plan_launches(heff_plan plan, int32_t *first, int32_t *second);
 /* Total elements of psi for the plan's layout. */
 int64_t heff_vector_length(heff_plan plan);
 /* The choice of grouped phase `phase` (0 = first product, 1 = second) in an
- * emulated plan: tile variant, order (0 XCD parts, 1 longest tile first) and
+ * emulated plan: tile variant, order (0 XCD parts, 1 longest tile first,
+ * 2 whole outputs per XCD) and
  * launch (0 one workgroup per tile, k > 0 streamed on k CUs); all -1 for a
  * native FP64 plan. */
 int heff_plan_phase(heff_plan plan, int phase, int32_t *variant, int32_t *order, int32_t *launch);

@@ -223,6 +223,43 @@ void xcd_order(std::vector<std::vector<TileWork>> &outputs, std::vector<TileDesc
         }
 }
 
+// Whole outputs to XCDs, heaviest first, each to the XCD with the least
+// cost so far (longest processing time first); every XCD walks the tiles of
+// its outputs in that order.  The tiles of one output then run side by side
+// on one XCD and share its L2 (their row and column panels), while the XCDs
+// stay balanced to within one output.
+void output_lpt_order(const std::vector<std::vector<TileWork>> &outputs, std::vector<TileDesc> *out,
+                      std::vector<int64_t> *cost) {
+    std::vector<int64_t> oc(outputs.size(), 0);
+    std::vector<size_t> idx;
+    for (size_t i = 0; i < outputs.size(); ++i) {
+        for (auto &t : outputs[i]) oc[i] += t.cost;
+        if (!outputs[i].empty()) idx.push_back(i);
+    }
+    std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return oc[a] > oc[b]; });
+    std::vector<std::vector<TileWork>> part(kXcds);
+    std::vector<int64_t> load(kXcds, 0);
+    for (size_t i : idx) {
+        const size_t x = static_cast<size_t>(std::min_element(load.begin(), load.end()) - load.begin());
+        part[x].insert(part[x].end(), outputs[i].begin(), outputs[i].end());
+        load[x] += oc[i];
+    }
+    size_t longest = 0;
+    for (auto &p : part) longest = std::max(longest, p.size());
+    out->clear();
+    cost->clear();
+    for (size_t i = 0; i < longest; ++i)
+        for (auto &p : part) {
+            if (i < p.size()) {
+                out->push_back(p[i].td);
+                cost->push_back(p[i].cost);
+            } else {
+                out->push_back(TileDesc{0, 0, 0, 0, -1, 0});
+                cost->push_back(0);
+            }
+        }
+}
+
 }  // namespace
 
 extern "C" {
@@ -652,8 +689,10 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
         if ((rc = upload(P, zq, &ch.argsL.queue)) || (rc = upload(P, zq, &ch.argsR.queue))) { free_plan(P); return rc; }
     }
 
-    // tile lists of chunk c per variant, in XCD order (xcd) or longest tile first
-    auto tiles_for = [&](size_t c, int v, bool xcd, std::vector<TileDesc> *tl, std::vector<TileDesc> *tr,
+    // tile lists of chunk c per variant, in order 0 (XCD parts of equal
+    // cost), 1 (longest tile first) or 2 (whole outputs to XCDs, heaviest
+    // first to the least loaded)
+    auto tiles_for = [&](size_t c, int v, int order, std::vector<TileDesc> *tl, std::vector<TileDesc> *tr,
                          std::vector<int64_t> *cl, std::vector<int64_t> *cr) {
         const HostLists &x = hl[c];
         const PairShape sh = pair_shape(S, G, v);
@@ -674,12 +713,15 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
                                          static_cast<int32_t>(q), 0}, cst};
             }, &wr[q]);
         }
-        if (xcd) {
+        if (order == 0) {
             xcd_order(wl, tl, cl);
             xcd_order(wr, tr, cr);
-        } else {
+        } else if (order == 1) {
             longest_first(wl, tl, cl);
             longest_first(wr, tr, cr);
+        } else {
+            output_lpt_order(wl, tl, cl);
+            output_lpt_order(wr, tr, cr);
         }
     };
 
@@ -716,7 +758,7 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
     // candidates: tile variant x tile order (the XCD order first, the
     // default) x launch (one workgroup per tile, or the streamed kernel whose
     // resident workgroups walk the list and prefetch across items)
-    struct Run { int v; bool xcd; bool stream; };
+    struct Run { int v; int order; bool stream; };
     constexpr double kStreamMaxMeanBlocks = 16.0;
     std::vector<Run> runs;
     std::vector<bool> launches;
@@ -724,9 +766,9 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
     else if (tuning) launches = {false, true};
     else launches.push_back(false);
     for (int v : cands)
-        for (bool xcd : {true, false}) {
-            if (!xcd && !tuning) break;
-            for (bool st : launches) runs.push_back({v, xcd, st});
+        for (int order : {0, 1, 2}) {
+            if (order > 0 && !tuning) break;
+            for (bool st : launches) runs.push_back({v, order, st});
         }
     Run chosenL = runs.front(), chosenR = runs.front();
     int32_t last_key = -1;  // tile lists are built once per (variant, order) and shared by both launches
@@ -752,12 +794,12 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
         runs.clear();
         const int32_t cus[2] = {ctx->heff_fix[0][2] > 0 ? std::min(ctx->heff_fix[0][2], ctx->num_cu) : 0,
                                 ctx->heff_fix[1][2] > 0 ? std::min(ctx->heff_fix[1][2], ctx->num_cu) : 0};
-        chosenL = Run{ctx->heff_fix[0][0], ctx->heff_fix[0][1] == 0, cus[0] > 0};
-        chosenR = Run{ctx->heff_fix[1][0], ctx->heff_fix[1][1] == 0, cus[1] > 0};
+        chosenL = Run{ctx->heff_fix[0][0], ctx->heff_fix[0][1], cus[0] > 0};
+        chosenR = Run{ctx->heff_fix[1][0], ctx->heff_fix[1][1], cus[1] > 0};
         std::vector<TileDesc> l1, r1, l2, r2;
         std::vector<int64_t> cl1, cr1, cl2, cr2;
-        tiles_for(0, chosenL.v, chosenL.xcd, &l1, &r1, &cl1, &cr1);
-        tiles_for(0, chosenR.v, chosenR.xcd, &l2, &r2, &cl2, &cr2);
+        tiles_for(0, chosenL.v, chosenL.order, &l1, &r1, &cl1, &cr1);
+        tiles_for(0, chosenR.v, chosenR.order, &l2, &r2, &cl2, &cr2);
         if ((rc = upload(P, l1, &dtl)) || (rc = upload(P, r2, &dtr))) { free_plan(P); return rc; }
         c0.argsL.tiles = dtl; c0.argsL.ntiles = static_cast<int32_t>(l1.size()); c0.argsL.stream_cus = cus[0];
         c0.argsR.tiles = dtr; c0.argsR.ntiles = static_cast<int32_t>(r2.size()); c0.argsR.stream_cus = cus[1];
@@ -766,14 +808,15 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
     }
     for (auto run : runs) {
         const int v = run.v;
-        const bool xcd = run.xcd, st = run.stream;
-        const int32_t key = v * 2 + (xcd ? 1 : 0);
+        const int order = run.order;
+        const bool st = run.stream;
+        const int32_t key = v * 3 + order;
         if (key != last_key) {
             tl.clear();
             tr.clear();
             cl.clear();
             cr.clear();
-            tiles_for(0, v, xcd, &tl, &tr, &cl, &cr);
+            tiles_for(0, v, order, &tl, &tr, &cl, &cr);
             if ((rc = upload(P, tl, &dtl)) || (rc = upload(P, tr, &dtr))) { if (tmp_sigma) hipFree(tmp_sigma); if (tmp_tiles) hipFree(tmp_tiles); free_plan(P); return rc; }
             ntl = static_cast<int32_t>(tl.size());
             ntr = static_cast<int32_t>(tr.size());
@@ -866,18 +909,18 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
                                         hipMemcpyHostToDevice)) != hipSuccess) { free_plan(P); return hip_fail(e, "heff_plan_create: reset"); }
     }
     P->choice[0][0] = P->varL;
-    P->choice[0][1] = chosenL.xcd ? 0 : 1;
+    P->choice[0][1] = chosenL.order;
     P->choice[0][2] = c0.argsL.stream_cus;
     P->choice[1][0] = P->varR;
-    P->choice[1][1] = chosenR.xcd ? 0 : 1;
+    P->choice[1][1] = chosenR.order;
     P->choice[1][2] = c0.argsR.stream_cus;
     // the other chunks take the first chunk's choice per phase
     for (size_t c = 1; c < hc.size(); ++c) {
         HeffChunk &ch = P->chunks[c];
         std::vector<TileDesc> l1, r1, l2, r2;
         std::vector<int64_t> cl1, cr1, cl2, cr2;
-        tiles_for(c, chosenL.v, chosenL.xcd, &l1, &r1, &cl1, &cr1);
-        tiles_for(c, chosenR.v, chosenR.xcd, &l2, &r2, &cl2, &cr2);
+        tiles_for(c, chosenL.v, chosenL.order, &l1, &r1, &cl1, &cr1);
+        tiles_for(c, chosenR.v, chosenR.order, &l2, &r2, &cl2, &cr2);
         TileDesc *d1, *d2;
         if ((rc = upload(P, l1, &d1)) || (rc = upload(P, r2, &d2))) { free_plan(P); return rc; }
         ch.argsL.tiles = d1; ch.argsL.ntiles = static_cast<int32_t>(l1.size()); ch.argsL.stream_cus = c0.argsL.stream_cus;

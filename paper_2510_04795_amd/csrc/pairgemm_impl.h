@@ -128,6 +128,26 @@ struct LoadPlan {
     }
 };
 
+typedef __attribute__((address_space(4))) const TermDesc ConstTermDesc;
+
+// Term i of a list that does not change during the launch, read through the
+// constant address space so the reads go to scalar registers (a vector load
+// would have to wait for every load into LDS issued before it).
+__device__ __forceinline__ TermDesc const_term(const TermDesc *list, int i) {
+    const ConstTermDesc *c = (const ConstTermDesc *)reinterpret_cast<uintptr_t>(list + i);
+    TermDesc t;
+    t.A = c->A;
+    t.e = c->e;
+    t.B = c->B;
+    t.f = c->f;
+    t.a_rows_p = c->a_rows_p;
+    t.b_rows_p = c->b_rows_p;
+    t.kblocks = c->kblocks;
+    t.pad_ = 0;
+    t.alpha = c->alpha;
+    return t;
+}
+
 // Operand fragments of one stage for one wave: every slice that meets a
 // kept pair, for the wave's MB row blocks (A) and NB column blocks (B).
 // Each fragment is one 16-byte LDS read per lane (a 1 KiB run).
@@ -592,14 +612,23 @@ __device__ __forceinline__ void pair_tile(const PairArgs &a, GetTerm get_term, i
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
-            for (int r = 0; r < SIG; ++r) {
-                sig[mb][nb][r] = 0.0;
-                if (MODE == kModeAccum && out.cont) {
+            for (int r = 0; r < SIG; ++r) sig[mb][nb][r] = 0.0;
+    if (MODE == kModeAccum && out.cont) {
+        // continuing an earlier launch's sums: straight-line loads (outside
+        // the output, of its first element; the value is then dropped)
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                for (int r = 0; r < SIG; ++r) {
                     const int i = m0 + (wm * MB + mb) * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
                     const int j = n0 + (wn * NB + nb) * 32 + l32;
-                    if (i < out.M && j < out.N) sig[mb][nb][r] = out.C[static_cast<int64_t>(i) * out.ldc + j];
+                    const bool ok = i < out.M && j < out.N;
+                    const double v = out.C[ok ? static_cast<int64_t>(i) * out.ldc + j : 0];
+                    sig[mb][nb][r] = ok ? v : 0.0;
                 }
-            }
+    }
 
     // only the accumulating mode sums several terms into one tile
     const int tend = (MODE == kModeAccum) ? te : tb + 1;
@@ -1019,8 +1048,9 @@ __global__ __launch_bounds__(64 * WM * WN) void k_pair_grouped(PairArgs a) {
     OutDesc od = a.outs[td.out];
     if (a.out_base) od.C = a.out_base + reinterpret_cast<intptr_t>(od.C);
     const TermDesc *terms = a.terms;
-    pair_tile<S, G, WM, WN, MB, NB, MODE, MODE == kModeGemm>(a, [&](int i) { return terms[i]; }, td.term_begin,
-                                                            td.term_end, od, td.m0, td.n0, lds0, lds1, lds2);
+    pair_tile<S, G, WM, WN, MB, NB, MODE, MODE == kModeGemm>(a, [&](int i) { return const_term(terms, i); },
+                                                            td.term_begin, td.term_end, od, td.m0, td.n0, lds0,
+                                                            lds1, lds2);
 }
 
 // Per-(S, G) tile shape: as wide as the accumulators allow.

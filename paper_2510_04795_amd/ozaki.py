@@ -263,7 +263,8 @@ class Context:
     def set_heff_phase(self, phase: int, variant: int = -1, order: int = 0, launch: int = 0):
         """Fix grouped phase `phase` (0 first product, 1 second) of later
         emulated heff plans: tile variant (-1 clears), order (0 XCD parts,
-        1 longest tile first), launch (0 per tile, k > 0 streamed on k CUs).
+        1 longest tile first, 2 whole outputs per XCD, heaviest first to the
+        least loaded), launch (0 per tile, k > 0 streamed on k CUs).
         With both phases fixed a plan times nothing."""
         _check(_lib.ozaki_ctx_set_heff_phase(self.handle, int(phase), int(variant), int(order), int(launch)),
                "ozaki_ctx_set_heff_phase")

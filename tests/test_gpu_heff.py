@@ -320,6 +320,28 @@ def test_fixed_phase_choice(oz):
         ctx.set_heff_phase(1, -1)
 
 
+@pytest.mark.parametrize("order", [0, 1, 2])
+def test_tile_orders_bitexact(oz, order):
+    """Every tile order (XCD parts, longest first, whole outputs per XCD),
+    per tile and streamed: the oracle's bits (the order moves tiles between
+    workgroups, never the arithmetic of one)."""
+    ozaki, ctx, torch = oz
+    prob = small_sparse(31)
+    ref = oracle.heff_sparse(prob, S=6)
+    try:
+        for (vl, ll), (vr, lr) in [((3, 0), (4, 0)), ((0, 7), (3, 0)), ((4, 0), (0, 0))]:
+            ctx.set_heff_phase(0, vl, order, ll)
+            ctx.set_heff_phase(1, vr, order, lr)
+            plan, dpsi, keep = sparse_plan(ozaki, ctx, torch, prob, 6)
+            assert plan.phase(0) == (vl, order, ll) and plan.phase(1) == (vr, order, lr)
+            sig = wl.unflatten_sparse(prob, plan.apply(dpsi).cpu().numpy())
+            for b in prob.psi_blocks:
+                assert_bitexact(sig[b], ref[b], "order %d L %d R %d block %s" % (order, vl, vr, b))
+    finally:
+        ctx.set_heff_phase(0, -1)
+        ctx.set_heff_phase(1, -1)
+
+
 def test_plan_argument_errors(oz):
     ozaki, ctx, torch = oz
     L, R, psi = wl.heff_dense(D=8, kop=2, phys=1, seed=0)
@@ -352,6 +374,35 @@ def test_plan_variants_bitexact(oz):
     plan, dpsi, keep = sparse_plan(ozaki, ctx, torch, prob, 6)
     built = [x[0] for x in ozaki.pair_variants(6)]
     assert plan.variants[0] in built and plan.variants[1] in built
+
+
+@pytest.mark.parametrize("S,G,seed", [(6, 6, 76), (4, 4, 84), (5, 6, 82)])
+def test_accumulating_many_short_terms(oz, S, G, seed):
+    """The accumulating phase on the 8-wave tiles (three-stage ring) with
+    sectors of 1 to 100 states (terms of 1 to 4 K blocks) and about ten
+    terms per sigma block, one workgroup per tile, in one chunk and in
+    chunks that continue a tile's sums: the oracle's bits."""
+    ozaki, ctx, torch = oz
+    prob = wl.heff_sparse(n_sectors=8, n_triples=400, kop=8, median=30, sigma_log=1.0,
+                          lo_hi=(1, 100), density=0.6, reach=7, U=8, seed=seed)
+    assert prob.dims.min() <= 8 and prob.dims.max() > 64
+    ref = oracle.heff_sparse(prob, S=S, G=G)
+    ctx.set_heff_launch(0)
+    try:
+        for v in (3, 4):
+            ctx.set_variant(S, G, v)
+            for budget in (0, 1):
+                ctx.set_heff_budget(budget)
+                plan, dpsi, keep = sparse_plan(ozaki, ctx, torch, prob, S, G)
+                assert plan.variants == (v, v) and plan.launches == (0, 0)
+                assert (plan.chunks > 1) == (budget == 1)
+                sig = wl.unflatten_sparse(prob, plan.apply(dpsi).cpu().numpy())
+                for b in prob.psi_blocks:
+                    assert_bitexact(sig[b], ref[b], "variant %d budget %d block %s" % (v, budget, b))
+    finally:
+        ctx.set_heff_budget(0)
+        ctx.set_variant(S, G, -1)
+        ctx.set_heff_launch(-1)
 
 
 @pytest.mark.parametrize("cus", [1, 3, 100000])
