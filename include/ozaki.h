@@ -385,7 +385,8 @@ int heff_plan_destroy(heff_plan plan);
  * (davidson_create issues the first), so a step reads (theta, rho) from a
  * pinned buffer, decides, and, when it continues, issues the correction,
  * the basis update, the matvec and the next Rayleigh-Ritz solve as one
- * replay of a graph captured per (basis size, Ritz buffer), then
+ * replay of a graph captured per Ritz buffer (two in all: the basis size
+ * lives on the device and the matvec runs on fixed buffers), then
  * synchronises once.  Replayed and directly issued steps give the same
  * bits.  Phase timing (ozaki_ctx_set_timing) issues the launches directly.
  * davidson_get_vector copies the Ritz vector of the theta the last step
