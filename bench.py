@@ -648,13 +648,19 @@ def device_record(torch):
 def cpu_baseline(oracle, A, B, S, G, seconds):
     """The oracle's emulated GEMM at the chosen (S, G) on a bounded sample of
     rows of A (all of B), sized from a probe so that the timed run takes about
-    ``seconds``; the rate is scaled as 2 * rows * n^2 / time."""
+    ``seconds`` (the per-call slicing of B and the per-row cost estimated from
+    two probes); the rate is scaled as 2 * rows * n^2 / time."""
     n = A.shape[0]
-    probe = sampled_rows(n, 8, seed=2)
-    t0 = time.perf_counter()
-    oracle.ozaki_dgemm(A[probe], B, S, G)
-    per_row = (time.perf_counter() - t0) / len(probe)
-    count = int(min(max(seconds / max(per_row, 1e-9), 8), n))
+    # two probes separate the per-call cost (slicing all of B) from the per-row cost
+    tp = []
+    for k in (8, 24):
+        probe = sampled_rows(n, k, seed=2)
+        t0 = time.perf_counter()
+        oracle.ozaki_dgemm(A[probe], B, S, G)
+        tp.append(time.perf_counter() - t0)
+    per_row = max((tp[1] - tp[0]) / 16, tp[1] / 24 / 4, 1e-9)
+    fixed = max(tp[0] - 8 * per_row, 0.0)
+    count = int(min(max((seconds - fixed) / per_row, 8), n))
     rows = sampled_rows(n, count, seed=2)
     t0 = time.perf_counter()
     oracle.ozaki_dgemm(A[rows], B, S, G)

@@ -494,15 +494,17 @@ __host__ __device__ constexpr bool use_prefetch() {
 
 // The ring of three stages where its conditions hold: one 32 x 32 block per
 // wave; 8 waves (the workgroup holds its compute unit alone anyway), or 4
-// waves whose registers already allow only one wave per SIMD (more than
-// 128 each, so one workgroup per compute unit and the third stage costs no
-// occupancy); three stages within 156 KiB of LDS and the register budget
-// (with 24 registers more in hand for the accumulating mode, whose term
-// loop keeps more live: at S = G = 7 it spills without them).
+// waves whose registers (more than 128 each) allow at most two workgroups
+// per compute unit anyway and whose three stages still let two fit in LDS
+// (S <= 6; from S = 7 the third stage would halve the occupancy, which
+// measured slower); three stages within 156 KiB of LDS and the register
+// budget (with 24 registers more in hand for the accumulating mode, whose
+// term loop keeps more live: at S = G = 7 it spills without them).
 template <int S, int G, int WM, int WN, int MB, int NB, int MODE>
 __host__ __device__ constexpr bool use_ring() {
     return AsmStep<S, G>::available && MB == 1 && NB == 1 &&
-           (WM * WN == 8 || (WM * WN == 4 && wave_budget_left<S, G, WM, WN, MB, NB, MODE>(1, 4) < 128)) &&
+           (WM * WN == 8 || (WM * WN == 4 && wave_budget_left<S, G, WM, WN, MB, NB, MODE>(1, 4) < 128 &&
+                             6 * Cfg<S, G, WM, WN, MB, NB>::STAGE_BYTES <= 160 * 1024)) &&
            3 * Cfg<S, G, WM, WN, MB, NB>::STAGE_BYTES <= 156 * 1024 &&
            wave_budget_left<S, G, WM, WN, MB, NB, MODE>(1, 4) >= (MODE == kModeAccum ? 24 : 0);
 }
