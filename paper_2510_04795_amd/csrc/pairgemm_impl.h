@@ -476,6 +476,69 @@ __device__ __forceinline__ void pair_mainloop_ring(v16i (&acc)[G][MB][NB], uint4
     asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 7" ::: "memory");
 }
 
+template <int S, int G, int WM, int WN, int MB, int NB, typename F, typename LP>
+__device__ __forceinline__ void ring_step2(v16i (&acc)[G][MB][NB], F &cur, uint4 *fill, const uint4 *rd,
+                                           const LP &lp, int kb, int nkb, int wm, int wn, int half, int l32) {
+    using C = Cfg<S, G, WM, WN, MB, NB>;
+    using RA = RingAddr<S, G, WM, WN, MB, NB>;
+    if (kb + 1 < nkb) {
+        __builtin_amdgcn_s_waitcnt(C::WAIT_ALL);
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        if (kb + 2 < nkb) lp.issue(fill, kb + 2);
+    }
+    AsmStep<S, G>::template run<RA::OA, RA::OB>(acc, cur, RA::a(rd, wm, half, l32), RA::b(rd, wn, half, l32));
+}
+
+// The ring's steps with two stages (loads one block ahead), for the 4-wave
+// tiles where a third stage would leave room for only one workgroup per
+// compute unit (S >= 7): the second resident workgroup covers the shorter
+// lead.
+template <int S, int G, int WM, int WN, int MB, int NB>
+__device__ __forceinline__ void pair_mainloop_ring2(v16i (&acc)[G][MB][NB], uint4 *lds0, uint4 *lds1,
+                                                    const TermDesc &T, int m0, int n0) {
+    using C = Cfg<S, G, WM, WN, MB, NB>;
+    using RA = RingAddr<S, G, WM, WN, MB, NB>;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform per wave
+    const int wm = wave / WN;
+    const int wn = wave % WN;
+    const int half = lane >> 5;
+    const int l32 = lane & 31;
+    const int nkb = T.kblocks;
+
+#pragma unroll
+    for (int g = 0; g < G; ++g) acc[g][0][0] = v16i{};
+    if (nkb == 0) return;
+
+    LoadPlan<S, G, WM, WN, MB, NB> lp;
+    lp.init(T.A, T.B, T.a_rows_p, T.b_rows_p, m0, n0, wave, lane);
+    // a previous term of this block (accumulating mode) may still read the stages
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    lp.issue(lds0, 0);
+    if (1 < nkb) lp.issue(lds1, 1);
+    if (1 < nkb)
+        __builtin_amdgcn_s_waitcnt(C::WAIT_NEWEST);
+    else
+        __builtin_amdgcn_s_waitcnt(C::WAIT_ALL);
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    Frags<S, G, MB, NB> f;
+    AsmStep<S, G>::template read<RA::OA, RA::OB>(f, RA::a(lds0, wm, half, l32), RA::b(lds0, wn, half, l32));
+    // step kb: wait for block kb + 1 (the only load in flight), barrier,
+    // loads of block kb + 2 into block kb's stage, then block kb's MFMAs with
+    // block kb + 1's fragment reads
+    int kb = 0;
+    for (; kb + 2 <= nkb; kb += 2) {
+        ring_step2<S, G, WM, WN, MB, NB>(acc, f, lds0, lds1, lp, kb, nkb, wm, wn, half, l32);
+        ring_step2<S, G, WM, WN, MB, NB>(acc, f, lds1, lds0, lp, kb + 1, nkb, wm, wn, half, l32);
+    }
+    if (kb < nkb) ring_step2<S, G, WM, WN, MB, NB>(acc, f, lds0, lds1, lp, kb, nkb, wm, wn, half, l32);
+    asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 7" ::: "memory");
+}
+
 // Registers of one wave: accumulators, fragments, the running sigma of the
 // accumulating mode and about 24 for addresses and counters, within 256 per
 // wave at two waves per SIMD (128 at four).  The prefetching loop holds two
@@ -509,12 +572,26 @@ __host__ __device__ constexpr bool use_ring() {
            wave_budget_left<S, G, WM, WN, MB, NB, MODE>(1, 4) >= (MODE == kModeAccum ? 24 : 0);
 }
 
+// The two-stage ring: the 4-wave tiles the three-stage ring leaves out
+// because a third stage would halve their occupancy (S >= 7), where the
+// registers (more than 128 per wave) allow two workgroups per compute unit
+// and their two stages fit in LDS twice.
+template <int S, int G, int WM, int WN, int MB, int NB, int MODE>
+__host__ __device__ constexpr bool use_ring2() {
+    return !use_ring<S, G, WM, WN, MB, NB, MODE>() && AsmStep<S, G>::available && MB == 1 && NB == 1 &&
+           WM * WN == 4 && wave_budget_left<S, G, WM, WN, MB, NB, MODE>(1, 4) < 128 &&
+           4 * Cfg<S, G, WM, WN, MB, NB>::STAGE_BYTES <= 160 * 1024 &&
+           wave_budget_left<S, G, WM, WN, MB, NB, MODE>(1, 4) >= (MODE == kModeAccum ? 24 : 0);
+}
+
 // Exact diagonal sums of one tile for one term, accumulated over all K blocks.
 template <int S, int G, int WM, int WN, int MB, int NB, int MODE>
 __device__ __forceinline__ void pair_mainloop(v16i (&acc)[G][MB][NB], uint4 *lds0, uint4 *lds1, uint4 *lds2,
                                               const TermDesc &T, int m0, int n0) {
     if constexpr (use_ring<S, G, WM, WN, MB, NB, MODE>())
         pair_mainloop_ring<S, G, WM, WN, MB, NB>(acc, lds0, lds1, lds2, T, m0, n0);
+    else if constexpr (use_ring2<S, G, WM, WN, MB, NB, MODE>())
+        pair_mainloop_ring2<S, G, WM, WN, MB, NB>(acc, lds0, lds1, T, m0, n0);
     else if constexpr (use_prefetch<S, G, WM, WN, MB, NB, MODE>())
         pair_mainloop_prefetch<S, G, WM, WN, MB, NB>(acc, lds0, lds1, T, m0, n0);
     else
