@@ -598,6 +598,11 @@ __device__ __forceinline__ void pair_mainloop(v16i (&acc)[G][MB][NB], uint4 *lds
         pair_mainloop_direct<S, G, WM, WN, MB, NB>(acc, lds0, lds1, T, m0, n0);
 }
 
+// Output elements whose recombinations the epilogue lets the scheduler
+// interleave (their dependent FP64 chains overlap); a schedule barrier
+// between groups keeps the registers of only one group live.
+constexpr int kEpilogueGroup = 4;
+
 // FP64 value of one output element from its diagonal sums (plus int64 carries).
 template <int G>
 __device__ __forceinline__ double horner(const long long (&q)[G], int32_t ei, int32_t fj) {
@@ -734,8 +739,8 @@ __device__ __forceinline__ void pair_tile(const PairArgs &a, GetTerm get_term, i
                 for (int rr = 0; rr < 16; ++rr) {
                     // with the fused maxima, values q and 8 + q in turn
                     const int r = EMAX ? ((rr & 1) ? 8 + (rr >> 1) : (rr >> 1)) : rr;
-                    // keep one element's recombination at a time in registers
-                    __builtin_amdgcn_sched_barrier(0);
+                    // keep kEpilogueGroup elements' recombinations at a time in registers
+                    if (rr % kEpilogueGroup == 0) __builtin_amdgcn_sched_barrier(0);
                     const int i = m0 + (wm * MB + mb) * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
                     const bool ok = jok && i < out.M;
                     long long mag = 0;
@@ -1020,7 +1025,7 @@ __device__ __forceinline__ void stream_tiles(const PairArgs &a, GetTerm get_term
 #pragma unroll
                     for (int rr = 0; rr < 16; ++rr) {
                         const int r = EMAX ? ((rr & 1) ? 8 + (rr >> 1) : (rr >> 1)) : rr;
-                        __builtin_amdgcn_sched_barrier(0);
+                        if (rr % kEpilogueGroup == 0) __builtin_amdgcn_sched_barrier(0);
                         const int i = m0 + (wm * MB + mb) * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
                         long long mag = 0;
                         if (jok && i < od.M) {
