@@ -1,6 +1,6 @@
 // Host-only stand-ins for the per-S pair-GEMM entry points of
 // csrc/pairgemm_s{2..8}.hip, so the sanitizer build of the host code
-// (tests/test_sanitizers.py) skips compiling those kernels.  The driver never
+// (tests/test_sanitizers.py) skips compiling those kernels.  The test program never
 // reaches a launch; a call here reports an invalid value.
 #include <hip/hip_runtime.h>
 
