@@ -213,14 +213,25 @@ int ozaki_ctx_get_variant(ozaki_ctx ctx, int slices, int ndiag);
  * keeps the fastest (default on; a variant fixed with ozaki_ctx_set_variant
  * takes precedence). */
 int ozaki_ctx_set_autotune(ozaki_ctx ctx, int enable);
+/* Launch code of the resident kernel (ozaki_ctx_set_heff_launch,
+ * ozaki_ctx_set_heff_phase, heff_plan_phase). */
+#define OZ_HEFF_LAUNCH_RESIDENT (-2)
 /* How heff plans created afterwards launch their two grouped pair phases:
  * 0 = one workgroup per output tile; k > 0 = the streamed kernel, in which
  * as many workgroups as fit at once on min(k, number of CUs) compute units
  * walk the tile list and the first K block of each (tile, term) item is
- * loaded during the last block of the item before it; -1 (default) = when
- * autotuning is on, time both for the first phase if its items average at
- * most 16 K blocks (the streamed kernel saves a fixed cost per item), else 0.
- * Results are bit-identical in every mode.  OZ_ERR_ARG for mode < -1. */
+ * loaded during the last block of the item before it;
+ * OZ_HEFF_LAUNCH_RESIDENT = the first phase on the resident kernel where it
+ * is built for the tile variant (one 32 x 32 block per wave on the
+ * three-stage LDS ring), the second one workgroup per tile: a grid that
+ * fits on the device at once, each workgroup walking its part of a
+ * schedule the plan balances by cost, the K blocks of its consecutive tiles
+ * streamed through one ring (a tile's first blocks load during the
+ * previous tile's last blocks and epilogue); -1 (default) = when
+ * autotuning is on, time the first phase one workgroup per tile, streamed
+ * (if its items average at most 16 K blocks) and resident (where built),
+ * the second one workgroup per tile; else 0.  Results are bit-identical in
+ * every mode.  OZ_ERR_ARG for mode < -2. */
 int ozaki_ctx_set_heff_launch(ozaki_ctx ctx, int mode);
 /* Device bytes that heff plans created afterwards may use for the
  * intermediates T_u = L psi of the first products (FP64 values, and their
@@ -235,11 +246,13 @@ int ozaki_ctx_set_heff_budget(ozaki_ctx ctx, size_t bytes);
  * ozaki_pair_variants; < 0 clears the fix), tile order (0 = cost-balanced
  * contiguous parts per XCD, 1 = longest tile first, 2 = whole outputs to
  * the least loaded XCD, heaviest first) and launch (0 = one
- * workgroup per tile, k > 0 = streamed on k compute units).  With both
+ * workgroup per tile, k > 0 = streamed on k compute units,
+ * OZ_HEFF_LAUNCH_RESIDENT = the resident kernel, first phase only).  With both
  * phases fixed a plan times nothing, which reproduces a timed plan's choice
  * (heff_plan_phase) exactly, e.g. for profiling.  OZ_ERR_ARG for an unknown
  * phase, variant, order or launch; a variant not built for the plan's
- * (S, G) makes heff_plan_create fail with OZ_ERR_ARG. */
+ * (S, G), or a resident launch not built for it or asked for the second
+ * phase, makes heff_plan_create fail with OZ_ERR_ARG. */
 int ozaki_ctx_set_heff_phase(ozaki_ctx ctx, int phase, int variant, int order, int launch);
 /* Time every built variant of this GEMM (alpha = 1, beta = 0 into C, one
  * warm-up and three timed calls each) and fix the fastest for (slices,
@@ -348,15 +361,15 @@ int heff_plan_graph_count(heff_plan plan);
  * native FP64 plans). */
 int heff_plan_variants(heff_plan plan, int32_t *first, int32_t *second);
 /* Launch kind of the plan's two grouped phases (0 one workgroup per tile,
- * 1 streamed; -1 for native FP64 plans). */
+ * 1 streamed, 2 resident; -1 for native FP64 plans). */
 int heff_plan_launches(heff_plan plan, int32_t *first, int32_t *second);
 /* Total elements of psi for the plan's layout. */
 int64_t heff_vector_length(heff_plan plan);
 /* The choice of grouped phase `phase` (0 = first product, 1 = second) in an
  * emulated plan: tile variant, order (0 XCD parts, 1 longest tile first,
  * 2 whole outputs per XCD) and
- * launch (0 one workgroup per tile, k > 0 streamed on k CUs); all -1 for a
- * native FP64 plan. */
+ * launch (0 one workgroup per tile, k > 0 streamed on k CUs,
+ * OZ_HEFF_LAUNCH_RESIDENT resident); all -1 for a native FP64 plan. */
 int heff_plan_phase(heff_plan plan, int phase, int32_t *variant, int32_t *order, int32_t *launch);
 /* Number of chunks the plan's triple list runs in (ozaki_ctx_set_heff_budget). */
 int heff_plan_chunks(heff_plan plan);

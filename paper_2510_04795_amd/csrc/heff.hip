@@ -260,6 +260,41 @@ void output_lpt_order(const std::vector<std::vector<TileWork>> &outputs, std::ve
         }
 }
 
+constexpr int kHeffLaunchResident = OZ_HEFF_LAUNCH_RESIDENT;
+// workgroups per compute unit the resident schedules are built for, at most
+constexpr int kMaxResidentPerCu = 8;
+
+// The fixed cost of starting a tile in a resident schedule, in the tile
+// costs' unit (K blocks times the tile's area): about two K blocks.
+int64_t resident_start_cost(const PairShape &sh) { return 2 * static_cast<int64_t>(sh.bm) * sh.bn; }
+
+// Schedule of the resident kernel over a tile list: nwg workgroups, all on
+// the device at once, workgroup b on XCD b % 8.  Each listed tile goes to
+// the XCD its list position names (position p to XCD p % 8, as in the
+// launch with one workgroup per tile), there to the workgroup with the least
+// cost so far, in list order.  *out gets the tiles of workgroup 0, 1, ... in
+// order, *off the nwg + 1 offsets of their runs.
+void resident_schedule(const std::vector<TileDesc> &tl, const std::vector<int64_t> &cost, int nwg,
+                       int64_t start_cost, std::vector<TileDesc> *out, std::vector<int32_t> *off) {
+    std::vector<std::vector<TileDesc>> per(static_cast<size_t>(nwg));
+    std::vector<int64_t> load(static_cast<size_t>(nwg), 0);
+    for (size_t p = 0; p < tl.size(); ++p) {
+        if (tl[p].out < 0) continue;
+        int best = -1;
+        for (int b = static_cast<int>(p % kXcds); b < nwg; b += kXcds)
+            if (best < 0 || load[b] < load[best]) best = b;
+        if (best < 0) best = static_cast<int>(p % static_cast<size_t>(nwg));
+        per[best].push_back(tl[p]);
+        load[best] += cost[p] + start_cost;
+    }
+    out->clear();
+    off->assign(1, 0);
+    for (auto &v : per) {
+        out->insert(out->end(), v.begin(), v.end());
+        off->push_back(static_cast<int32_t>(out->size()));
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -735,7 +770,6 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
     // by the sample's share of the total cost; inputs are zeroed scratch (the
     // timing does not depend on the values).  Every chunk then uses the
     // choice per phase.
-    HeffChunk &c0 = P->chunks[0];
     double bestL = -1, bestR = -1;
     void *tmp_sigma = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -755,27 +789,40 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
         hipEventCreate(&ev0);
         hipEventCreate(&ev1);
     }
-    // candidates: tile variant x tile order (the XCD order first, the
-    // default) x launch (one workgroup per tile, or the streamed kernel whose
-    // resident workgroups walk the list and prefetch across items)
-    struct Run { int v; int order; bool stream; };
+    // Candidates: tile variant x tile order (the XCD order first, the
+    // default) x launch: one workgroup per tile; the streamed kernel, whose
+    // resident workgroups take tiles from counters and prefetch across
+    // items; or the resident kernel on a precomputed schedule (first phase
+    // only, for the variants it is built for), which streams the K blocks
+    // of consecutive tiles through one ring.
+    struct Run { int v; int order; int kind; int cus; };  // kind 0 per tile, 1 streamed (cus), 2 resident
     constexpr double kStreamMaxMeanBlocks = 16.0;
-    std::vector<Run> runs;
-    std::vector<bool> launches;
-    if (ctx->heff_launch >= 0) launches.push_back(ctx->heff_launch > 0);
-    else if (tuning) launches = {false, true};
-    else launches.push_back(false);
-    for (int v : cands)
-        for (int order : {0, 1, 2}) {
-            if (order > 0 && !tuning) break;
-            for (bool st : launches) runs.push_back({v, order, st});
+    const int forced = ctx->heff_launch;  // -1 timed, 0 per tile, k > 0 streamed, kHeffLaunchResident
+    const int stream_cus_of = forced > 0 ? std::min(forced, ctx->num_cu) : ctx->num_cu;
+    // the launches a phase may use for variant v
+    auto kinds_for = [&](int ph, int v) {
+        std::vector<int> k;
+        if (forced == kHeffLaunchResident) {
+            k.push_back(ph == 0 && pair_resident_per_cu(S, G, v) > 0 ? 2 : 0);
+        } else if (forced >= 0) {
+            k.push_back(forced > 0 ? 1 : 0);
+        } else {
+            k.push_back(0);
+            if (tuning && ph == 0) {
+                k.push_back(1);
+                if (pair_resident_per_cu(S, G, v) > 0) k.push_back(2);
+            }
         }
-    Run chosenL = runs.front(), chosenR = runs.front();
-    int32_t last_key = -1;  // tile lists are built once per (variant, order) and shared by both launches
-    TileDesc *dtl = nullptr, *dtr = nullptr;
-    std::vector<int64_t> cl, cr;
-    std::vector<TileDesc> tl, tr;
-    int32_t ntl = 0, ntr = 0;
+        return k;
+    };
+    Run chosenL{cands.front(), 0, 0, 0}, chosenR{cands.front(), 0, 0, 0};
+    {
+        const std::vector<int> kl = kinds_for(0, chosenL.v), kr = kinds_for(1, chosenR.v);
+        chosenL.kind = kl.front();
+        chosenR.kind = kr.front();
+        chosenL.cus = chosenL.kind == 1 ? stream_cus_of : 0;
+        chosenR.cus = chosenR.kind == 1 ? stream_cus_of : 0;
+    }
     // Timing sample: the equivalent of 64 tiles of 16 K blocks per CU, at
     // least 8 and at most 64 tiles per CU, as 8 windows of consecutive list
     // positions spread evenly over the list.  A window keeps the XCD order's
@@ -785,147 +832,184 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
     const size_t cap = static_cast<size_t>(64) * ctx->num_cu;
     const size_t floor_tiles = static_cast<size_t>(8) * ctx->num_cu;
     TileDesc *tmp_tiles = nullptr;
-    if (tuning && (e = hipMalloc(&tmp_tiles, sizeof(TileDesc) * (cap + 8))) != hipSuccess) {
+    int32_t *tmp_off = nullptr;
+    if (tuning && ((e = hipMalloc(&tmp_tiles, sizeof(TileDesc) * (cap + 8))) != hipSuccess ||
+                   (e = hipMalloc(&tmp_off, sizeof(int32_t) * (static_cast<size_t>(kMaxResidentPerCu) * ctx->num_cu + 1))) != hipSuccess)) {
         hipFree(tmp_sigma);
+        hipFree(tmp_tiles);
         free_plan(P);
         return hip_fail(e, "heff_plan_create: tuning buffer");
     }
+    auto free_tuning = [&]() {
+        if (tmp_sigma) hipFree(tmp_sigma);
+        if (tmp_tiles) hipFree(tmp_tiles);
+        if (tmp_off) hipFree(tmp_off);
+        tmp_sigma = nullptr;
+        tmp_tiles = nullptr;
+        tmp_off = nullptr;
+    };
     if (fixed_phases) {
-        runs.clear();
-        const int32_t cus[2] = {ctx->heff_fix[0][2] > 0 ? std::min(ctx->heff_fix[0][2], ctx->num_cu) : 0,
-                                ctx->heff_fix[1][2] > 0 ? std::min(ctx->heff_fix[1][2], ctx->num_cu) : 0};
-        chosenL = Run{ctx->heff_fix[0][0], ctx->heff_fix[0][1], cus[0] > 0};
-        chosenR = Run{ctx->heff_fix[1][0], ctx->heff_fix[1][1], cus[1] > 0};
-        std::vector<TileDesc> l1, r1, l2, r2;
-        std::vector<int64_t> cl1, cr1, cl2, cr2;
-        tiles_for(0, chosenL.v, chosenL.order, &l1, &r1, &cl1, &cr1);
-        tiles_for(0, chosenR.v, chosenR.order, &l2, &r2, &cl2, &cr2);
-        if ((rc = upload(P, l1, &dtl)) || (rc = upload(P, r2, &dtr))) { free_plan(P); return rc; }
-        c0.argsL.tiles = dtl; c0.argsL.ntiles = static_cast<int32_t>(l1.size()); c0.argsL.stream_cus = cus[0];
-        c0.argsR.tiles = dtr; c0.argsR.ntiles = static_cast<int32_t>(r2.size()); c0.argsR.stream_cus = cus[1];
-        P->varL = chosenL.v;
-        P->varR = chosenR.v;
-    }
-    for (auto run : runs) {
-        const int v = run.v;
-        const int order = run.order;
-        const bool st = run.stream;
-        const int32_t key = v * 3 + order;
-        if (key != last_key) {
-            tl.clear();
-            tr.clear();
-            cl.clear();
-            cr.clear();
-            tiles_for(0, v, order, &tl, &tr, &cl, &cr);
-            if ((rc = upload(P, tl, &dtl)) || (rc = upload(P, tr, &dtr))) { if (tmp_sigma) hipFree(tmp_sigma); if (tmp_tiles) hipFree(tmp_tiles); free_plan(P); return rc; }
-            ntl = static_cast<int32_t>(tl.size());
-            ntr = static_cast<int32_t>(tr.size());
-            last_key = key;
-        }
-        const int32_t scus = !st ? 0 : ctx->heff_launch > 0 ? std::min(ctx->heff_launch, ctx->num_cu) : ctx->num_cu;
-        if (!tuning) {
-            c0.argsL.tiles = dtl; c0.argsL.ntiles = ntl; P->varL = v; c0.argsL.stream_cus = scus;
-            c0.argsR.tiles = dtr; c0.argsR.ntiles = ntr; P->varR = v; c0.argsR.stream_cus = scus;
-            chosenL = chosenR = run;
-            break;
-        }
         for (int ph = 0; ph < 2; ++ph) {
-            const std::vector<int64_t> &cost = ph == 0 ? cl : cr;
-            int64_t total = 0, items = 0;
-            for (auto cc : cost) {
-                total += cc;
-                items += cc > 0;
+            const int l = ctx->heff_fix[ph][2];
+            Run &r = ph == 0 ? chosenL : chosenR;
+            r = Run{ctx->heff_fix[ph][0], ctx->heff_fix[ph][1], 0, 0};
+            if (l == kHeffLaunchResident) {
+                if (ph != 0 || pair_resident_per_cu(S, G, r.v) <= 0) {
+                    free_plan(P);
+                    return fail(OZ_ERR_ARG, "heff_plan_create: resident launch not built for phase %d, variant %d", ph, r.v);
+                }
+                r.kind = 2;
+            } else if (l > 0) {
+                r.kind = 1;
+                r.cus = std::min(l, ctx->num_cu);
             }
-            if (st && ctx->heff_launch < 0) {
-                // Timed choice: the streamed kernel saves a fixed cost per
-                // (tile, term) item (the first K block's load, the exposed
-                // epilogue), so it is a candidate for the GEMM-mode phase
-                // with short items only; in the accumulating phase it was
-                // slower at every measured shape.
-                const PairShape sh = pair_shape(S, G, v);
-                const double mean_kb = items ? static_cast<double>(total) / items / (sh.bm * sh.bn) : 0.0;
-                if (ph == 1 || mean_kb > kStreamMaxMeanBlocks) continue;
-            }
-            const std::vector<TileDesc> &list = ph == 0 ? tl : tr;
-            PairArgs a = ph == 0 ? c0.argsL : c0.argsR;
-            const PairShape shp = pair_shape(S, G, v);
-            const double blocks_per_tile = items ? static_cast<double>(total) / items / (shp.bm * shp.bn) : 1.0;
-            const size_t n_sample = std::min(cap, std::max(floor_tiles, static_cast<size_t>(16.0 * cap / std::max(blocks_per_tile, 1.0))));
-            int64_t part = 0;
-            if (list.size() <= n_sample) {
-                a.tiles = ph == 0 ? dtl : dtr;
-                a.ntiles = static_cast<int32_t>(list.size());
-                part = total;
-            } else {
-                constexpr size_t kWindows = 8;
-                const size_t wlen = std::max<size_t>(n_sample / kWindows / 8 * 8, 8);
-                std::vector<TileDesc> sample;
-                for (size_t w = 0; w < kWindows; ++w) {
-                    const size_t start = (w * list.size() / kWindows) / 8 * 8;
-                    for (size_t j = start; j < std::min(start + wlen, list.size()); ++j) {
-                        sample.push_back(list[j]);
-                        part += cost[j];
+        }
+    } else if (tuning) {
+        std::vector<TileDesc> tl, tr, sample, perm;
+        std::vector<int64_t> cl, cr, scost;
+        std::vector<int32_t> off;
+        for (int v : cands)
+            for (int order : {0, 1, 2}) {
+                tiles_for(0, v, order, &tl, &tr, &cl, &cr);
+                for (int ph = 0; ph < 2; ++ph) {
+                    const std::vector<int64_t> &cost = ph == 0 ? cl : cr;
+                    const std::vector<TileDesc> &list = ph == 0 ? tl : tr;
+                    int64_t total = 0, items = 0;
+                    for (auto cc : cost) {
+                        total += cc;
+                        items += cc > 0;
+                    }
+                    const PairShape shp = pair_shape(S, G, v);
+                    const double blocks_per_tile = items ? static_cast<double>(total) / items / (shp.bm * shp.bn) : 1.0;
+                    // the timing sample (the whole list when it is short)
+                    const size_t n_sample = std::min(cap, std::max(floor_tiles, static_cast<size_t>(16.0 * cap / std::max(blocks_per_tile, 1.0))));
+                    int64_t part = 0;
+                    sample.clear();
+                    scost.clear();
+                    if (list.size() <= n_sample) {
+                        sample = list;
+                        scost = cost;
+                        part = total;
+                    } else {
+                        constexpr size_t kWindows = 8;
+                        const size_t wlen = std::max<size_t>(n_sample / kWindows / 8 * 8, 8);
+                        for (size_t w = 0; w < kWindows; ++w) {
+                            const size_t start = (w * list.size() / kWindows) / 8 * 8;
+                            for (size_t j = start; j < std::min(start + wlen, list.size()); ++j) {
+                                sample.push_back(list[j]);
+                                scost.push_back(cost[j]);
+                                part += cost[j];
+                            }
+                        }
+                    }
+                    for (int kind : kinds_for(ph, v)) {
+                        // Timed choice: the streamed kernel saves a fixed cost
+                        // per (tile, term) item (the first K block's load, the
+                        // exposed epilogue), so it is a candidate for the
+                        // GEMM-mode phase with short items only; in the
+                        // accumulating phase it was slower at every measured
+                        // shape.
+                        if (kind == 1 && forced < 0 && (ph == 1 || blocks_per_tile > kStreamMaxMeanBlocks)) continue;
+                        PairArgs a = ph == 0 ? P->chunks[0].argsL : P->chunks[0].argsR;
+                        a.stream_cus = kind == 1 ? stream_cus_of : 0;
+                        a.nwg = 0;
+                        a.wg_off = nullptr;
+                        const std::vector<TileDesc> *up = &sample;
+                        if (kind == 2) {
+                            const int nwg = std::min(pair_resident_per_cu(S, G, v), kMaxResidentPerCu) * ctx->num_cu;
+                            resident_schedule(sample, scost, nwg, resident_start_cost(shp), &perm, &off);
+                            if ((e = hipMemcpy(tmp_off, off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice)) != hipSuccess) {
+                                free_tuning();
+                                free_plan(P);
+                                return hip_fail(e, "heff_plan_create: tuning schedule");
+                            }
+                            a.nwg = nwg;
+                            a.wg_off = tmp_off;
+                            up = &perm;
+                        }
+                        if (up->empty()) continue;
+                        if ((e = hipMemcpy(tmp_tiles, up->data(), sizeof(TileDesc) * up->size(), hipMemcpyHostToDevice)) != hipSuccess) {
+                            free_tuning();
+                            free_plan(P);
+                            return hip_fail(e, "heff_plan_create: tuning sample");
+                        }
+                        a.tiles = tmp_tiles;
+                        a.ntiles = static_cast<int32_t>(up->size());
+                        if (ph == 1) a.out_base = static_cast<double *>(tmp_sigma);
+                        // a warm-up launch, then the faster of two timed ones
+                        float ms = 0.f;
+                        for (int rep = 0; rep < 3; ++rep) {
+                            float r = 0.f;
+                            hipEventRecord(ev0, s);
+                            if ((e = launch_pair_grouped(S, G, v, a, s)) != hipSuccess) {
+                                free_tuning();
+                                free_plan(P);
+                                return hip_fail(e, "heff_plan_create: tuning launch");
+                            }
+                            hipEventRecord(ev1, s);
+                            hipEventSynchronize(ev1);
+                            hipEventElapsedTime(&r, ev0, ev1);
+                            if (rep == 1 || (rep > 1 && r < ms)) ms = r;
+                        }
+                        const double est = part > 0 ? ms * static_cast<double>(total) / static_cast<double>(part) : 0.0;
+                        double &best = ph == 0 ? bestL : bestR;
+                        if (best < 0 || est < best) {
+                            best = est;
+                            (ph == 0 ? chosenL : chosenR) = Run{v, order, kind, kind == 1 ? stream_cus_of : 0};
+                        }
                     }
                 }
-                if ((e = hipMemcpy(tmp_tiles, sample.data(), sizeof(TileDesc) * sample.size(), hipMemcpyHostToDevice)) != hipSuccess) {
-                    hipFree(tmp_sigma);
-                    hipFree(tmp_tiles);
-                    free_plan(P);
-                    return hip_fail(e, "heff_plan_create: tuning sample");
-                }
-                a.tiles = tmp_tiles;
-                a.ntiles = static_cast<int32_t>(sample.size());
             }
-            a.stream_cus = scus;
-            if (ph == 1) a.out_base = static_cast<double *>(tmp_sigma);
-            // a warm-up launch, then the faster of two timed ones
-            float ms = 0.f;
-            for (int rep = 0; rep < 3; ++rep) {
-                float r = 0.f;
-                hipEventRecord(ev0, s);
-                if ((e = launch_pair_grouped(S, G, v, a, s)) != hipSuccess) { hipFree(tmp_sigma); hipFree(tmp_tiles); free_plan(P); return hip_fail(e, "heff_plan_create: tuning launch"); }
-                hipEventRecord(ev1, s);
-                hipEventSynchronize(ev1);
-                hipEventElapsedTime(&r, ev0, ev1);
-                if (rep == 1 || (rep > 1 && r < ms)) ms = r;
-            }
-            const double est = part > 0 ? ms * static_cast<double>(total) / static_cast<double>(part) : 0.0;
-            double &best = ph == 0 ? bestL : bestR;
-            if (best < 0 || est < best) {
-                best = est;
-                if (ph == 0) { c0.argsL.tiles = dtl; c0.argsL.ntiles = ntl; P->varL = v; c0.argsL.stream_cus = scus; chosenL = run; }
-                else { c0.argsR.tiles = dtr; c0.argsR.ntiles = ntr; P->varR = v; c0.argsR.stream_cus = scus; chosenR = run; }
-            }
-        }
-    }
-    if (tuning) {
         hipEventDestroy(ev0);
         hipEventDestroy(ev1);
         hipStreamSynchronize(s);
-        hipFree(tmp_sigma);
-        hipFree(tmp_tiles);
+        free_tuning();
         // the timed launches of the first phase may have left maxima
         if (P->T_emax && (e = hipMemcpy(P->T_emax, emax_init.data(), sizeof(int32_t) * emax_init.size(),
                                         hipMemcpyHostToDevice)) != hipSuccess) { free_plan(P); return hip_fail(e, "heff_plan_create: reset"); }
     }
-    P->choice[0][0] = P->varL;
-    P->choice[0][1] = chosenL.order;
-    P->choice[0][2] = c0.argsL.stream_cus;
-    P->choice[1][0] = P->varR;
-    P->choice[1][1] = chosenR.order;
-    P->choice[1][2] = c0.argsR.stream_cus;
-    // the other chunks take the first chunk's choice per phase
-    for (size_t c = 1; c < hc.size(); ++c) {
-        HeffChunk &ch = P->chunks[c];
+    // every chunk: the chosen tile lists, schedules and launches per phase
+    for (size_t c = 0; c < hc.size(); ++c) {
         std::vector<TileDesc> l1, r1, l2, r2;
         std::vector<int64_t> cl1, cr1, cl2, cr2;
         tiles_for(c, chosenL.v, chosenL.order, &l1, &r1, &cl1, &cr1);
         tiles_for(c, chosenR.v, chosenR.order, &l2, &r2, &cl2, &cr2);
-        TileDesc *d1, *d2;
-        if ((rc = upload(P, l1, &d1)) || (rc = upload(P, r2, &d2))) { free_plan(P); return rc; }
-        ch.argsL.tiles = d1; ch.argsL.ntiles = static_cast<int32_t>(l1.size()); ch.argsL.stream_cus = c0.argsL.stream_cus;
-        ch.argsR.tiles = d2; ch.argsR.ntiles = static_cast<int32_t>(r2.size()); ch.argsR.stream_cus = c0.argsR.stream_cus;
+        HeffChunk &ch = P->chunks[c];
+        for (int ph = 0; ph < 2; ++ph) {
+            const Run &run = ph == 0 ? chosenL : chosenR;
+            const std::vector<TileDesc> &list = ph == 0 ? l1 : r2;
+            const std::vector<int64_t> &cost = ph == 0 ? cl1 : cr2;
+            PairArgs &a = ph == 0 ? ch.argsL : ch.argsR;
+            a.stream_cus = run.kind == 1 ? run.cus : 0;
+            a.nwg = 0;
+            a.wg_off = nullptr;
+            TileDesc *d = nullptr;
+            if (run.kind == 2) {
+                const int nwg = std::min(pair_resident_per_cu(S, G, run.v), kMaxResidentPerCu) * ctx->num_cu;
+                std::vector<TileDesc> perm;
+                std::vector<int32_t> off;
+                resident_schedule(list, cost, nwg, resident_start_cost(pair_shape(S, G, run.v)), &perm, &off);
+                int32_t *doff = nullptr;
+                if ((rc = upload(P, perm, &d)) || (rc = upload(P, off, &doff))) { free_plan(P); return rc; }
+                a.tiles = d;
+                a.ntiles = static_cast<int32_t>(perm.size());
+                a.nwg = nwg;
+                a.wg_off = doff;
+            } else {
+                if ((rc = upload(P, list, &d))) { free_plan(P); return rc; }
+                a.tiles = d;
+                a.ntiles = static_cast<int32_t>(list.size());
+            }
+        }
     }
+    P->varL = chosenL.v;
+    P->varR = chosenR.v;
+    P->choice[0][0] = chosenL.v;
+    P->choice[0][1] = chosenL.order;
+    P->choice[0][2] = chosenL.kind == 2 ? kHeffLaunchResident : chosenL.cus;
+    P->choice[1][0] = chosenR.v;
+    P->choice[1][1] = chosenR.order;
+    P->choice[1][2] = chosenR.kind == 2 ? kHeffLaunchResident : chosenR.cus;
     if ((e = hipStreamSynchronize(s)) != hipSuccess) { free_plan(P); return hip_fail(e, "heff_plan_create: sync"); }
     *out = P;
     return OZ_OK;
@@ -1070,8 +1154,9 @@ int heff_plan_variants(heff_plan P, int32_t *first, int32_t *second) {
 
 int heff_plan_launches(heff_plan P, int32_t *first, int32_t *second) {
     if (!P) return fail(OZ_ERR_ARG, "heff_plan_launches: plan is NULL");
-    if (first) *first = P->S ? (P->chunks[0].argsL.stream_cus > 0 ? 1 : 0) : -1;
-    if (second) *second = P->S ? (P->chunks[0].argsR.stream_cus > 0 ? 1 : 0) : -1;
+    auto kind = [](const PairArgs &a) { return a.nwg > 0 ? 2 : a.stream_cus > 0 ? 1 : 0; };
+    if (first) *first = P->S ? kind(P->chunks[0].argsL) : -1;
+    if (second) *second = P->S ? kind(P->chunks[0].argsR) : -1;
     return OZ_OK;
 }
 

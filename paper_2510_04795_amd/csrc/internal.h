@@ -123,6 +123,11 @@ struct PairArgs {
     // `queue` (kStreamQueueInts zeroed ints, left zeroed by every launch)
     int32_t stream_cus;
     int32_t *queue;
+    // grouped, GEMM mode with beta = 0: nwg > 0 = the resident kernel, nwg
+    // workgroups (all resident at once), workgroup b taking the tiles
+    // tiles[wg_off[b] .. wg_off[b + 1]) in order
+    int32_t nwg;
+    const int32_t *wg_off;
 };
 
 // FP64 GEMM term: op(A) (M x K) times op(B) (K x N), both plain FP64.
@@ -224,6 +229,9 @@ int pair_default_variant(int G);
 PairShape pair_shape(int S, int G, int v);
 hipError_t launch_pair_single(int S, int G, int v, const PairArgs &a, int tiles_m, hipStream_t s);
 hipError_t launch_pair_grouped(int S, int G, int v, const PairArgs &a, hipStream_t s);
+// Workgroups of the resident GEMM-mode kernel that fit on one compute unit
+// at once for (S, G, v); 0 where that kernel is not built for the variant.
+int pair_resident_per_cu(int S, int G, int v);
 
 // FP64 MFMA GEMM.  The single launch picks its tile size from the output
 // extent (a.out) and the compute-unit count; the grouped launch takes tiles

@@ -48,4 +48,18 @@ hipError_t launch_pair_grouped(int S, int G, int v, const PairArgs &a, hipStream
     }
 }
 
+int pair_resident_per_cu(int S, int G, int v) {
+    if (v < 0) v = pair::default_variant(G);
+    switch (S) {
+        case 2: return pair_resident_s2(G, v);
+        case 3: return pair_resident_s3(G, v);
+        case 4: return pair_resident_s4(G, v);
+        case 5: return pair_resident_s5(G, v);
+        case 6: return pair_resident_s6(G, v);
+        case 7: return pair_resident_s7(G, v);
+        case 8: return pair_resident_s8(G, v);
+        default: return 0;
+    }
+}
+
 }  // namespace oz

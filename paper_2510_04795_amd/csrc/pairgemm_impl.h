@@ -61,6 +61,7 @@ struct Cfg {
     static constexpr int WAIT_ALL = wait_vm(0);
     static constexpr int WAIT_NEWEST = wait_vm(NL_MIN);      // one block's loads may stay in flight
     static constexpr int WAIT_NEWER2 = wait_vm(2 * NL_MIN);  // two blocks' loads may stay in flight
+    static constexpr int WAIT_LDS = wait_vm(63);              // lgkmcnt(0) only
 };
 
 // Direct-to-LDS loads of one packed K block: the stage holds 2S runs of BM
@@ -630,6 +631,16 @@ __device__ __forceinline__ void emax_issue(long long lo, long long hi, int l32, 
     keep = b4 ? hi : lo;
 }
 
+typedef __attribute__((address_space(1))) int32_t global_i32;
+
+// Atomic max on global memory, through the global address space: through a
+// generic pointer (which may point into LDS) the compiler first waits for
+// every load into LDS in flight.
+__device__ __forceinline__ void global_atomic_max(int32_t *p, int32_t v) {
+    __hip_atomic_fetch_max((global_i32 *)reinterpret_cast<uintptr_t>(p), v, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // The remaining exchanges (partners l ^ 8, 4, 2, 1), then the even lanes
 // turn their row's maximum into an exponent code and combine it into emax
 // with one atomic max.  The columns j0 .. j0 + 31 map to one emax group.
@@ -664,7 +675,7 @@ __device__ __forceinline__ void emax_block(const OutDesc &out, const long long (
     const int i = i0 + 8 * (r >> 2) + 4 * half + (r & 3);
     if (!(l32 & 1) && i < out.M && j0 < out.N && w != 0) {
         const int32_t code = w >= 0x7ff0000000000000ll ? kEmaxNaN : shared_exponent(__longlong_as_double(w));
-        atomicMax(out.emax + static_cast<int64_t>(i) * out.ep + j0 / out.en, code);
+        global_atomic_max(out.emax + static_cast<int64_t>(i) * out.ep + j0 / out.en, code);
     }
 }
 
@@ -1086,6 +1097,301 @@ __global__ __launch_bounds__(64 * WM * WN) void k_pair_stream(PairArgs a) {
     stream_tiles<S, G, WM, WN, MB, NB, MODE>(a, [&](int i) { return terms[i]; }, lds0, lds1);
 }
 
+// ---- resident GEMM-mode kernel ---------------------------------------------
+// For lists of short tiles (the first products of a block-sparse H_eff),
+// where a workgroup per tile spends much of its life starting up: every
+// workgroup of a grid that fits on the device at once takes the tiles
+// tiles[wg_off[b] .. wg_off[b + 1]) of a schedule the host balanced by cost
+// (no counters), in order.  The K blocks of its tiles form one stream
+// through the three-stage ring: each step loads the block three positions
+// ahead, of the current tile or of the next one, so a tile starts with its
+// first blocks in LDS or on their way and its epilogue runs while they
+// load.  Each tile's row and column exponents come into LDS with its first
+// block (the epilogue issues no vector loads, whose waits would also wait
+// for the next tile's blocks).  Same arithmetic as pair_tile's GEMM mode
+// with beta = 0 and no int64 partial sums.
+
+typedef __attribute__((address_space(4))) const TileDesc ConstTileDesc;
+typedef __attribute__((address_space(4))) const OutDesc ConstOutDesc;
+typedef __attribute__((address_space(4))) const int32_t ConstI32;
+
+__device__ __forceinline__ TileDesc const_tile(const TileDesc *list, int i) {
+    const ConstTileDesc *c = (const ConstTileDesc *)reinterpret_cast<uintptr_t>(list + i);
+    TileDesc t;
+    t.term_begin = c->term_begin;
+    t.term_end = c->term_end;
+    t.m0 = c->m0;
+    t.n0 = c->n0;
+    t.out = c->out;
+    t.pad_ = 0;
+    return t;
+}
+
+__device__ __forceinline__ OutDesc const_out(const OutDesc *list, int i) {
+    const ConstOutDesc *c = (const ConstOutDesc *)reinterpret_cast<uintptr_t>(list + i);
+    OutDesc o;
+    o.C = c->C;
+    o.ldc = c->ldc;
+    o.M = c->M;
+    o.N = c->N;
+    o.emax = c->emax;
+    o.ep = c->ep;
+    o.en = c->en;
+    o.cont = c->cont;
+    o.pad_ = 0;
+    return o;
+}
+
+__device__ __forceinline__ int32_t const_i32(const int32_t *p, int i) {
+    return *(const ConstI32 *)reinterpret_cast<uintptr_t>(p + i);
+}
+
+// Whether the resident kernel is built for a tile shape: one 32 x 32 block
+// per wave on the three-stage ring.
+template <int S, int G, int WM, int WN, int MB, int NB>
+__host__ __device__ constexpr bool resident_fits() {
+    return MB == 1 && NB == 1 && use_ring<S, G, WM, WN, MB, NB, kModeGemm>();
+}
+
+// The exponents of one tile into LDS slot `ex` (BM row exponents, then BN
+// column exponents): one 64-entry load per wave for the first BM / 64 + BN
+// / 64 waves; entries past the output's edge are out of the buffer's range
+// and left unused by the epilogue.
+template <int BM, int BN>
+__device__ __forceinline__ void resident_exponents(int32_t *ex, const TermDesc &T, const OutDesc &od, int m0, int n0,
+                                                   int wave, int lane) {
+    constexpr int NE = BM / 64, NF = BN / 64;
+    if (wave < NE + NF) {
+        const bool rows = wave < NE;
+        const int first = rows ? m0 + wave * 64 : n0 + (wave - NE) * 64;
+        const int valid = (rows ? od.M : od.N) - first;
+        const int32_t *base = rows ? T.e : T.f;
+        const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<int32_t *>(valid > 0 ? base + first : base), 0, valid > 0 ? 4 * min(valid, 64) : 0,
+            kBufferDword3);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_void *)(ex + wave * 64), 4, 4 * lane, 0, 0, 0);
+    }
+}
+
+// One step of a resident item: as ring_step, except that the block three
+// positions ahead may be the next item's (its block p - nkb, for p - nkb <
+// nxt), and the last block also hands its stage on when the next item has a
+// third block.
+template <int S, int G, int WM, int WN, typename F, typename LP>
+__device__ __forceinline__ void resident_step(v16i (&acc)[G][1][1], F &cur, uint4 *fill, const uint4 *rd,
+                                              const LP &lp, const LP &np, int kb, int nkb, int nxt, int wm, int wn,
+                                              int half, int l32) {
+    using C = Cfg<S, G, WM, WN, 1, 1>;
+    using RA = RingAddr<S, G, WM, WN, 1, 1>;
+    const int p = kb + 3;
+    if (kb + 1 < nkb) {
+        // block kb + 1 has arrived once only the position after it may still load
+        const bool ahead = kb + 2 < nkb || kb + 2 - nkb < nxt;
+        if (ahead)
+            __builtin_amdgcn_s_waitcnt(C::WAIT_NEWEST);
+        else
+            __builtin_amdgcn_s_waitcnt(C::WAIT_ALL);
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        if (p < nkb)
+            lp.issue(fill, p);
+        else if (p - nkb < nxt)
+            np.issue(fill, p - nkb);
+    } else if (p - nkb < nxt) {
+        // every wave has read this block's fragments before its stage is refilled
+        __builtin_amdgcn_s_waitcnt(C::WAIT_LDS);
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        np.issue(fill, p - nkb);
+    }
+    AsmStep<S, G>::template run<RA::OA, RA::OB>(acc, cur, RA::a(rd, wm, half, l32), RA::b(rd, wn, half, l32));
+}
+
+// The diagonal sums of one item whose first min(nkb, 3) blocks are issued
+// into s0, s1, s2 (in that order) with its exponents before them; issues the
+// next item's exponents (through `next_exp`) and its first `nxt` blocks.
+template <int S, int G, int WM, int WN, typename LP, typename NextExp>
+__device__ __forceinline__ void resident_item(v16i (&acc)[G][1][1], uint4 *s0, uint4 *s1, uint4 *s2, const LP &lp,
+                                              int nkb, const LP &np, int nxt, NextExp next_exp) {
+    using C = Cfg<S, G, WM, WN, 1, 1>;
+    using RA = RingAddr<S, G, WM, WN, 1, 1>;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave / WN;
+    const int wn = wave % WN;
+    const int half = lane >> 5;
+    const int l32 = lane & 31;
+#pragma unroll
+    for (int g = 0; g < G; ++g) acc[g][0][0] = v16i{};
+    if (nkb == 0) {
+        // no blocks: the exponents have arrived and no wave reads the stages
+        __builtin_amdgcn_s_waitcnt(C::WAIT_ALL);
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        next_exp();
+        if (0 < nxt) np.issue(s0, 0);
+        if (1 < nxt) np.issue(s1, 1);
+        if (2 < nxt) np.issue(s2, 2);
+        return;
+    }
+    // block 0 (and the exponents issued before it) has arrived, while this
+    // item's blocks 1 and 2 may still load
+    if (2 < nkb)
+        __builtin_amdgcn_s_waitcnt(C::WAIT_NEWER2);
+    else if (1 < nkb)
+        __builtin_amdgcn_s_waitcnt(C::WAIT_NEWEST);
+    else
+        __builtin_amdgcn_s_waitcnt(C::WAIT_ALL);
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    // the other exponent slot was last read by the previous item's epilogue
+    next_exp();
+    // positions nkb .. 2 of a short item take the next item's first blocks
+    if (nkb == 1) {
+        if (0 < nxt) np.issue(s1, 0);
+        if (1 < nxt) np.issue(s2, 1);
+    } else if (nkb == 2) {
+        if (0 < nxt) np.issue(s2, 0);
+    }
+    Frags<S, G, 1, 1> f;
+    AsmStep<S, G>::template read<RA::OA, RA::OB>(f, RA::a(s0, wm, half, l32), RA::b(s0, wn, half, l32));
+    int kb = 0;
+    for (; kb + 3 <= nkb; kb += 3) {
+        resident_step<S, G, WM, WN>(acc, f, s0, s1, lp, np, kb, nkb, nxt, wm, wn, half, l32);
+        resident_step<S, G, WM, WN>(acc, f, s1, s2, lp, np, kb + 1, nkb, nxt, wm, wn, half, l32);
+        resident_step<S, G, WM, WN>(acc, f, s2, s0, lp, np, kb + 2, nkb, nxt, wm, wn, half, l32);
+    }
+    if (kb < nkb) resident_step<S, G, WM, WN>(acc, f, s0, s1, lp, np, kb, nkb, nxt, wm, wn, half, l32);
+    if (kb + 1 < nkb) resident_step<S, G, WM, WN>(acc, f, s1, s2, lp, np, kb + 1, nkb, nxt, wm, wn, half, l32);
+    asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 7" ::: "memory");
+}
+
+// The epilogue's exponents from LDS slot `ex`: the lane's 16 row exponents
+// (four runs of four) and its column's, read in one asm block that waits for
+// them itself.  A read the compiler sees would first wait for every load
+// into LDS in flight, the next item's blocks among them.
+template <int BM>
+__device__ __forceinline__ void resident_read_exponents(int32_t (&ei)[16], int32_t &fj, const int32_t *ex, int wm,
+                                                        int wn, int half, int l32) {
+    const unsigned rows = static_cast<unsigned>(reinterpret_cast<uintptr_t>(ex + wm * 32 + 4 * half));
+    const unsigned col = static_cast<unsigned>(reinterpret_cast<uintptr_t>(ex + BM + wn * 32 + l32));
+    v4i q0, q1, q2, q3;
+    int32_t c;
+    asm volatile(
+        "ds_read_b128 %0, %5\n\t"
+        "ds_read_b128 %1, %5 offset:32\n\t"
+        "ds_read_b128 %2, %5 offset:64\n\t"
+        "ds_read_b128 %3, %5 offset:96\n\t"
+        "ds_read_b32 %4, %6\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=v"(q0), "=v"(q1), "=v"(q2), "=v"(q3), "=v"(c)
+        : "v"(rows), "v"(col)
+        : "memory");
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        ei[k] = q0[k];
+        ei[4 + k] = q1[k];
+        ei[8 + k] = q2[k];
+        ei[12 + k] = q3[k];
+    }
+    fj = c;
+}
+
+// The GEMM-mode epilogue of one item (beta = 0) with its exponents from LDS.
+template <int S, int G, int WM, int WN>
+__device__ __forceinline__ void resident_epilogue(const OutDesc &out, const TermDesc &T, v16i (&acc)[G][1][1],
+                                                  int m0, int n0, const int32_t *ex) {
+    using C = Cfg<S, G, WM, WN, 1, 1>;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wm = wave / WN;
+    const int wn = wave % WN;
+    const int half = lane >> 5;
+    const int l32 = lane & 31;
+    const int j = n0 + wn * 32 + l32;
+    const bool jok = j < out.N;
+    int32_t ei[16], fj;
+    resident_read_exponents<C::BM>(ei, fj, ex, wm, wn, half, l32);
+    long long w8[8], mlo = 0, keep = 0, got = 0;
+#pragma unroll
+    for (int rr = 0; rr < 16; ++rr) {
+        const int r = (rr & 1) ? 8 + (rr >> 1) : (rr >> 1);
+        if (rr % kEpilogueGroup == 0) __builtin_amdgcn_sched_barrier(0);
+        const int i = m0 + wm * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+        long long mag = 0;
+        if (jok && i < out.M) {
+            long long q[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) q[g] = acc[g][0][0][r];
+            const double v = T.alpha * horner<G>(q, ei[r], fj);
+            out.C[static_cast<int64_t>(i) * out.ldc + j] = v;
+            mag = __double_as_longlong(v) & 0x7fffffffffffffffll;
+        }
+        if (out.emax) {
+            if (rr & 1) {
+                if (rr > 1) w8[(rr >> 1) - 1] = keep > got ? keep : got;
+                emax_issue(mlo, mag, l32, keep, got);
+            } else {
+                mlo = mag;
+            }
+        }
+    }
+    if (out.emax) {
+        w8[7] = keep > got ? keep : got;
+        emax_block(out, w8, m0 + wm * 32, n0 + wn * 32, half, l32);
+    }
+}
+
+template <int S, int G, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) void k_pair_resident(PairArgs a) {
+    using C = Cfg<S, G, WM, WN, 1, 1>;
+    using LP = LoadPlan<S, G, WM, WN, 1, 1, 2>;
+    __shared__ uint4 st[3][C::STAGE];
+    __shared__ __align__(16) int32_t ex[2][C::BM + C::BN];
+    const int t0 = const_i32(a.wg_off, blockIdx.x), t1 = const_i32(a.wg_off, blockIdx.x + 1);
+    if (t0 >= t1) return;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    TileDesc td = const_tile(a.tiles, t0);
+    OutDesc od = const_out(a.outs, td.out);
+    if (a.out_base) od.C = a.out_base + reinterpret_cast<intptr_t>(od.C);
+    TermDesc T = const_term(a.terms, td.term_begin);
+    LP lp;
+    lp.init(T.A, T.B, T.a_rows_p, T.b_rows_p, td.m0, td.n0, wave, lane);
+    resident_exponents<C::BM, C::BN>(ex[0], T, od, td.m0, td.n0, wave, lane);
+    if (0 < T.kblocks) lp.issue(st[0], 0);
+    if (1 < T.kblocks) lp.issue(st[1], 1);
+    if (2 < T.kblocks) lp.issue(st[2], 2);
+    int ph = 0;   // stage of the current item's first block
+    int slot = 0; // its exponent slot
+    for (int t = t0; t < t1; ++t) {
+        const bool more = t + 1 < t1;
+        const TileDesc nd = const_tile(a.tiles, more ? t + 1 : t);
+        OutDesc nod = const_out(a.outs, nd.out);
+        if (a.out_base) nod.C = a.out_base + reinterpret_cast<intptr_t>(nod.C);
+        const TermDesc N = const_term(a.terms, nd.term_begin);
+        LP np;
+        np.init(N.A, N.B, N.a_rows_p, N.b_rows_p, nd.m0, nd.n0, wave, lane);
+        const int nxt = more ? min(N.kblocks, 3) : 0;
+        int32_t *nex = ex[slot ^ 1];
+        v16i acc[G][1][1];
+        uint4 *s0 = st[ph];
+        uint4 *s1 = st[ph == 2 ? 0 : ph + 1];
+        uint4 *s2 = st[ph == 0 ? 2 : ph - 1];
+        resident_item<S, G, WM, WN>(acc, s0, s1, s2, lp, T.kblocks, np, nxt, [&]() {
+            if (more) resident_exponents<C::BM, C::BN>(nex, N, nod, nd.m0, nd.n0, wave, lane);
+        });
+        resident_epilogue<S, G, WM, WN>(od, T, acc, td.m0, td.n0, ex[slot]);
+        ph = (ph + T.kblocks) % 3;
+        slot ^= 1;
+        td = nd;
+        od = nod;
+        T = N;
+        lp = np;
+    }
+}
+
 // Tile index -> (tm, tn).  Blocks are dispatched to the 8 XCDs round robin;
 // give every XCD a contiguous range of tiles, walked in groups of `group`
 // tile rows, so the blocks that run together on one L2 share A and B panels.
@@ -1213,6 +1519,15 @@ hipError_t run_grouped_v(const PairArgs &a, hipStream_t s) {
         return hipErrorInvalidValue;
     } else {
         if (a.ntiles == 0) return hipSuccess;
+        if (a.nwg > 0) {
+            if constexpr (resident_fits<S, G, WM, WN, MB, NB>()) {
+                if (a.mode != kModeGemm || !a.wg_off || a.beta != 0.0 || a.Qw) return hipErrorInvalidValue;
+                hipLaunchKernelGGL((k_pair_resident<S, G, WM, WN>), dim3(a.nwg), dim3(NT), 0, s, a);
+                return hipGetLastError();
+            } else {
+                return hipErrorInvalidValue;
+            }
+        }
         if (a.stream_cus > 0) {
             if (!a.queue) return hipErrorInvalidValue;
             // resident workgroups only: the grid walks the list, nothing queues behind it
@@ -1245,6 +1560,36 @@ hipError_t run_grouped_v(const PairArgs &a, hipStream_t s) {
             default: return hipErrorInvalidValue;
         }
         return hipGetLastError();
+    }
+}
+
+template <int S, int G, int V>
+int resident_per_cu_v() {
+    constexpr int WM = variant_wm(V), WN = variant_wn(V), MB = variant_mb(V), NB = variant_nb(V);
+    if constexpr (!variant_fits(G, V)) {
+        return 0;
+    } else if constexpr (!resident_fits<S, G, WM, WN, MB, NB>()) {
+        return 0;
+    } else {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_pair_resident<S, G, WM, WN>, 64 * WM * WN, 0) !=
+            hipSuccess)
+            return 0;
+        return n;
+    }
+}
+
+template <int S, int G>
+int resident_per_cu(int v) {
+    switch (v) {
+        case 0: return resident_per_cu_v<S, G, 0>();
+        case 1: return resident_per_cu_v<S, G, 1>();
+        case 2: return resident_per_cu_v<S, G, 2>();
+        case 3: return resident_per_cu_v<S, G, 3>();
+        case 4: return resident_per_cu_v<S, G, 4>();
+        case 5: return resident_per_cu_v<S, G, 5>();
+        case 6: return resident_per_cu_v<S, G, 6>();
+        default: return 0;
     }
 }
 
@@ -1281,7 +1626,8 @@ hipError_t run_grouped(int v, const PairArgs &a, hipStream_t s) {
 // Per-S entry points (pairgemm_s<S>.hip).
 #define OZ_DECLARE_PAIR_S(S_)                                                                   \
     hipError_t pair_single_s##S_(int G, int v, const PairArgs &a, int tiles_m, hipStream_t s);  \
-    hipError_t pair_grouped_s##S_(int G, int v, const PairArgs &a, hipStream_t s);
+    hipError_t pair_grouped_s##S_(int G, int v, const PairArgs &a, hipStream_t s);              \
+    int pair_resident_s##S_(int G, int v);
 OZ_DECLARE_PAIR_S(2)
 OZ_DECLARE_PAIR_S(3)
 OZ_DECLARE_PAIR_S(4)
@@ -1304,6 +1650,12 @@ OZ_DECLARE_PAIR_S(8)
         if (G == S_ + 1) return pair::run_grouped<S_, S_ + 1>(v, a, s);                         \
         if (G == 2 * S_ - 1) return pair::run_grouped<S_, 2 * S_ - 1>(v, a, s);                 \
         return hipErrorInvalidValue;                                                            \
+    }                                                                                           \
+    int pair_resident_s##S_(int G, int v) {                                                     \
+        if (G == S_) return pair::resident_per_cu<S_, S_>(v);                                   \
+        if (G == S_ + 1) return pair::resident_per_cu<S_, S_ + 1>(v);                           \
+        if (G == 2 * S_ - 1) return pair::resident_per_cu<S_, 2 * S_ - 1>(v);                   \
+        return 0;                                                                               \
     }
 
 }  // namespace oz

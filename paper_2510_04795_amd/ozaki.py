@@ -20,6 +20,7 @@ OZ_OK, OZ_CONVERGED, OZ_STAGNATED, OZ_MAX_ITER = 0, 1, 2, 3
 OZ_STATIC_WORKSPACE_BYTES = 96 << 20
 OZ_FLAG_NONFINITE = 1
 OZ_EXP_NONFINITE = -(2 ** 31)
+OZ_HEFF_LAUNCH_RESIDENT = -2
 PHASES = {1: "slice", 2: "pair", 3: "fp64", 4: "heff_L", 5: "heff_R", 6: "heff_aux"}
 STATUS = {0: "running", 1: "converged", 2: "stagnated", 3: "max_iter"}
 
@@ -256,15 +257,17 @@ class Context:
     def set_heff_launch(self, mode: int = -1):
         """Launch of later heff plans' grouped phases: 0 one workgroup per
         tile, k > 0 streamed on k compute units (capped at the device's),
-        -1 timed choice for the first phase when its items are short
-        (default)."""
+        OZ_HEFF_LAUNCH_RESIDENT the resident kernel for the first phase
+        where it is built for the tile variant, -1 timed choice for the
+        first phase (default)."""
         _check(_lib.ozaki_ctx_set_heff_launch(self.handle, int(mode)), "ozaki_ctx_set_heff_launch")
 
     def set_heff_phase(self, phase: int, variant: int = -1, order: int = 0, launch: int = 0):
         """Fix grouped phase `phase` (0 first product, 1 second) of later
         emulated heff plans: tile variant (-1 clears), order (0 XCD parts,
         1 longest tile first, 2 whole outputs per XCD, heaviest first to the
-        least loaded), launch (0 per tile, k > 0 streamed on k CUs).
+        least loaded), launch (0 per tile, k > 0 streamed on k CUs,
+        OZ_HEFF_LAUNCH_RESIDENT resident, first phase only).
         With both phases fixed a plan times nothing."""
         _check(_lib.ozaki_ctx_set_heff_phase(self.handle, int(phase), int(variant), int(order), int(launch)),
                "ozaki_ctx_set_heff_phase")

@@ -223,23 +223,37 @@ def test_sparse_fp64(oz):
         assert np.all(np.abs(sig[b] - ref[b]) <= 2 * K * u * mag[b] + 1e-300), b
 
 
-@pytest.mark.parametrize("launch", [-1, 0, 100000])
+@pytest.mark.parametrize("launch", [-1, 0, 100000, -2])
 def test_sparse_full_size_sampled_blocks(oz, launch):
     """The 40-sector, 2000-triple batch; sigma blocks depend only on their own
     triples, so the oracle recomputes a few blocks alone: the three with the
     fewest triples and the three with the most (the longest ordered
-    accumulation chains).  Timed launch choice, one workgroup per tile, and
-    the streamed kernel on every CU."""
+    accumulation chains).  Timed launch choice, one workgroup per tile, the
+    streamed kernel on every CU, and the resident first phase on the 64 x 64
+    tiles (every workgroup walks some 65 tiles of 1 to 47 K blocks), whose
+    whole sigma must also equal the per-tile launch's."""
     ozaki, ctx, torch = oz
     prob = wl.heff_sparse()
     ctx.set_heff_launch(launch)
+    if launch == ozaki.OZ_HEFF_LAUNCH_RESIDENT:
+        ctx.set_variant(6, 0, 0)
     try:
         plan, dpsi, keep = sparse_plan(ozaki, ctx, torch, prob, 6)
+        if launch == ozaki.OZ_HEFF_LAUNCH_RESIDENT:
+            ctx.set_heff_launch(0)
+            plan0, _, keep0 = sparse_plan(ozaki, ctx, torch, prob, 6)
+            assert plan0.launches == (0, 0)
     finally:
         ctx.set_heff_launch(-1)
+        ctx.set_variant(6, 0, -1)
     if launch >= 0:
         assert plan.launches == ((1, 1) if launch else (0, 0))
-    sig = wl.unflatten_sparse(prob, plan.apply(dpsi).cpu().numpy())
+    elif launch == ozaki.OZ_HEFF_LAUNCH_RESIDENT:
+        assert plan.launches == (2, 0) and plan.phase(0)[2] == launch
+    out = plan.apply(dpsi)
+    if launch == ozaki.OZ_HEFF_LAUNCH_RESIDENT:
+        assert torch.equal(out, plan0.apply(dpsi))
+    sig = wl.unflatten_sparse(prob, out.cpu().numpy())
     counts = {}
     for t in prob.triples:
         counts[(t[1], t[4])] = counts.get((t[1], t[4]), 0) + 1
@@ -323,13 +337,15 @@ def test_fixed_phase_choice(oz):
 @pytest.mark.parametrize("order", [0, 1, 2])
 def test_tile_orders_bitexact(oz, order):
     """Every tile order (XCD parts, longest first, whole outputs per XCD),
-    per tile and streamed: the oracle's bits (the order moves tiles between
-    workgroups, never the arithmetic of one)."""
+    per tile, streamed and resident: the oracle's bits (the order moves
+    tiles between workgroups, never the arithmetic of one)."""
     ozaki, ctx, torch = oz
     prob = small_sparse(31)
     ref = oracle.heff_sparse(prob, S=6)
+    res = ozaki.OZ_HEFF_LAUNCH_RESIDENT
     try:
-        for (vl, ll), (vr, lr) in [((3, 0), (4, 0)), ((0, 7), (3, 0)), ((4, 0), (0, 0))]:
+        for (vl, ll), (vr, lr) in [((3, 0), (4, 0)), ((0, 7), (3, 0)), ((4, 0), (0, 0)), ((0, res), (0, 0)),
+                                   ((4, res), (3, 0))]:
             ctx.set_heff_phase(0, vl, order, ll)
             ctx.set_heff_phase(1, vr, order, lr)
             plan, dpsi, keep = sparse_plan(ozaki, ctx, torch, prob, 6)
@@ -463,10 +479,78 @@ def test_streamed_tiny_sectors(oz, cus):
         ctx.set_heff_launch(-1)
 
 
+@pytest.mark.parametrize("S,G", [(6, 6), (5, 6), (3, 5), (4, 4), (2, 3), (7, 7), (8, 8)])
+def test_resident_launch_bitexact(oz, S, G):
+    """The resident first phase (a grid that fits at once, each workgroup
+    streaming the K blocks of its scheduled tiles through one ring, the next
+    tile's first blocks loading during the current tile's last blocks and
+    epilogue) for every tile variant it is built for: the oracle's bits on a
+    dense problem, a sparse one and one of 1- to 40-state sectors (tiles of
+    one K block, so a tile's successors fill the ring behind it), and the
+    per-tile launch's bits on all of them."""
+    ozaki, ctx, torch = oz
+    res = ozaki.OZ_HEFF_LAUNCH_RESIDENT
+    L, R, psi = wl.heff_dense(D=70, kop=3, phys=4, seed=70 + S)
+    ref_d = oracle.heff_dense(L, R, psi, S=S, G=G)
+    probs = [small_sparse(80 + S),
+             wl.heff_sparse(n_sectors=6, n_triples=30, kop=3, median=6, sigma_log=1.2, lo_hi=(1, 40), density=0.5,
+                            reach=2, U=8, seed=4)]
+    refs = [oracle.heff_sparse(p, S=S, G=G) for p in probs]
+    kinds = set()
+    try:
+        for (v, tm, tn) in ozaki.pair_variants(S, G):
+            ctx.set_variant(S, G, v)
+            ctx.set_heff_launch(res)
+            plan, dpsi, keep = dense_plan(ozaki, ctx, torch, L, R, psi, S, G)
+            assert plan.variants == (v, v) and plan.launches[0] in (0, 2) and plan.launches[1] == 0
+            kinds.add(plan.launches[0])
+            out = plan.apply(dpsi)
+            assert_bitexact(out.cpu().numpy().reshape(psi.shape), ref_d, "dense variant %d" % v)
+            ctx.set_heff_launch(0)
+            plan0, _, keep0 = dense_plan(ozaki, ctx, torch, L, R, psi, S, G)
+            assert torch.equal(out, plan0.apply(dpsi))
+            for prob, ref in zip(probs, refs):
+                ctx.set_heff_launch(res)
+                plan, dpsi, keep = sparse_plan(ozaki, ctx, torch, prob, S, G)
+                assert plan.launches[0] in (0, 2) and plan.launches[1] == 0
+                sig = wl.unflatten_sparse(prob, plan.apply(dpsi).cpu().numpy())
+                for b in prob.psi_blocks:
+                    assert_bitexact(sig[b], ref[b], "sparse variant %d block %s" % (v, b))
+    finally:
+        ctx.set_heff_launch(-1)
+        ctx.set_variant(S, G, -1)
+    # built for the 8-wave tiles with G <= 8, and for the 64 x 64 tile from S = 3, G = 5 to S = 6
+    assert 2 in kinds
+
+
+def test_resident_second_phase_refused(oz):
+    ozaki, ctx, torch = oz
+    L, R, psi = wl.heff_dense(D=40, kop=2, phys=4, seed=2)
+    res = ozaki.OZ_HEFF_LAUNCH_RESIDENT
+    try:
+        ctx.set_heff_phase(0, 0, 0, 0)
+        ctx.set_heff_phase(1, 0, 0, res)
+        with pytest.raises(ozaki.OzakiError):
+            dense_plan(ozaki, ctx, torch, L, R, psi, 6)
+        # the 16-wave tile has no resident kernel
+        ctx.set_heff_phase(0, 6, 0, res)
+        ctx.set_heff_phase(1, 0, 0, 0)
+        with pytest.raises(ozaki.OzakiError):
+            dense_plan(ozaki, ctx, torch, L, R, psi, 4)
+        ctx.set_heff_phase(0, 0, 0, res)
+        plan, dpsi, keep = dense_plan(ozaki, ctx, torch, L, R, psi, 6)
+        assert plan.phase(0) == (0, 0, res) and plan.launches == (2, 0)
+        assert_bitexact(plan.apply(dpsi).cpu().numpy().reshape(psi.shape), oracle.heff_dense(L, R, psi, S=6),
+                        "fixed resident phase")
+    finally:
+        ctx.set_heff_phase(0, -1)
+        ctx.set_heff_phase(1, -1)
+
+
 def test_launch_modes(oz):
     ozaki, ctx, torch = oz
     with pytest.raises(ozaki.OzakiError):
-        ctx.set_heff_launch(-2)
+        ctx.set_heff_launch(-3)
     L, R, psi = wl.heff_dense(D=40, kop=2, phys=4, seed=1)
     try:
         ctx.set_heff_launch(0)
@@ -479,9 +563,9 @@ def test_launch_modes(oz):
         assert torch.equal(a, plan2.apply(dpsi))
     finally:
         ctx.set_heff_launch(-1)
-    # timed choice: only the first phase may stream
+    # timed choice: only the first phase may stream or run resident
     plan3, _, keep3 = dense_plan(ozaki, ctx, torch, L, R, psi, 6)
-    assert plan3.launches[0] in (0, 1) and plan3.launches[1] == 0
+    assert plan3.launches[0] in (0, 1, 2) and plan3.launches[1] == 0
     assert torch.equal(a, plan3.apply(dpsi))
     plan, dpsi, keep = dense_plan(ozaki, ctx, torch, L, R, psi, 0)
     assert plan.launches == (-1, -1)
