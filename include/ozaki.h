@@ -213,9 +213,11 @@ int ozaki_ctx_get_variant(ozaki_ctx ctx, int slices, int ndiag);
  * keeps the fastest (default on; a variant fixed with ozaki_ctx_set_variant
  * takes precedence). */
 int ozaki_ctx_set_autotune(ozaki_ctx ctx, int enable);
-/* Launch code of the resident kernel (ozaki_ctx_set_heff_launch,
+/* Launch codes of the resident kernel (first phase) and of the
+ * paired-term kernel (second phase) (ozaki_ctx_set_heff_launch,
  * ozaki_ctx_set_heff_phase, heff_plan_phase). */
 #define OZ_HEFF_LAUNCH_RESIDENT (-2)
+#define OZ_HEFF_LAUNCH_PAIRED_TERMS (-3)
 /* How heff plans created afterwards launch their two grouped pair phases:
  * 0 = one workgroup per output tile; k > 0 = the streamed kernel, in which
  * as many workgroups as fit at once on min(k, number of CUs) compute units
@@ -227,11 +229,17 @@ int ozaki_ctx_set_autotune(ozaki_ctx ctx, int enable);
  * fits on the device at once, each workgroup walking its part of a
  * schedule the plan balances by cost, the K blocks of its consecutive tiles
  * streamed through one ring (a tile's first blocks load during the
- * previous tile's last blocks and epilogue); -1 (default) = when
- * autotuning is on, time the first phase one workgroup per tile, streamed
- * (if its items average at most 16 K blocks) and resident (where built),
- * the second one workgroup per tile; else 0.  Results are bit-identical in
- * every mode.  OZ_ERR_ARG for mode < -2. */
+ * previous tile's last blocks and epilogue); OZ_HEFF_LAUNCH_PAIRED_TERMS =
+ * the first phase one workgroup per tile, the second on the paired-term
+ * kernel where it is built (64 x 64 tiles of variant 0 with the
+ * three-stage ring, S <= 6): eight waves per tile in two groups with a
+ * ring each, taking the tile's terms two at a time and adding their FP64
+ * values in term order (for outputs too small to give every SIMD two
+ * waves otherwise); -1 (default) = when autotuning is on, time the first
+ * phase one workgroup per tile, streamed (if its items average at most 16
+ * K blocks) and resident (where built), the second one workgroup per tile
+ * and paired (where built); else 0.  Results are bit-identical in every
+ * mode.  OZ_ERR_ARG for mode < -3. */
 int ozaki_ctx_set_heff_launch(ozaki_ctx ctx, int mode);
 /* Device bytes that heff plans created afterwards may use for the
  * intermediates T_u = L psi of the first products (FP64 values, and their
@@ -247,12 +255,14 @@ int ozaki_ctx_set_heff_budget(ozaki_ctx ctx, size_t bytes);
  * contiguous parts per XCD, 1 = longest tile first, 2 = whole outputs to
  * the least loaded XCD, heaviest first) and launch (0 = one
  * workgroup per tile, k > 0 = streamed on k compute units,
- * OZ_HEFF_LAUNCH_RESIDENT = the resident kernel, first phase only).  With both
+ * OZ_HEFF_LAUNCH_RESIDENT = the resident kernel, first phase only,
+ * OZ_HEFF_LAUNCH_PAIRED_TERMS = the paired-term kernel, second phase
+ * only).  With both
  * phases fixed a plan times nothing, which reproduces a timed plan's choice
  * (heff_plan_phase) exactly, e.g. for profiling.  OZ_ERR_ARG for an unknown
  * phase, variant, order or launch; a variant not built for the plan's
- * (S, G), or a resident launch not built for it or asked for the second
- * phase, makes heff_plan_create fail with OZ_ERR_ARG. */
+ * (S, G), or a resident or paired-term launch not built for it or asked
+ * for the other phase, makes heff_plan_create fail with OZ_ERR_ARG. */
 int ozaki_ctx_set_heff_phase(ozaki_ctx ctx, int phase, int variant, int order, int launch);
 /* Time every built variant of this GEMM (alpha = 1, beta = 0 into C, one
  * warm-up and three timed calls each) and fix the fastest for (slices,
@@ -361,7 +371,7 @@ int heff_plan_graph_count(heff_plan plan);
  * native FP64 plans). */
 int heff_plan_variants(heff_plan plan, int32_t *first, int32_t *second);
 /* Launch kind of the plan's two grouped phases (0 one workgroup per tile,
- * 1 streamed, 2 resident; -1 for native FP64 plans). */
+ * 1 streamed, 2 resident, 3 paired terms; -1 for native FP64 plans). */
 int heff_plan_launches(heff_plan plan, int32_t *first, int32_t *second);
 /* Total elements of psi for the plan's layout. */
 int64_t heff_vector_length(heff_plan plan);
@@ -369,7 +379,8 @@ int64_t heff_vector_length(heff_plan plan);
  * emulated plan: tile variant, order (0 XCD parts, 1 longest tile first,
  * 2 whole outputs per XCD) and
  * launch (0 one workgroup per tile, k > 0 streamed on k CUs,
- * OZ_HEFF_LAUNCH_RESIDENT resident); all -1 for a native FP64 plan. */
+ * OZ_HEFF_LAUNCH_RESIDENT resident, OZ_HEFF_LAUNCH_PAIRED_TERMS paired
+ * terms); all -1 for a native FP64 plan. */
 int heff_plan_phase(heff_plan plan, int phase, int32_t *variant, int32_t *order, int32_t *launch);
 /* Number of chunks the plan's triple list runs in (ozaki_ctx_set_heff_budget). */
 int heff_plan_chunks(heff_plan plan);

@@ -261,6 +261,7 @@ void output_lpt_order(const std::vector<std::vector<TileWork>> &outputs, std::ve
 }
 
 constexpr int kHeffLaunchResident = OZ_HEFF_LAUNCH_RESIDENT;
+constexpr int kHeffLaunchPairedTerms = OZ_HEFF_LAUNCH_PAIRED_TERMS;
 // workgroups per compute unit the resident schedules are built for, at most
 constexpr int kMaxResidentPerCu = 8;
 
@@ -792,18 +793,22 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
     // Candidates: tile variant x tile order (the XCD order first, the
     // default) x launch: one workgroup per tile; the streamed kernel, whose
     // resident workgroups take tiles from counters and prefetch across
-    // items; or the resident kernel on a precomputed schedule (first phase
+    // items; the resident kernel on a precomputed schedule (first phase
     // only, for the variants it is built for), which streams the K blocks
-    // of consecutive tiles through one ring.
-    struct Run { int v; int order; int kind; int cus; };  // kind 0 per tile, 1 streamed (cus), 2 resident
+    // of consecutive tiles through one ring; or the paired-term kernel
+    // (second phase only, 64 x 64 tiles), eight waves per tile taking two
+    // terms at a time.
+    struct Run { int v; int order; int kind; int cus; };  // kind 0 per tile, 1 streamed (cus), 2 resident, 3 paired terms
     constexpr double kStreamMaxMeanBlocks = 16.0;
-    const int forced = ctx->heff_launch;  // -1 timed, 0 per tile, k > 0 streamed, kHeffLaunchResident
+    const int forced = ctx->heff_launch;  // -1 timed, 0 per tile, k > 0 streamed, resident or paired terms
     const int stream_cus_of = forced > 0 ? std::min(forced, ctx->num_cu) : ctx->num_cu;
     // the launches a phase may use for variant v
     auto kinds_for = [&](int ph, int v) {
         std::vector<int> k;
         if (forced == kHeffLaunchResident) {
             k.push_back(ph == 0 && pair_resident_per_cu(S, G, v) > 0 ? 2 : 0);
+        } else if (forced == kHeffLaunchPairedTerms) {
+            k.push_back(ph == 1 && pair_terms2_ok(S, G, v) ? 3 : 0);
         } else if (forced >= 0) {
             k.push_back(forced > 0 ? 1 : 0);
         } else {
@@ -812,6 +817,7 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
                 k.push_back(1);
                 if (pair_resident_per_cu(S, G, v) > 0) k.push_back(2);
             }
+            if (tuning && ph == 1 && pair_terms2_ok(S, G, v)) k.push_back(3);
         }
         return k;
     };
@@ -859,6 +865,12 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
                     return fail(OZ_ERR_ARG, "heff_plan_create: resident launch not built for phase %d, variant %d", ph, r.v);
                 }
                 r.kind = 2;
+            } else if (l == kHeffLaunchPairedTerms) {
+                if (ph != 1 || !pair_terms2_ok(S, G, r.v)) {
+                    free_plan(P);
+                    return fail(OZ_ERR_ARG, "heff_plan_create: paired-term launch not built for phase %d, variant %d", ph, r.v);
+                }
+                r.kind = 3;
             } else if (l > 0) {
                 r.kind = 1;
                 r.cus = std::min(l, ctx->num_cu);
@@ -914,6 +926,7 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
                         a.stream_cus = kind == 1 ? stream_cus_of : 0;
                         a.nwg = 0;
                         a.wg_off = nullptr;
+                        a.terms2 = kind == 3 ? 1 : 0;
                         const std::vector<TileDesc> *up = &sample;
                         if (kind == 2) {
                             const int nwg = std::min(pair_resident_per_cu(S, G, v), kMaxResidentPerCu) * ctx->num_cu;
@@ -983,6 +996,7 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
             a.stream_cus = run.kind == 1 ? run.cus : 0;
             a.nwg = 0;
             a.wg_off = nullptr;
+            a.terms2 = run.kind == 3 ? 1 : 0;
             TileDesc *d = nullptr;
             if (run.kind == 2) {
                 const int nwg = std::min(pair_resident_per_cu(S, G, run.v), kMaxResidentPerCu) * ctx->num_cu;
@@ -1006,10 +1020,13 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
     P->varR = chosenR.v;
     P->choice[0][0] = chosenL.v;
     P->choice[0][1] = chosenL.order;
-    P->choice[0][2] = chosenL.kind == 2 ? kHeffLaunchResident : chosenL.cus;
+    auto launch_code = [](const Run &r) {
+        return r.kind == 2 ? kHeffLaunchResident : r.kind == 3 ? kHeffLaunchPairedTerms : r.cus;
+    };
+    P->choice[0][2] = launch_code(chosenL);
     P->choice[1][0] = chosenR.v;
     P->choice[1][1] = chosenR.order;
-    P->choice[1][2] = chosenR.kind == 2 ? kHeffLaunchResident : chosenR.cus;
+    P->choice[1][2] = launch_code(chosenR);
     if ((e = hipStreamSynchronize(s)) != hipSuccess) { free_plan(P); return hip_fail(e, "heff_plan_create: sync"); }
     *out = P;
     return OZ_OK;
@@ -1154,7 +1171,7 @@ int heff_plan_variants(heff_plan P, int32_t *first, int32_t *second) {
 
 int heff_plan_launches(heff_plan P, int32_t *first, int32_t *second) {
     if (!P) return fail(OZ_ERR_ARG, "heff_plan_launches: plan is NULL");
-    auto kind = [](const PairArgs &a) { return a.nwg > 0 ? 2 : a.stream_cus > 0 ? 1 : 0; };
+    auto kind = [](const PairArgs &a) { return a.terms2 ? 3 : a.nwg > 0 ? 2 : a.stream_cus > 0 ? 1 : 0; };
     if (first) *first = P->S ? kind(P->chunks[0].argsL) : -1;
     if (second) *second = P->S ? kind(P->chunks[0].argsR) : -1;
     return OZ_OK;

@@ -128,6 +128,9 @@ struct PairArgs {
     // tiles[wg_off[b] .. wg_off[b + 1]) in order
     int32_t nwg;
     const int32_t *wg_off;
+    // grouped, accumulating mode on the 64 x 64 tiles of variant 0: 1 = the
+    // paired-term kernel (eight waves per tile, two terms at a time)
+    int32_t terms2;
 };
 
 // FP64 GEMM term: op(A) (M x K) times op(B) (K x N), both plain FP64.
@@ -232,6 +235,8 @@ hipError_t launch_pair_grouped(int S, int G, int v, const PairArgs &a, hipStream
 // Workgroups of the resident GEMM-mode kernel that fit on one compute unit
 // at once for (S, G, v); 0 where that kernel is not built for the variant.
 int pair_resident_per_cu(int S, int G, int v);
+// Whether the paired-term accumulating kernel is built for (S, G, v).
+bool pair_terms2_ok(int S, int G, int v);
 
 // FP64 MFMA GEMM.  The single launch picks its tile size from the output
 // extent (a.out) and the compute-unit count; the grouped launch takes tiles

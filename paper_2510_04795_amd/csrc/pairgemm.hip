@@ -62,4 +62,18 @@ int pair_resident_per_cu(int S, int G, int v) {
     }
 }
 
+bool pair_terms2_ok(int S, int G, int v) {
+    if (v != 0 || !pair_supported(S, G)) return false;
+    switch (S) {
+        case 2: return pair_terms2_s2(G);
+        case 3: return pair_terms2_s3(G);
+        case 4: return pair_terms2_s4(G);
+        case 5: return pair_terms2_s5(G);
+        case 6: return pair_terms2_s6(G);
+        case 7: return pair_terms2_s7(G);
+        case 8: return pair_terms2_s8(G);
+        default: return false;
+    }
+}
+
 }  // namespace oz

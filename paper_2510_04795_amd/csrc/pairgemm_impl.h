@@ -1392,6 +1392,182 @@ __global__ __launch_bounds__(64 * WM * WN) void k_pair_resident(PairArgs a) {
     }
 }
 
+// ---- paired-term accumulating kernel ---------------------------------------
+// For term lists over few tiles (a Davidson step's sigma of 1024 x 1024 is
+// 256 tiles of 64 x 64), where a workgroup of four waves per tile leaves one
+// wave per SIMD and every wait of that wave idles the matrix cores: eight
+// waves per tile in two groups of four, each group with its own three-stage
+// ring, group g taking the tile's terms 2 r + g in round r.  The FP64 value
+// of each term (the Horner recombination of its diagonal sums) goes through
+// LDS, and each group adds the round's two values, in term order, into its
+// half of the running sums (the lane's values 8 g .. 8 g + 7), so the sums
+// are those of the one-group kernel.  Both rings of a round run as many
+// steps as the longer term has K blocks (the other group's steps past its
+// own blocks load and multiply nothing), so every wave meets the same
+// barriers.
+
+template <int S, int G>
+__host__ __device__ constexpr bool terms2_fits() {
+    return use_ring<S, G, 2, 2, 1, 1, kModeAccum>() && 6 * Cfg<S, G, 2, 2, 1, 1>::STAGE_BYTES <= 156 * 1024;
+}
+
+// One step of a group's ring: as ring_step over `nsteps` steps of which the
+// first `nvalid` have blocks.
+template <int S, int G, typename F, typename LP>
+__device__ __forceinline__ void group_step(v16i (&acc)[G][1][1], F &cur, uint4 *fill, const uint4 *rd, const LP &lp,
+                                           int kb, int nsteps, int nvalid, int wm, int wn, int half, int l32) {
+    using C = Cfg<S, G, 2, 2, 1, 1>;
+    using RA = RingAddr<S, G, 2, 2, 1, 1>;
+    if (kb + 1 < nsteps) {
+        // block kb + 1 (if any) has arrived once only block kb + 2 may still load
+        if (kb + 2 < nvalid)
+            __builtin_amdgcn_s_waitcnt(C::WAIT_NEWEST);
+        else
+            __builtin_amdgcn_s_waitcnt(C::WAIT_ALL);
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+        if (kb + 3 < nvalid) lp.issue(fill, kb + 3);
+    }
+    if (kb < nvalid)
+        AsmStep<S, G>::template run<RA::OA, RA::OB>(acc, cur, RA::a(rd, wm, half, l32), RA::b(rd, wn, half, l32));
+}
+
+// The diagonal sums of a group's term of `nvalid` K blocks over a round of
+// `nsteps` >= nvalid steps; returns with the group's loads all arrived.
+template <int S, int G, typename LP>
+__device__ __forceinline__ void group_ring(v16i (&acc)[G][1][1], uint4 *s0, uint4 *s1, uint4 *s2, const LP &lp,
+                                           int nvalid, int nsteps, int wm, int wn, int half, int l32) {
+    using C = Cfg<S, G, 2, 2, 1, 1>;
+    using RA = RingAddr<S, G, 2, 2, 1, 1>;
+#pragma unroll
+    for (int g = 0; g < G; ++g) acc[g][0][0] = v16i{};
+    if (nsteps == 0) return;
+    // the previous round's reads of LDS (fragments, exchanged values) are done
+    __builtin_amdgcn_s_waitcnt(C::WAIT_LDS);
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    if (0 < nvalid) lp.issue(s0, 0);
+    if (1 < nvalid) lp.issue(s1, 1);
+    if (2 < nvalid) lp.issue(s2, 2);
+    if (2 < nvalid)
+        __builtin_amdgcn_s_waitcnt(C::WAIT_NEWER2);
+    else if (1 < nvalid)
+        __builtin_amdgcn_s_waitcnt(C::WAIT_NEWEST);
+    else
+        __builtin_amdgcn_s_waitcnt(C::WAIT_ALL);
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    // (a group without blocks reads values it never uses)
+    Frags<S, G, 1, 1> f;
+    AsmStep<S, G>::template read<RA::OA, RA::OB>(f, RA::a(s0, wm, half, l32), RA::b(s0, wn, half, l32));
+    int kb = 0;
+    for (; kb + 3 <= nsteps; kb += 3) {
+        group_step<S, G>(acc, f, s0, s1, lp, kb, nsteps, nvalid, wm, wn, half, l32);
+        group_step<S, G>(acc, f, s1, s2, lp, kb + 1, nsteps, nvalid, wm, wn, half, l32);
+        group_step<S, G>(acc, f, s2, s0, lp, kb + 2, nsteps, nvalid, wm, wn, half, l32);
+    }
+    if (kb < nsteps) group_step<S, G>(acc, f, s0, s1, lp, kb, nsteps, nvalid, wm, wn, half, l32);
+    if (kb + 1 < nsteps) group_step<S, G>(acc, f, s1, s2, lp, kb + 1, nsteps, nvalid, wm, wn, half, l32);
+    asm volatile("s_nop 7\n\ts_nop 7\n\ts_nop 7" ::: "memory");
+}
+
+template <int S, int G>
+__global__ __launch_bounds__(512) void k_pair_terms2(PairArgs a) {
+    using C = Cfg<S, G, 2, 2, 1, 1>;
+    using LP = LoadPlan<S, G, 2, 2, 1, 1, 3>;
+    // two rings of three stages; between rounds the first 64 KiB hold the
+    // exchanged term values [group][wave][value][lane]
+    constexpr int kRings = 2 * 3 * C::STAGE;
+    constexpr int kExchange = 2 * 4 * 16 * 64 * 8 / 16;
+    __shared__ uint4 lds[kRings > kExchange ? kRings : kExchange];
+    const TileDesc td = a.tiles[blockIdx.x];
+    if (td.out < 0) return;  // padding of the XCD order
+    OutDesc od = a.outs[td.out];
+    if (a.out_base) od.C = a.out_base + reinterpret_cast<intptr_t>(od.C);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int grp = wave >> 2;
+    const int w4 = wave & 3;
+    const int wm = w4 / 2;
+    const int wn = w4 % 2;
+    const int half = lane >> 5;
+    const int l32 = lane & 31;
+    const int m0 = td.m0, n0 = td.n0;
+    const int j = n0 + wn * 32 + l32;
+    const bool jok = j < od.N;
+    // this group's half of the tile's running sums: the lane's values 8 grp + q
+    double sig[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sig[q] = 0.0;
+    if (od.cont) {
+        // continuing an earlier launch's sums: straight-line loads (outside
+        // the output, of its first element; the value is then dropped)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int r = 8 * grp + q;
+            const int i = m0 + wm * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+            const bool ok = jok && i < od.M;
+            const double v = od.C[ok ? static_cast<int64_t>(i) * od.ldc + j : 0];
+            sig[q] = ok ? v : 0.0;
+        }
+    }
+    uint4 *s0 = lds + grp * 3 * C::STAGE;
+    uint4 *s1 = s0 + C::STAGE;
+    uint4 *s2 = s1 + C::STAGE;
+    double *xch = reinterpret_cast<double *>(lds);
+    const TermDesc *terms = a.terms;
+    for (int ta = td.term_begin; ta < td.term_end; ta += 2) {
+        const bool hb = ta + 1 < td.term_end;
+        const TermDesc Ta = const_term(terms, ta);
+        const TermDesc Tb = const_term(terms, hb ? ta + 1 : ta);
+        const int nka = Ta.kblocks, nkb = hb ? Tb.kblocks : 0;
+        const int nsteps = nka > nkb ? nka : nkb;
+        const TermDesc T = grp ? Tb : Ta;
+        const int nvalid = grp ? nkb : nka;
+        LP lp;
+        lp.init(T.A, T.B, T.a_rows_p, T.b_rows_p, m0, n0, w4, lane);
+        v16i acc[G][1][1];
+        group_ring<S, G>(acc, s0, s1, s2, lp, nvalid, nsteps, wm, wn, half, l32);
+        // every wave is done with the stages before they take the values
+        __syncthreads();
+        if (grp == 0 || hb) {
+            const int32_t fj = jok ? T.f[j] : 0;
+            int32_t ei[16];
+            row_exponents(ei, T.e, od.M, m0 + wm * 32 + 4 * half, jok);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                if (r % kEpilogueGroup == 0) __builtin_amdgcn_sched_barrier(0);
+                const int i = m0 + wm * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+                double c = 0.0;
+                if (jok && i < od.M) {
+                    long long q[G];
+#pragma unroll
+                    for (int g = 0; g < G; ++g) q[g] = acc[g][0][0][r];
+                    c = horner<G>(q, ei[r], fj);
+                }
+                xch[((grp * 4 + w4) * 16 + r) * 64 + lane] = c;
+            }
+        }
+        __syncthreads();
+        // term a's value, then term b's, into this group's half
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int r = 8 * grp + q;
+            const int i = m0 + wm * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+            if (jok && i < od.M) {
+                sig[q] = fma(Ta.alpha, xch[(w4 * 16 + r) * 64 + lane], sig[q]);
+                if (hb) sig[q] = fma(Tb.alpha, xch[((4 + w4) * 16 + r) * 64 + lane], sig[q]);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int r = 8 * grp + q;
+        const int i = m0 + wm * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+        if (jok && i < od.M) od.C[static_cast<int64_t>(i) * od.ldc + j] = sig[q];
+    }
+}
+
 // Tile index -> (tm, tn).  Blocks are dispatched to the 8 XCDs round robin;
 // give every XCD a contiguous range of tiles, walked in groups of `group`
 // tile rows, so the blocks that run together on one L2 share A and B panels.
@@ -1519,6 +1695,15 @@ hipError_t run_grouped_v(const PairArgs &a, hipStream_t s) {
         return hipErrorInvalidValue;
     } else {
         if (a.ntiles == 0) return hipSuccess;
+        if (a.terms2) {
+            if constexpr (V == 0 && terms2_fits<S, G>()) {
+                if (a.mode != kModeAccum) return hipErrorInvalidValue;
+                hipLaunchKernelGGL((k_pair_terms2<S, G>), dim3(a.ntiles), dim3(512), 0, s, a);
+                return hipGetLastError();
+            } else {
+                return hipErrorInvalidValue;
+            }
+        }
         if (a.nwg > 0) {
             if constexpr (resident_fits<S, G, WM, WN, MB, NB>()) {
                 if (a.mode != kModeGemm || !a.wg_off || a.beta != 0.0 || a.Qw) return hipErrorInvalidValue;
@@ -1627,7 +1812,8 @@ hipError_t run_grouped(int v, const PairArgs &a, hipStream_t s) {
 #define OZ_DECLARE_PAIR_S(S_)                                                                   \
     hipError_t pair_single_s##S_(int G, int v, const PairArgs &a, int tiles_m, hipStream_t s);  \
     hipError_t pair_grouped_s##S_(int G, int v, const PairArgs &a, hipStream_t s);              \
-    int pair_resident_s##S_(int G, int v);
+    int pair_resident_s##S_(int G, int v);                                                      \
+    bool pair_terms2_s##S_(int G);
 OZ_DECLARE_PAIR_S(2)
 OZ_DECLARE_PAIR_S(3)
 OZ_DECLARE_PAIR_S(4)
@@ -1656,6 +1842,12 @@ OZ_DECLARE_PAIR_S(8)
         if (G == S_ + 1) return pair::resident_per_cu<S_, S_ + 1>(v);                           \
         if (G == 2 * S_ - 1) return pair::resident_per_cu<S_, 2 * S_ - 1>(v);                   \
         return 0;                                                                               \
+    }                                                                                           \
+    bool pair_terms2_s##S_(int G) {                                                             \
+        if (G == S_) return pair::terms2_fits<S_, S_>();                                        \
+        if (G == S_ + 1) return pair::terms2_fits<S_, S_ + 1>();                                \
+        if (G == 2 * S_ - 1) return pair::terms2_fits<S_, 2 * S_ - 1>();                        \
+        return false;                                                                           \
     }
 
 }  // namespace oz

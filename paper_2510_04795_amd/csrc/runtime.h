@@ -22,7 +22,7 @@ struct ozaki_ctx_s {
     int variant[9][16];
     bool autotune = true;  // heff plans time the variants of their grouped phases
     int heff_launch = -1;  // grouped heff phases: -1 timed choice, 0 one workgroup per tile, k > 0 streamed on k CUs,
-                           // OZ_HEFF_LAUNCH_RESIDENT resident first phase
+                           // OZ_HEFF_LAUNCH_RESIDENT resident first phase, OZ_HEFF_LAUNCH_PAIRED_TERMS paired-term second
     size_t heff_budget = 0;  // bytes for a heff plan's intermediates T; 0 = kHeffDefaultBudget
     // fixed choice per grouped phase of later emulated heff plans (variant < 0:
     // timed): tile variant, order (0 XCD parts, 1 longest tile first), launch

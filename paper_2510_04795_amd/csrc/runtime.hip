@@ -278,7 +278,7 @@ int ozaki_ctx_set_autotune(ozaki_ctx ctx, int enable) {
 int ozaki_ctx_set_heff_phase(ozaki_ctx ctx, int phase, int variant, int order, int launch) {
     if (!ctx) return fail(OZ_ERR_ARG, "ozaki_ctx_set_heff_phase: ctx is NULL");
     if (phase < 0 || phase > 1) return fail(OZ_ERR_ARG, "ozaki_ctx_set_heff_phase: phase = %d", phase);
-    if (variant >= pair_num_variants() || order < 0 || order > 2 || (launch < 0 && launch != OZ_HEFF_LAUNCH_RESIDENT))
+    if (variant >= pair_num_variants() || order < 0 || order > 2 || (launch < 0 && launch != OZ_HEFF_LAUNCH_RESIDENT && launch != OZ_HEFF_LAUNCH_PAIRED_TERMS))
         return fail(OZ_ERR_ARG, "ozaki_ctx_set_heff_phase: variant %d, order %d, launch %d", variant, order, launch);
     ctx->heff_fix[phase][0] = variant < 0 ? -1 : variant;
     ctx->heff_fix[phase][1] = order;
@@ -294,7 +294,7 @@ int ozaki_ctx_set_heff_budget(ozaki_ctx ctx, size_t bytes) {
 
 int ozaki_ctx_set_heff_launch(ozaki_ctx ctx, int mode) {
     if (!ctx) return fail(OZ_ERR_ARG, "ozaki_ctx_set_heff_launch: ctx is NULL");
-    if (mode < OZ_HEFF_LAUNCH_RESIDENT) return fail(OZ_ERR_ARG, "ozaki_ctx_set_heff_launch: mode = %d", mode);
+    if (mode < OZ_HEFF_LAUNCH_PAIRED_TERMS) return fail(OZ_ERR_ARG, "ozaki_ctx_set_heff_launch: mode = %d", mode);
     ctx->heff_launch = mode;
     return OZ_OK;
 }

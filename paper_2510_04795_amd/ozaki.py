@@ -21,6 +21,7 @@ OZ_STATIC_WORKSPACE_BYTES = 96 << 20
 OZ_FLAG_NONFINITE = 1
 OZ_EXP_NONFINITE = -(2 ** 31)
 OZ_HEFF_LAUNCH_RESIDENT = -2
+OZ_HEFF_LAUNCH_PAIRED_TERMS = -3
 PHASES = {1: "slice", 2: "pair", 3: "fp64", 4: "heff_L", 5: "heff_R", 6: "heff_aux"}
 STATUS = {0: "running", 1: "converged", 2: "stagnated", 3: "max_iter"}
 
@@ -258,8 +259,9 @@ class Context:
         """Launch of later heff plans' grouped phases: 0 one workgroup per
         tile, k > 0 streamed on k compute units (capped at the device's),
         OZ_HEFF_LAUNCH_RESIDENT the resident kernel for the first phase
-        where it is built for the tile variant, -1 timed choice for the
-        first phase (default)."""
+        where it is built for the tile variant, OZ_HEFF_LAUNCH_PAIRED_TERMS
+        the paired-term kernel for the second phase where built, -1 timed
+        choice (default)."""
         _check(_lib.ozaki_ctx_set_heff_launch(self.handle, int(mode)), "ozaki_ctx_set_heff_launch")
 
     def set_heff_phase(self, phase: int, variant: int = -1, order: int = 0, launch: int = 0):
@@ -267,7 +269,8 @@ class Context:
         emulated heff plans: tile variant (-1 clears), order (0 XCD parts,
         1 longest tile first, 2 whole outputs per XCD, heaviest first to the
         least loaded), launch (0 per tile, k > 0 streamed on k CUs,
-        OZ_HEFF_LAUNCH_RESIDENT resident, first phase only).
+        OZ_HEFF_LAUNCH_RESIDENT resident, first phase only,
+        OZ_HEFF_LAUNCH_PAIRED_TERMS paired terms, second phase only).
         With both phases fixed a plan times nothing."""
         _check(_lib.ozaki_ctx_set_heff_phase(self.handle, int(phase), int(variant), int(order), int(launch)),
                "ozaki_ctx_set_heff_phase")

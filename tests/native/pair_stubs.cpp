@@ -10,7 +10,8 @@ namespace oz {
 #define OZ_STUB_PAIR_S(S_)                                                                               \
     hipError_t pair_single_s##S_(int, int, const PairArgs &, int, hipStream_t) { return hipErrorInvalidValue; } \
     hipError_t pair_grouped_s##S_(int, int, const PairArgs &, hipStream_t) { return hipErrorInvalidValue; } \
-    int pair_resident_s##S_(int, int) { return 0; }
+    int pair_resident_s##S_(int, int) { return 0; }                                                    \
+    bool pair_terms2_s##S_(int) { return false; }
 OZ_STUB_PAIR_S(2)
 OZ_STUB_PAIR_S(3)
 OZ_STUB_PAIR_S(4)

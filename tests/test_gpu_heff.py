@@ -223,23 +223,24 @@ def test_sparse_fp64(oz):
         assert np.all(np.abs(sig[b] - ref[b]) <= 2 * K * u * mag[b] + 1e-300), b
 
 
-@pytest.mark.parametrize("launch", [-1, 0, 100000, -2])
+@pytest.mark.parametrize("launch", [-1, 0, 100000, -2, -3])
 def test_sparse_full_size_sampled_blocks(oz, launch):
     """The 40-sector, 2000-triple batch; sigma blocks depend only on their own
     triples, so the oracle recomputes a few blocks alone: the three with the
     fewest triples and the three with the most (the longest ordered
     accumulation chains).  Timed launch choice, one workgroup per tile, the
-    streamed kernel on every CU, and the resident first phase on the 64 x 64
-    tiles (every workgroup walks some 65 tiles of 1 to 47 K blocks), whose
-    whole sigma must also equal the per-tile launch's."""
+    streamed kernel on every CU, the resident first phase on the 64 x 64
+    tiles (every workgroup walks some 65 tiles of 1 to 47 K blocks) and the
+    paired-term second phase (terms of different lengths paired), the last
+    two also against the per-tile launch's whole sigma."""
     ozaki, ctx, torch = oz
     prob = wl.heff_sparse()
     ctx.set_heff_launch(launch)
-    if launch == ozaki.OZ_HEFF_LAUNCH_RESIDENT:
+    if launch < -1:
         ctx.set_variant(6, 0, 0)
     try:
         plan, dpsi, keep = sparse_plan(ozaki, ctx, torch, prob, 6)
-        if launch == ozaki.OZ_HEFF_LAUNCH_RESIDENT:
+        if launch < -1:
             ctx.set_heff_launch(0)
             plan0, _, keep0 = sparse_plan(ozaki, ctx, torch, prob, 6)
             assert plan0.launches == (0, 0)
@@ -250,8 +251,10 @@ def test_sparse_full_size_sampled_blocks(oz, launch):
         assert plan.launches == ((1, 1) if launch else (0, 0))
     elif launch == ozaki.OZ_HEFF_LAUNCH_RESIDENT:
         assert plan.launches == (2, 0) and plan.phase(0)[2] == launch
+    elif launch == ozaki.OZ_HEFF_LAUNCH_PAIRED_TERMS:
+        assert plan.launches == (0, 3) and plan.phase(1)[2] == launch
     out = plan.apply(dpsi)
-    if launch == ozaki.OZ_HEFF_LAUNCH_RESIDENT:
+    if launch < -1:
         assert torch.equal(out, plan0.apply(dpsi))
     sig = wl.unflatten_sparse(prob, out.cpu().numpy())
     counts = {}
@@ -523,11 +526,67 @@ def test_resident_launch_bitexact(oz, S, G):
     assert 2 in kinds
 
 
-def test_resident_second_phase_refused(oz):
+@pytest.mark.parametrize("S,G", [(6, 6), (5, 6), (4, 4), (3, 5), (2, 3), (6, 7)])
+def test_paired_terms_bitexact(oz, S, G):
+    """The paired-term second phase (eight waves per 64 x 64 tile, two
+    groups with a ring each taking the terms two at a time, their FP64 values
+    added in term order through LDS): the oracle's bits on a dense problem
+    with an odd number of terms per tile (the last round has one term), a
+    sparse one whose paired terms differ in length (the shorter group's
+    steps load and multiply nothing) and one of 1- to 40-state sectors, in
+    one chunk and in chunks that continue the sums; and the per-tile
+    launch's bits."""
+    ozaki, ctx, torch = oz
+    L, R, psi = wl.heff_dense(D=70, kop=3, phys=4, seed=90 + S)
+    ref_d = oracle.heff_dense(L, R, psi, S=S, G=G)
+    probs = [small_sparse(95 + S),
+             wl.heff_sparse(n_sectors=6, n_triples=30, kop=3, median=6, sigma_log=1.2, lo_hi=(1, 40), density=0.5,
+                            reach=2, U=8, seed=5)]
+    refs = [oracle.heff_sparse(p, S=S, G=G) for p in probs]
+    try:
+        ctx.set_variant(S, G, 0)
+        for budget in (0, 1):
+            ctx.set_heff_budget(budget)
+            ctx.set_heff_launch(ozaki.OZ_HEFF_LAUNCH_PAIRED_TERMS)
+            plan, dpsi, keep = dense_plan(ozaki, ctx, torch, L, R, psi, S, G)
+            assert plan.launches == (0, 3) and (plan.chunks > 1) == (budget == 1)
+            out = plan.apply(dpsi)
+            assert_bitexact(out.cpu().numpy().reshape(psi.shape), ref_d, "dense budget %d" % budget)
+            ctx.set_heff_launch(0)
+            plan0, _, keep0 = dense_plan(ozaki, ctx, torch, L, R, psi, S, G)
+            assert torch.equal(out, plan0.apply(dpsi))
+            for prob, ref in zip(probs, refs):
+                ctx.set_heff_launch(ozaki.OZ_HEFF_LAUNCH_PAIRED_TERMS)
+                plan, dpsi, keep = sparse_plan(ozaki, ctx, torch, prob, S, G)
+                assert plan.launches == (0, 3)
+                sig = wl.unflatten_sparse(prob, plan.apply(dpsi).cpu().numpy())
+                for b in prob.psi_blocks:
+                    assert_bitexact(sig[b], ref[b], "sparse budget %d block %s" % (budget, b))
+    finally:
+        ctx.set_heff_budget(0)
+        ctx.set_heff_launch(-1)
+        ctx.set_variant(S, G, -1)
+
+
+def test_fixed_launch_phases(oz):
     ozaki, ctx, torch = oz
     L, R, psi = wl.heff_dense(D=40, kop=2, phys=4, seed=2)
     res = ozaki.OZ_HEFF_LAUNCH_RESIDENT
     try:
+        # the paired-term kernel serves the second phase only, on variant 0
+        ctx.set_heff_phase(0, 0, 0, ozaki.OZ_HEFF_LAUNCH_PAIRED_TERMS)
+        ctx.set_heff_phase(1, 0, 0, 0)
+        with pytest.raises(ozaki.OzakiError):
+            dense_plan(ozaki, ctx, torch, L, R, psi, 6)
+        ctx.set_heff_phase(0, 0, 0, 0)
+        ctx.set_heff_phase(1, 3, 0, ozaki.OZ_HEFF_LAUNCH_PAIRED_TERMS)
+        with pytest.raises(ozaki.OzakiError):
+            dense_plan(ozaki, ctx, torch, L, R, psi, 6)
+        ctx.set_heff_phase(1, 0, 1, ozaki.OZ_HEFF_LAUNCH_PAIRED_TERMS)
+        plan, dpsi, keep = dense_plan(ozaki, ctx, torch, L, R, psi, 6)
+        assert plan.phase(1) == (0, 1, ozaki.OZ_HEFF_LAUNCH_PAIRED_TERMS) and plan.launches == (0, 3)
+        assert_bitexact(plan.apply(dpsi).cpu().numpy().reshape(psi.shape), oracle.heff_dense(L, R, psi, S=6),
+                        "fixed paired-term phase")
         ctx.set_heff_phase(0, 0, 0, 0)
         ctx.set_heff_phase(1, 0, 0, res)
         with pytest.raises(ozaki.OzakiError):
@@ -550,7 +609,7 @@ def test_resident_second_phase_refused(oz):
 def test_launch_modes(oz):
     ozaki, ctx, torch = oz
     with pytest.raises(ozaki.OzakiError):
-        ctx.set_heff_launch(-3)
+        ctx.set_heff_launch(-4)
     L, R, psi = wl.heff_dense(D=40, kop=2, phys=4, seed=1)
     try:
         ctx.set_heff_launch(0)
@@ -563,9 +622,10 @@ def test_launch_modes(oz):
         assert torch.equal(a, plan2.apply(dpsi))
     finally:
         ctx.set_heff_launch(-1)
-    # timed choice: only the first phase may stream or run resident
+    # timed choice: only the first phase may stream or run resident, only
+    # the second pair its terms
     plan3, _, keep3 = dense_plan(ozaki, ctx, torch, L, R, psi, 6)
-    assert plan3.launches[0] in (0, 1, 2) and plan3.launches[1] == 0
+    assert plan3.launches[0] in (0, 1, 2) and plan3.launches[1] in (0, 3)
     assert torch.equal(a, plan3.apply(dpsi))
     plan, dpsi, keep = dense_plan(ozaki, ctx, torch, L, R, psi, 0)
     assert plan.launches == (-1, -1)
