@@ -695,7 +695,7 @@ def main():
                     help="rows of the n = 8192 product checked against the double-double reference")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target length of the timed CPU-oracle sample")
-    ap.add_argument("--full-json", default=os.path.join("gpurun_out", "bench_full.json"),
+    ap.add_argument("--full-json", default="bench_full.json",
                     help="file for the full record (every section's tables); '' to skip")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--oracle-seconds", type=float, default=10.0,

@@ -1,7 +1,7 @@
 // Sanitizer run of the library's host code (test infrastructure): the
 // csrc/*.hip files (the per-S pair-GEMM kernels replaced by pair_stubs.cpp)
 // are compiled with -fsanitize=address,undefined on their host side and
-// linked with this driver by tests/test_sanitizers.py.  No GPU is touched: the driver builds a context
+// linked with this program by tests/test_sanitizers.py.  No GPU is touched: the program builds a context
 // by hand and calls the entry points with arguments their checks reject
 // before any HIP call (sizes, leading dimensions, slice and diagonal
 // counts, block layouts and triples of an effective Hamiltonian), plus the
