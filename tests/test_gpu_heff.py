@@ -514,12 +514,18 @@ def test_resident_launch_bitexact(oz, S, G):
             assert torch.equal(out, plan0.apply(dpsi))
             for prob, ref in zip(probs, refs):
                 ctx.set_heff_launch(res)
-                plan, dpsi, keep = sparse_plan(ozaki, ctx, torch, prob, S, G)
-                assert plan.launches[0] in (0, 2) and plan.launches[1] == 0
-                sig = wl.unflatten_sparse(prob, plan.apply(dpsi).cpu().numpy())
-                for b in prob.psi_blocks:
-                    assert_bitexact(sig[b], ref[b], "sparse variant %d block %s" % (v, b))
+                # one chunk, and chunks with a schedule each that continue the sums
+                for budget in (0, 1):
+                    ctx.set_heff_budget(budget)
+                    plan, dpsi, keep = sparse_plan(ozaki, ctx, torch, prob, S, G)
+                    assert plan.launches[0] in (0, 2) and plan.launches[1] == 0
+                    assert (plan.chunks > 1) == (budget == 1)
+                    sig = wl.unflatten_sparse(prob, plan.apply(dpsi).cpu().numpy())
+                    for b in prob.psi_blocks:
+                        assert_bitexact(sig[b], ref[b], "sparse variant %d budget %d block %s" % (v, budget, b))
+                ctx.set_heff_budget(0)
     finally:
+        ctx.set_heff_budget(0)
         ctx.set_heff_launch(-1)
         ctx.set_variant(S, G, -1)
     # built for the 8-wave tiles with G <= 8, and for the 64 x 64 tile from S = 3, G = 5 to S = 6
