@@ -764,10 +764,8 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
     const int fixed = ctx->variant[S][G];
     std::vector<int> cands;
     for (int v = 0; v < pair_num_variants(); ++v)
-        if (pair_grouped_variant_ok(G, v) && (fixed < 0 ? (ctx->autotune || v == pair_default_variant(G)) : v == fixed))
+        if (pair_variant_ok(G, v) && (fixed < 0 ? (ctx->autotune || v == pair_default_variant(G)) : v == fixed))
             cands.push_back(v);
-    // a variant fixed for the single GEMM that the grouped launches lack
-    if (cands.empty()) cands.push_back(pair_default_variant(G));
     // Autotuning on the first chunk: time each candidate (tile variant, tile
     // order, launch) on its whole tile list or an even sample of it, scaled
     // by the sample's share of the total cost; inputs are zeroed scratch (the
@@ -778,7 +776,7 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     // both phases fixed by the context: nothing is timed
     const bool fixed_phases = ctx->heff_fix[0][0] >= 0 && ctx->heff_fix[1][0] >= 0;
-    if (fixed_phases && (!pair_grouped_variant_ok(G, ctx->heff_fix[0][0]) || !pair_grouped_variant_ok(G, ctx->heff_fix[1][0]))) {
+    if (fixed_phases && (!pair_variant_ok(G, ctx->heff_fix[0][0]) || !pair_variant_ok(G, ctx->heff_fix[1][0]))) {
         free_plan(P);
         return fail(OZ_ERR_ARG, "heff_plan_create: fixed tile variant not built for ndiag %d", G);
     }

@@ -228,8 +228,6 @@ struct PairShape { int bm, bn; };
 bool pair_supported(int S, int G);
 int pair_num_variants();
 bool pair_variant_ok(int G, int v);
-// Whether the grouped launches (H_eff phases) are built for variant v.
-bool pair_grouped_variant_ok(int G, int v);
 int pair_default_variant(int G);
 PairShape pair_shape(int S, int G, int v);
 hipError_t launch_pair_single(int S, int G, int v, const PairArgs &a, int tiles_m, hipStream_t s);

@@ -12,8 +12,6 @@ int pair_num_variants() { return pair::kNumVariants; }
 
 bool pair_variant_ok(int G, int v) { return v >= 0 && v < pair::kNumVariants && pair::variant_fits(G, v); }
 
-bool pair_grouped_variant_ok(int G, int v) { return v >= 0 && v < pair::kNumVariants && pair::grouped_fits(G, v); }
-
 int pair_default_variant(int G) { return pair::default_variant(G); }
 
 PairShape pair_shape(int S, int G, int v) {

@@ -401,21 +401,11 @@ struct RingAddr {
     static constexpr int OB = 2 * C::BN * 16;
     // LDS byte addresses of this lane's A and B fragments of slice 0 in a stage
     __device__ __forceinline__ static unsigned a(const uint4 *stage, int wm, int half, int l32) {
-        return static_cast<unsigned>(reinterpret_cast<uintptr_t>(stage + half * C::BM + wm * MB * 32 + l32));
+        return static_cast<unsigned>(reinterpret_cast<uintptr_t>(stage + half * C::BM + wm * 32 + l32));
     }
     __device__ __forceinline__ static unsigned b(const uint4 *stage, int wn, int half, int l32) {
         return static_cast<unsigned>(reinterpret_cast<uintptr_t>(stage + 2 * S * C::BM + half * C::BN + wn * 32 + l32));
     }
-};
-
-// The generated step for waves of MB row blocks of 32 (one column block).
-template <int S, int G, int MB>
-struct StepFor {
-    using type = AsmStep<S, G>;
-};
-template <int S, int G>
-struct StepFor<S, G, 2> {
-    using type = AsmStep2<S, G>;
 };
 
 template <int S, int G, int WM, int WN, int MB, int NB, typename F, typename LP>
@@ -433,7 +423,7 @@ __device__ __forceinline__ void ring_step(v16i (&acc)[G][MB][NB], F &cur, uint4 
         if (kb + 3 < nkb) lp.issue(fill, kb + 3);
     }
     // the last step reads a stage no load is pending on; the values go unused
-    StepFor<S, G, MB>::type::template run<RA::OA, RA::OB>(acc, cur, RA::a(rd, wm, half, l32), RA::b(rd, wn, half, l32));
+    AsmStep<S, G>::template run<RA::OA, RA::OB>(acc, cur, RA::a(rd, wm, half, l32), RA::b(rd, wn, half, l32));
 }
 
 template <int S, int G, int WM, int WN, int MB, int NB>
@@ -451,9 +441,7 @@ __device__ __forceinline__ void pair_mainloop_ring(v16i (&acc)[G][MB][NB], uint4
     const int nkb = T.kblocks;
 
 #pragma unroll
-    for (int g = 0; g < G; ++g)
-#pragma unroll
-        for (int mb = 0; mb < MB; ++mb) acc[g][mb][0] = v16i{};
+    for (int g = 0; g < G; ++g) acc[g][0][0] = v16i{};
     if (nkb == 0) return;
 
     LoadPlan<S, G, WM, WN, MB, NB> lp;
@@ -473,7 +461,7 @@ __device__ __forceinline__ void pair_mainloop_ring(v16i (&acc)[G][MB][NB], uint4
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
     Frags<S, G, MB, NB> f;
-    StepFor<S, G, MB>::type::template read<RA::OA, RA::OB>(f, RA::a(lds0, wm, half, l32), RA::b(lds0, wn, half, l32));
+    AsmStep<S, G>::template read<RA::OA, RA::OB>(f, RA::a(lds0, wm, half, l32), RA::b(lds0, wn, half, l32));
     // Blocks are taken three at a time so each stage keeps its own object;
     // the loop has a single exit and the last nkb % 3 blocks are peeled.
     int kb = 0;
@@ -578,10 +566,6 @@ __host__ __device__ constexpr bool use_prefetch() {
 // term loop keeps more live: at S = G = 7 it spills without them).
 template <int S, int G, int WM, int WN, int MB, int NB, int MODE>
 __host__ __device__ constexpr bool use_ring() {
-    // the 128 x 64 tile of four waves with two row blocks each at G = 7, 8
-    // (one wave per SIMD, accumulators in the accumulation registers)
-    if constexpr (MB == 2 && NB == 1 && WM * WN == 4 && (G == 7 || G == 8))
-        return AsmStep2<S, G>::available && 3 * Cfg<S, G, WM, WN, MB, NB>::STAGE_BYTES <= 156 * 1024;
     return AsmStep<S, G>::available && MB == 1 && NB == 1 &&
            (WM * WN == 8 || (WM * WN == 4 && wave_budget_left<S, G, WM, WN, MB, NB, MODE>(1, 4) < 128 &&
                              6 * Cfg<S, G, WM, WN, MB, NB>::STAGE_BYTES <= 160 * 1024)) &&
@@ -1642,9 +1626,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_pair_grouped(PairArgs a) {
 // Tile variants: WM x WN waves of MB x NB blocks of 32 x 32 outputs.
 //   v  waves  wave tile  block tile  built when (registers per wave)
 //   0  2x2    1x1        64 x 64     always
-//   1  2x2    2x1        128 x 64    32 G <= 192, or G = 7, 8 at one wave
-//                                      per SIMD (accumulators in the
-//                                      accumulation registers, ring)
+//   1  2x2    2x1        128 x 64    32 G <= 192
 //   2  2x2    2x2        128 x 128   64 G <= 192
 //   3  4x2    1x1        128 x 64    16 G <= 128 (two waves per SIMD)
 //   4  2x4    1x1        64 x 128    16 G <= 128
@@ -1660,21 +1642,17 @@ __host__ __device__ constexpr int variant_mb(int v) { return v == 1 || v == 2 ||
 __host__ __device__ constexpr int variant_nb(int v) { return v == 2 ? 2 : 1; }
 __host__ __device__ constexpr bool variant_fits(int G, int v) {
     return v == 0 ? true
-         : v == 1 ? 32 * G <= 192 || G == 7 || G == 8
+         : v == 1 ? 32 * G <= 192
          : v == 2 ? 64 * G <= 192
          : v == 3 || v == 4 ? 16 * G <= 128
          : v == 5 ? 32 * G <= 160
          : v == 6 ? 16 * G <= 64
          : false;
 }
-// The grouped launches (H_eff phases) take the variants except the 128 x 64
-// tile at G = 7, 8, which serves the single GEMM only: its term loop and
-// fused maxima would not fit the registers left beside the accumulators.
-__host__ __device__ constexpr bool grouped_fits(int G, int v) { return variant_fits(G, v) && !(v == 1 && G >= 7); }
 __host__ __device__ constexpr int variant_bm(int v) { return variant_wm(v) * variant_mb(v) * 32; }
 __host__ __device__ constexpr int variant_bn(int v) { return variant_wn(v) * variant_nb(v) * 32; }
 // default before tuning: the 128 x 64 four-wave tile where it fits
-__host__ __device__ constexpr int default_variant(int G) { return 32 * G <= 192 ? 1 : 0; }
+__host__ __device__ constexpr int default_variant(int G) { return variant_fits(G, 1) ? 1 : 0; }
 
 template <int S, int G, int V>
 hipError_t run_single_v(const PairArgs &a, int tiles_m, hipStream_t s) {
@@ -1713,7 +1691,7 @@ template <int S, int G, int V>
 hipError_t run_grouped_v(const PairArgs &a, hipStream_t s) {
     constexpr int WM = variant_wm(V), WN = variant_wn(V), MB = variant_mb(V), NB = variant_nb(V);
     constexpr int NT = 64 * WM * WN;
-    if constexpr (!grouped_fits(G, V)) {
+    if constexpr (!variant_fits(G, V)) {
         return hipErrorInvalidValue;
     } else {
         if (a.ntiles == 0) return hipSuccess;
@@ -1773,7 +1751,7 @@ hipError_t run_grouped_v(const PairArgs &a, hipStream_t s) {
 template <int S, int G, int V>
 int resident_per_cu_v() {
     constexpr int WM = variant_wm(V), WN = variant_wn(V), MB = variant_mb(V), NB = variant_nb(V);
-    if constexpr (!grouped_fits(G, V)) {
+    if constexpr (!variant_fits(G, V)) {
         return 0;
     } else if constexpr (!resident_fits<S, G, WM, WN, MB, NB>()) {
         return 0;

@@ -215,14 +215,13 @@ def test_fp64_mfma_large_tiles_within_gamma_bound(oz, transa, transb):
     assert np.all(err <= gam * mag * (1 + 1e-12) + 4 * u * np.abs(ref))
 
 
-@pytest.mark.parametrize("S,variant", [(6, -1), (7, 4), (7, 0), (6, 0), (7, 1)])
+@pytest.mark.parametrize("S,variant", [(6, -1), (7, 4), (7, 0), (6, 0)])
 def test_dgemm_full_size_sampled_rows(oz, S, variant):
     """n = 8192: S = 6 with the default tile, and S = G = 7 on the 64 x 128
-    tile (three-stage ring), on the 64 x 64 tile (two-stage ring) and on the
-    128 x 64 tile of four two-block waves (three-stage ring, accumulators in
-    the accumulation registers), S = 6 on the 64 x 64 tile (three-stage
-    ring); checked on sampled rows (exponents are per row of A and per
-    column of B, so rows are independent)."""
+    tile (three-stage ring) and on the 64 x 64 tile (two-stage ring, the
+    launch the benchmark's tuning takes for its equal-error line), S = 6 on
+    the 64 x 64 tile (three-stage ring); checked on sampled rows (exponents
+    are per row of A and per column of B, so rows are independent)."""
     ozaki, ctx, torch = oz
     n = 8192
     A, B = wl.gemm_pair(n, U=10, seed=0)
