@@ -718,7 +718,8 @@ def main():
                     help="fixed phase choices of the emulated H_eff plans, e.g. L=0:1:256,R=4:1:0 "
                          "(variant:order:launch per phase, as the bench log prints them); nothing is timed")
     ap.add_argument("--heff-launch", type=int, default=-1,
-                    help="H_eff grouped launch: -1 timed choice, 0 one workgroup per tile, k > 0 streamed on k CUs")
+                    help="H_eff grouped launch: -1 timed choice, 0 one workgroup per tile, k > 0 streamed on k "
+                         "CUs, -2 resident first phase, -3 paired-term second phase")
     ap.add_argument("--dd-samples", type=int, default=3,
                     help="(i, j) pairs of the dense sigma checked against double-double (4 columns each)")
     ap.add_argument("--dav-d", type=int, default=1024)
