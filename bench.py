@@ -444,6 +444,48 @@ def davidson_section(args, ozaki, ctx, torch):
     return out
 
 
+def dispatch_section(args, ozaki, ctx, torch):
+    """Emulated (S = 6) against native FP64 on the block-sparse batch by block
+    size: the triples grouped by their largest sector, each group applied
+    as a plan of its own, best of 3 x 20 applies per path.  Whether a
+    per-block choice between the two paths could gain anything."""
+    from paper_2510_04795_amd import workloads as wl
+    prob = wl.heff_sparse()
+    d = prob.dims
+    out = []
+    for lo, hi in [(1, 64), (65, 128), (129, 256), (257, 512), (513, 1 << 30)]:
+        tr = [t for t in prob.triples if lo <= max(d[t[1]], d[t[2]], d[t[3]], d[t[4]]) <= hi]
+        if not tr:
+            continue
+        sub = wl.HeffSparse(dims=prob.dims, psi_blocks=prob.psi_blocks, psi=prob.psi, L=prob.L, R=prob.R,
+                            triples=tr)
+        layout, Lf, Rf, pf, triples = wl.flatten_sparse(sub)
+        psi = torch.from_numpy(pf).cuda()
+        r = {"largest_sector": [lo, hi], "triples": len(tr)}
+        for S in (6, 0):
+            plan, _, keep = heff_flat_plan(ozaki, ctx, torch, layout, Lf, Rf, triples, S, 0)
+            sig = plan.apply(psi)
+            for _ in range(5):
+                plan.apply(psi, sig)
+            torch.cuda.synchronize()
+            best = float("inf")
+            for _ in range(3):
+                t0 = time.perf_counter()
+                for _ in range(20):
+                    plan.apply(psi, sig)
+                torch.cuda.synchronize()
+                best = min(best, (time.perf_counter() - t0) / 20 * 1e3)
+            r["flops"] = plan.flops
+            r["emulated_ms" if S else "fp64_ms"] = round(best, 4)
+            plan.close()
+            del keep
+        r["fp64_over_emulated"] = round(r["fp64_ms"] / r["emulated_ms"], 3)
+        log("[bench] dispatch by size: largest sector %d..%d, %d triples: emulated %.3f ms, FP64 %.3f ms (x%.2f)"
+            % (lo, hi, len(tr), r["emulated_ms"], r["fp64_ms"], r["fp64_over_emulated"]))
+        out.append(r)
+    return out
+
+
 def stability_section(args, ozaki, ctx, torch):
     """Low-slice stability of the two Krylov solvers (the paper's numerical
     stability study): for several independent H_eff problems (standing in
@@ -700,8 +742,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--oracle-seconds", type=float, default=10.0,
                     help="budget of each bounded oracle sample in the oracle section")
-    ap.add_argument("--sections", default="gemm,dense,sparse,davidson,stability,rdm,sweep,oracle",
-                    help="comma list of gemm, dense, sparse, davidson, stability, rdm, sweep, oracle; without gemm "
+    ap.add_argument("--sections", default="gemm,dense,sparse,davidson,dispatch,stability,rdm,sweep,oracle",
+                    help="comma list of gemm, dense, sparse, davidson, dispatch, stability, rdm, sweep, oracle; without gemm "
                          "(profiling runs) the last line holds the sections' records, not the headline")
     ap.add_argument("--gemm-configs", default="",
                     help="comma list of S:G for the GEMM section (default: S = 4..8, G in {S, S+1})")
@@ -793,6 +835,8 @@ def main():
             layout, Lf, Rf, pf, triples, heff_slices(args))
     if "davidson" in sections:
         extra["davidson"] = davidson_section(args, ozaki, ctx, torch)
+    if "dispatch" in sections:
+        extra["dispatch_by_size"] = dispatch_section(args, ozaki, ctx, torch)
     if "stability" in sections:
         extra["stability"] = stability_section(args, ozaki, ctx, torch)
     if "rdm" in sections:
