@@ -574,6 +574,42 @@ def test_paired_terms_bitexact(oz, S, G):
         ctx.set_variant(S, G, -1)
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_random_sparse_every_launch(oz, seed):
+    """Seeded random block-sparse problems (5 to 9 sectors of 1 to 200
+    states, so tiles of one K block, edges inside a 32-block and paired terms
+    of unequal length all occur) under every launch of the grouped phases:
+    one workgroup per tile, streamed, resident first phase, paired-term
+    second phase, and the timed choice; S from 3 to 8: the oracle's bits."""
+    ozaki, ctx, torch = oz
+    rng = np.random.default_rng(1000 + seed)
+    S = int(rng.integers(3, 9))
+    G = [S, S + 1][int(rng.integers(0, 2))] if S < 8 else S
+    prob = wl.heff_sparse(n_sectors=int(rng.integers(5, 10)), n_triples=int(rng.integers(20, 90)),
+                          kop=int(rng.integers(2, 6)), median=float(rng.uniform(6, 100)), sigma_log=1.0,
+                          lo_hi=(1, 200), density=float(rng.uniform(0.3, 0.6)), reach=2, U=10, seed=2000 + seed)
+    ref = oracle.heff_sparse(prob, S=S, G=G)
+    res, paired = ozaki.OZ_HEFF_LAUNCH_RESIDENT, ozaki.OZ_HEFF_LAUNCH_PAIRED_TERMS
+    kinds = set()
+    try:
+        # the 64 x 64 tile (resident up to S = 6, paired terms) and the
+        # 8-wave 128 x 64 tile (resident at every S here)
+        for v in (0, 3):
+            ctx.set_variant(S, G, v)
+            for launch in (0, 100000, res, paired, -1):
+                ctx.set_heff_launch(launch)
+                plan, dpsi, keep = sparse_plan(ozaki, ctx, torch, prob, S, G)
+                kinds.update(plan.launches)
+                sig = wl.unflatten_sparse(prob, plan.apply(dpsi).cpu().numpy())
+                for b in prob.psi_blocks:
+                    assert_bitexact(sig[b], ref[b], "seed %d S=%d G=%d variant %d launch %d (kinds %s) block %s"
+                                    % (seed, S, G, v, launch, plan.launches, b))
+        assert {0, 1, 2} <= kinds
+    finally:
+        ctx.set_heff_launch(-1)
+        ctx.set_variant(S, G, -1)
+
+
 def test_fixed_launch_phases(oz):
     ozaki, ctx, torch = oz
     L, R, psi = wl.heff_dense(D=40, kop=2, phys=4, seed=2)
