@@ -287,3 +287,37 @@ def test_dgemm_vector_shapes_zero_rows_and_extreme_exponents(oz, S, G):
     for (a, b) in [(A, B), (A[:1], B), (A, B[:, :1]), (A[:1], B[:, :1])]:
         got = ctx.dgemm(dev(torch, a), dev(torch, b), slices=S, ndiag=G).cpu().numpy()
         assert_bitexact(got, oracle.ozaki_dgemm(a, b, S, G), "shape %s x %s" % (a.shape, b.shape))
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_shapes_every_variant(oz, seed):
+    """Seeded random products: shapes from 1 to 300 drawn near multiples of
+    32 and 64 (tile edges one inside and one past a block), random
+    transposes, alpha and beta, and (S, G) from every built combination,
+    under every tile variant: the oracle's bits."""
+    ozaki, ctx, torch = oz
+    rng = np.random.default_rng(5000 + seed)
+
+    def dim():
+        base = int(rng.choice([1, 32, 64, 96, 128, 160, 192, 256, 288]))
+        return max(1, base + int(rng.integers(-1, 2)) * int(rng.integers(0, 2)) + int(rng.integers(0, 3)))
+
+    S, G = SG[int(rng.integers(0, len(SG)))]
+    M, N, K = dim(), dim(), dim()
+    transa, transb = ("N", "T")[int(rng.integers(0, 2))], ("N", "T")[int(rng.integers(0, 2))]
+    alpha, beta = float(rng.choice([1.0, -1.5, 0.5])), float(rng.choice([0.0, 1.0, -0.25]))
+    A = wl.wide_normal(rng, (M, K), int(rng.integers(0, 31)))
+    B = wl.wide_normal(rng, (K, N), int(rng.integers(0, 31)))
+    As = A.T.copy() if transa == "T" else A
+    Bs = B.T.copy() if transb == "T" else B
+    C0 = rng.standard_normal((M, N))
+    ref = oracle.ozaki_dgemm(As, Bs, S, G, alpha=alpha, beta=beta, C=C0, transa=transa, transb=transb)
+    try:
+        for (v, tm, tn) in ozaki.pair_variants(S, G):
+            ctx.set_variant(S, G, v)
+            got = ctx.dgemm(dev(torch, As), dev(torch, Bs), slices=S, ndiag=G, alpha=alpha, beta=beta,
+                            C=dev(torch, C0), transa=transa, transb=transb).cpu().numpy()
+            assert_bitexact(got, ref, "seed %d S=%d G=%d %dx%dx%d %s%s a=%g b=%g variant %d"
+                            % (seed, S, G, M, N, K, transa, transb, alpha, beta, v))
+    finally:
+        ctx.set_variant(S, G, -1)
