@@ -610,6 +610,33 @@ def test_random_sparse_every_launch(oz, seed):
         ctx.set_variant(S, G, -1)
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_random_dense_every_launch(oz, seed):
+    """Seeded random dense problems (D from 5 to 100, phys 1, 2, 4 or 16,
+    1 to 5 operator pairs, so right dimensions off the 32-column groups
+    and the unfused exponent pass occur) under every grouped launch, S from
+    3 to 8: the oracle's bits."""
+    ozaki, ctx, torch = oz
+    rng = np.random.default_rng(3000 + seed)
+    S = int(rng.integers(3, 9))
+    G = [S, S + 1][int(rng.integers(0, 2))] if S < 8 else S
+    D, phys, kop = int(rng.integers(5, 101)), int(rng.choice([1, 2, 4, 16])), int(rng.integers(1, 6))
+    L, R, psi = wl.heff_dense(D=D, kop=kop, phys=phys, seed=4000 + seed)
+    ref = oracle.heff_dense(L, R, psi, S=S, G=G)
+    try:
+        for v in (0, 3):
+            ctx.set_variant(S, G, v)
+            for launch in (0, 100000, ozaki.OZ_HEFF_LAUNCH_RESIDENT, ozaki.OZ_HEFF_LAUNCH_PAIRED_TERMS, -1):
+                ctx.set_heff_launch(launch)
+                plan, dpsi, keep = dense_plan(ozaki, ctx, torch, L, R, psi, S, G)
+                got = plan.apply(dpsi).cpu().numpy().reshape(psi.shape)
+                assert_bitexact(got, ref, "seed %d S=%d G=%d D=%d phys %d kop %d variant %d launch %d (kinds %s)"
+                                % (seed, S, G, D, phys, kop, v, launch, plan.launches))
+    finally:
+        ctx.set_heff_launch(-1)
+        ctx.set_variant(S, G, -1)
+
+
 def test_fixed_launch_phases(oz):
     ozaki, ctx, torch = oz
     L, R, psi = wl.heff_dense(D=40, kop=2, phys=4, seed=2)
