@@ -349,7 +349,8 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *layout,
                      const double *L_data, const double *R_data, int32_t n_triples,
                      const heff_triple *triples, const double *diag, int slices, int ndiag,
                      void *stream);
-/* sigma = H_eff psi (sigma overwritten; psi and sigma must not overlap).
+/* sigma = H_eff psi (sigma overwritten; psi and sigma, n elements each,
+ * must not overlap: OZ_ERR_ARG if their address ranges intersect).
  * One grouped launch per phase and chunk of the triple list; enqueue only.
  * Replay: the first apply with a given (psi, sigma) pair captures the
  * plan's launch sequence into a HIP graph (on a private stream; this creates

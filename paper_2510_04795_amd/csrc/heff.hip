@@ -787,8 +787,12 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
         hipMemsetAsync(P->psi_e, 0, sizeof(int32_t) * std::max<int64_t>(Ps.e_total, 1), s);
         hipMemsetAsync(P->T_p, 0, Tp_max, s);
         hipMemsetAsync(P->T_e, 0, sizeof(int32_t) * Te_max, s);
-        hipEventCreate(&ev0);
-        hipEventCreate(&ev1);
+        if ((e = hipEventCreate(&ev0)) != hipSuccess || (e = hipEventCreate(&ev1)) != hipSuccess) {
+            if (ev0) hipEventDestroy(ev0);
+            hipFree(tmp_sigma);
+            free_plan(P);
+            return hip_fail(e, "heff_plan_create: tuning events");
+        }
     }
     // Candidates: tile variant x tile order (the XCD order first, the
     // default) x launch: one workgroup per tile; the streamed kernel, whose
@@ -839,21 +843,24 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
     const size_t floor_tiles = static_cast<size_t>(8) * ctx->num_cu;
     TileDesc *tmp_tiles = nullptr;
     int32_t *tmp_off = nullptr;
-    if (tuning && ((e = hipMalloc(&tmp_tiles, sizeof(TileDesc) * (cap + 8))) != hipSuccess ||
-                   (e = hipMalloc(&tmp_off, sizeof(int32_t) * (static_cast<size_t>(kMaxResidentPerCu) * ctx->num_cu + 1))) != hipSuccess)) {
-        hipFree(tmp_sigma);
-        hipFree(tmp_tiles);
-        free_plan(P);
-        return hip_fail(e, "heff_plan_create: tuning buffer");
-    }
+    // the tuning's scratch buffers and events, released on every path
     auto free_tuning = [&]() {
         if (tmp_sigma) hipFree(tmp_sigma);
         if (tmp_tiles) hipFree(tmp_tiles);
         if (tmp_off) hipFree(tmp_off);
+        if (ev0) hipEventDestroy(ev0);
+        if (ev1) hipEventDestroy(ev1);
         tmp_sigma = nullptr;
         tmp_tiles = nullptr;
         tmp_off = nullptr;
+        ev0 = ev1 = nullptr;
     };
+    if (tuning && ((e = hipMalloc(&tmp_tiles, sizeof(TileDesc) * (cap + 8))) != hipSuccess ||
+                   (e = hipMalloc(&tmp_off, sizeof(int32_t) * (static_cast<size_t>(kMaxResidentPerCu) * ctx->num_cu + 1))) != hipSuccess)) {
+        free_tuning();
+        free_plan(P);
+        return hip_fail(e, "heff_plan_create: tuning buffer");
+    }
     if (fixed_phases) {
         for (int ph = 0; ph < 2; ++ph) {
             const int l = ctx->heff_fix[ph][2];
@@ -973,8 +980,6 @@ int heff_plan_create(ozaki_ctx ctx, heff_plan *out, const heff_layout *L, const 
                     }
                 }
             }
-        hipEventDestroy(ev0);
-        hipEventDestroy(ev1);
         hipStreamSynchronize(s);
         free_tuning();
         // the timed launches of the first phase may have left maxima
@@ -1126,7 +1131,11 @@ int capture_apply(heff_plan P, const double *psi, double *sigma, hipStream_t s,
 int heff_apply(heff_plan P, const double *psi, double *sigma, void *stream) {
     if (!P) return fail(OZ_ERR_ARG, "heff_apply: plan is NULL");
     if (P->n > 0 && (!psi || !sigma)) return fail(OZ_ERR_ARG, "heff_apply: psi / sigma NULL");
-    if (psi == sigma && P->n > 0) return fail(OZ_ERR_ARG, "heff_apply: psi and sigma overlap");
+    if (P->n > 0) {
+        const uintptr_t a = reinterpret_cast<uintptr_t>(psi), b = reinterpret_cast<uintptr_t>(sigma);
+        const uintptr_t bytes = static_cast<uintptr_t>(P->n) * sizeof(double);
+        if (a < b + bytes && b < a + bytes) return fail(OZ_ERR_ARG, "heff_apply: psi and sigma overlap");
+    }
     hipStream_t s = static_cast<hipStream_t>(stream);
     ozaki_ctx ctx = P->ctx;
     hipError_t e;

@@ -170,6 +170,22 @@ def _dev_f64(t: torch.Tensor, name: str) -> torch.Tensor:
     return t
 
 
+def _dev_vec(t: torch.Tensor, n: int, name: str) -> torch.Tensor:
+    """A float64 CUDA vector the library reads or writes n elements of."""
+    _dev_f64(t, name)
+    if t.numel() != n or not t.is_contiguous():
+        raise ValueError("%s must be contiguous with %d elements" % (name, n))
+    return t
+
+
+def _dev_out(t: torch.Tensor, rows: int, cols: int, name: str) -> torch.Tensor:
+    """A float64 CUDA matrix of rows x cols the library writes."""
+    _dev_f64(t, name)
+    if tuple(t.shape) != (rows, cols):
+        raise ValueError("%s must be %d x %d, not %s" % (name, rows, cols, tuple(t.shape)))
+    return t
+
+
 def _ld(t: torch.Tensor, name: str) -> int:
     """Leading dimension of a row-major 2-D view (unit column stride)."""
     if t.dim() != 2:
@@ -286,12 +302,12 @@ class Context:
         """Time every tile variant on this GEMM and keep the fastest; returns
         (variant, {variant: ms})."""
         import numpy as np
-        ta, tb = transa.upper() == "T", transb.upper() == "T"
-        M = A.size(1) if ta else A.size(0)
-        K = A.size(0) if ta else A.size(1)
-        N = B.size(0) if tb else B.size(1)
+        _dev_f64(A, "A")
+        _dev_f64(B, "B")
+        M, N, K = self._dims(A, B, transa, transb)
         if C is None:
             C = torch.empty((M, N), dtype=torch.float64, device=A.device)
+        _dev_out(C, M, N, "C")
         if workspace is None:
             workspace = self.workspace(M, N, K, slices, ndiag)
         ms = np.full(16, -1.0, dtype=np.float64)
@@ -325,7 +341,7 @@ class Context:
             C = torch.empty((M, N), dtype=torch.float64, device=A.device)
             if beta != 0.0:
                 raise ValueError("beta != 0 needs C")
-        _dev_f64(C, "C")
+        _dev_out(C, M, N, "C")
         if workspace is None:
             workspace = self.workspace(M, N, K, slices, ndiag)
         wptr = workspace.data_ptr() if workspace is not None else None
@@ -367,6 +383,11 @@ class Context:
                 raise ValueError("every operator must be %d x %d" % (n, n))
         if outs is None:
             outs = [torch.empty((D, D), dtype=torch.float64, device=U.device) for _ in ops]
+        outs = list(outs)
+        if len(outs) != len(ops):
+            raise ValueError("one output per operator: %d outputs for %d operators" % (len(outs), len(ops)))
+        for o in outs:
+            _dev_out(o, D, D, "outs[k]")
         ldo = _ld(ops[0], "ops[0]") if ops else max(n, 1)
         ldout = _ld(outs[0], "outs[0]") if outs else max(D, 1)
         if any(_ld(o, "ops[k]") != ldo for o in ops) or any(_ld(o, "outs[k]") != ldout for o in outs):
@@ -431,7 +452,7 @@ class Context:
             if beta != 0.0:
                 raise ValueError("beta != 0 needs C")
             C = torch.empty((M, N), dtype=torch.float64, device=A.device)
-        _dev_f64(C, "C")
+        _dev_out(C, M, N, "C")
         if workspace is None:
             workspace = self.auto_workspace(M, N, K)
         s_out, g_out = ctypes.c_int32(), ctypes.c_int32()
@@ -515,6 +536,12 @@ class HeffPlan:
                                      _stream(stream)), "heff_plan_create")
         self.handle = h
         self.n = int(_lib.heff_vector_length(h))
+        if diag is not None:
+            try:
+                _dev_vec(diag, self.n, "diag")
+            except (TypeError, ValueError):
+                self.close()
+                raise
         self.flops = float(_lib.heff_flops(h))
         a, b = ctypes.c_int32(), ctypes.c_int32()
         _check(_lib.heff_plan_variants(h, ctypes.byref(a), ctypes.byref(b)), "heff_plan_variants")
@@ -523,11 +550,11 @@ class HeffPlan:
         self.launches = (a.value, b.value)
 
     def apply(self, psi, sigma=None, stream=None):
-        _dev_f64(psi, "psi")
-        if psi.numel() != self.n or not psi.is_contiguous():
-            raise ValueError("psi must be contiguous with %d elements" % self.n)
+        _dev_vec(psi, self.n, "psi")
         if sigma is None:
             sigma = torch.empty_like(psi)
+        else:
+            _dev_vec(sigma, self.n, "sigma")
         _check(_lib.heff_apply(self.handle, psi.data_ptr(), sigma.data_ptr(), _stream(stream)),
                "heff_apply")
         return sigma
@@ -579,8 +606,8 @@ class Davidson:
         self.plan = plan
         h = _ptr()
         _check(_lib.davidson_create(ctx.handle, ctypes.byref(h), plan.handle,
-                                    _dev_f64(hdiag, "hdiag").data_ptr(),
-                                    _dev_f64(x0, "x0").data_ptr(), m_max, tol, max_iter,
+                                    _dev_vec(hdiag, plan.n, "hdiag").data_ptr(),
+                                    _dev_vec(x0, plan.n, "x0").data_ptr(), m_max, tol, max_iter,
                                     _stream(stream)), "davidson_create")
         self.handle = h
 
@@ -592,6 +619,7 @@ class Davidson:
     def vector(self, out=None, stream=None):
         if out is None:
             out = torch.empty(self.plan.n, dtype=torch.float64, device="cuda:%d" % self.ctx.device)
+        _dev_vec(out, self.plan.n, "out")
         _check(_lib.davidson_get_vector(self.handle, out.data_ptr(), _stream(stream)),
                "davidson_get_vector")
         return out
@@ -632,7 +660,7 @@ class Lanczos:
         self.ctx = ctx
         self.plan = plan
         h = _ptr()
-        _check(_lib.lanczos_create(ctx.handle, ctypes.byref(h), plan.handle, _dev_f64(x0, "x0").data_ptr(),
+        _check(_lib.lanczos_create(ctx.handle, ctypes.byref(h), plan.handle, _dev_vec(x0, plan.n, "x0").data_ptr(),
                                    m_max, tol, max_iter, _stream(stream)), "lanczos_create")
         self.handle = h
 
@@ -644,6 +672,7 @@ class Lanczos:
     def vector(self, out=None, stream=None):
         if out is None:
             out = torch.empty(self.plan.n, dtype=torch.float64, device="cuda:%d" % self.ctx.device)
+        _dev_vec(out, self.plan.n, "out")
         _check(_lib.lanczos_get_vector(self.handle, out.data_ptr(), _stream(stream)), "lanczos_get_vector")
         return out
 

@@ -131,6 +131,43 @@ def test_bad_arguments(oz):
         solver(ozaki, ctx, torch, prob, 0, m_max=1)
 
 
+
+def test_binding_checks_vector_sizes(oz):
+    """hdiag, x0, the plan's diagonal and the vector output must hold the
+    plan's n elements: the binding refuses others before the library could
+    read or write past them."""
+    ozaki, ctx, torch = oz
+    prob = wl.davidson_problem(D=8, kop=2)
+    layout, Lf, Rf, _, triples = wl.flatten_dense(prob.L, prob.R, prob.x0[:, None, :])
+    dL, dR = dev(torch, Lf), dev(torch, Rf)
+    n = prob.x0.size
+    with pytest.raises(ValueError):
+        ozaki.HeffPlan(ctx, layout, dL, dR, triples, diag=dev(torch, prob.delta.ravel()[:-1]), slices=6)
+    with pytest.raises(TypeError):
+        ozaki.HeffPlan(ctx, layout, dL, dR, triples, diag=dev(torch, prob.delta.ravel()).float(), slices=6)
+    plan = ozaki.HeffPlan(ctx, layout, dL, dR, triples, diag=dev(torch, prob.delta.ravel()), slices=6)
+    hd, x0 = dev(torch, prob.hdiag.ravel()), dev(torch, prob.x0.ravel())
+    with pytest.raises(ValueError):
+        ozaki.Davidson(ctx, plan, hd[:-1], x0)
+    with pytest.raises(ValueError):
+        ozaki.Davidson(ctx, plan, hd, torch.cat([x0, x0]))
+    with pytest.raises(ValueError):
+        ozaki.Lanczos(ctx, plan, x0[:n - 2])
+    dav = ozaki.Davidson(ctx, plan, hd, x0)
+    dav.step()
+    with pytest.raises(ValueError):
+        dav.vector(torch.empty(n - 1, dtype=torch.float64, device="cuda"))
+    assert dav.vector().numel() == n
+    lz = ozaki.Lanczos(ctx, plan, x0)
+    lz.step()
+    with pytest.raises(ValueError):
+        lz.vector(torch.empty(2 * n, dtype=torch.float64, device="cuda")[::2])
+    assert lz.vector().numel() == n
+    dav.close()
+    lz.close()
+    plan.close()
+
+
 # ---------------------------------------------------------------- Lanczos
 def lanczos_solver(ozaki, ctx, torch, prob, S, G=0, m_max=32, tol=1e-8, max_iter=300):
     layout, Lf, Rf, _, triples = wl.flatten_dense(prob.L, prob.R, prob.x0[:, None, :])

@@ -321,3 +321,35 @@ def test_random_shapes_every_variant(oz, seed):
                             % (seed, S, G, M, N, K, transa, transb, alpha, beta, v))
     finally:
         ctx.set_variant(S, G, -1)
+
+
+def test_binding_checks_output_shapes(oz):
+    """A C of another shape than op(A) op(B), or outputs that do not match
+    the operators, are refused by the binding before the library could
+    write past them; a strided C of the right shape is accepted."""
+    ozaki, ctx, torch = oz
+    A, B = wl.gemm_pair(40, U=4, seed=3, m=24, k=32)
+    dA, dB = dev(torch, A), dev(torch, B)
+    for bad in [(23, 40), (24, 39), (40, 24)]:
+        C = torch.zeros(bad, dtype=torch.float64, device="cuda")
+        with pytest.raises(ValueError):
+            ctx.dgemm(dA, dB, slices=6, C=C)
+        with pytest.raises(ValueError):
+            ctx.dgemm_auto(dA, dB, C=C)
+        with pytest.raises(ValueError):
+            ctx.tune(dA, dB, slices=6, C=C)
+    with pytest.raises(TypeError):
+        ctx.dgemm(dA, dB, slices=6, C=torch.zeros((24, 40), dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError):
+        ctx.tune(dA, dev(torch, B[:31]), slices=6)
+    buf = torch.zeros((24, 50), dtype=torch.float64, device="cuda")
+    got = ctx.dgemm(dA, dB, slices=6, C=buf[:, 5:45]).cpu().numpy()
+    assert_bitexact(got, oracle.ozaki_dgemm(A, B, 6), "strided C")
+    U = dev(torch, np.linalg.qr(np.random.default_rng(0).standard_normal((40, 40)))[0][:, :8])
+    ops = [dev(torch, A[:, :24].T @ A[:, :24] / 40.0 + np.eye(24)) for _ in range(2)]
+    U24 = U[:24].contiguous()
+    with pytest.raises(ValueError):
+        ctx.renormalize(U24, ops, outs=[torch.empty((8, 8), dtype=torch.float64, device="cuda")])
+    with pytest.raises(ValueError):
+        ctx.renormalize(U24, ops, outs=[torch.empty((8, 7), dtype=torch.float64, device="cuda") for _ in ops])
+

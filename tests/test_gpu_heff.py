@@ -375,6 +375,29 @@ def test_plan_argument_errors(oz):
         ozaki.HeffPlan(ctx, bad, dL, dR, triples, slices=6)
 
 
+def test_apply_argument_errors(oz):
+    """psi and sigma whose ranges intersect are refused by the library (equal
+    or shifted by one element, either way round); a sigma of the wrong size,
+    type or layout by the binding; the plan still applies correctly after."""
+    ozaki, ctx, torch = oz
+    L, R, psi = wl.heff_dense(D=8, kop=2, phys=1, seed=0)
+    plan, dpsi, keep = dense_plan(ozaki, ctx, torch, L, R, psi, 6)
+    n = plan.n
+    buf = torch.zeros(2 * n + 1, dtype=torch.float64, device="cuda")
+    buf[:n] = dpsi
+    for a, b in [(0, 0), (0, 1), (1, 0), (0, n - 1)]:
+        with pytest.raises(ozaki.OzakiError):
+            plan.apply(buf[a:a + n], buf[b:b + n])
+    with pytest.raises(ValueError):
+        plan.apply(dpsi, torch.empty(n - 1, dtype=torch.float64, device="cuda"))
+    with pytest.raises(ValueError):
+        plan.apply(dpsi, torch.empty(2 * n, dtype=torch.float64, device="cuda")[::2])
+    with pytest.raises(TypeError):
+        plan.apply(dpsi, torch.empty(n, dtype=torch.float32, device="cuda"))
+    got = plan.apply(buf[:n], buf[n:2 * n]).cpu().numpy().reshape(psi.shape)   # adjacent ranges are fine
+    assert_bitexact(got, oracle.heff_dense(L, R, psi, S=6), "after the refused calls")
+
+
 def test_plan_variants_bitexact(oz):
     """Each fixed tile variant and the autotuned choice give the oracle's bits."""
     ozaki, ctx, torch = oz
