@@ -168,6 +168,39 @@ def test_binding_checks_vector_sizes(oz):
     plan.close()
 
 
+
+@pytest.mark.parametrize("seed", range(8))
+def test_random_problems_against_brute_force(oz, seed):
+    """Seeded random small problems (D = 4..20, 1 to 8 operator pairs, with
+    or without the planted low state, basis limits 4, 8 and 32 so restarts
+    occur): Davidson and Lanczos reach the lowest eigenvalue of the dense
+    matrix (numpy eigh), FP64 within 1e-9 relative with the eigenvector,
+    emulated S = 4..8 within 1e-6 (the energy target)."""
+    ozaki, ctx, torch = oz
+    rng = np.random.default_rng(500 + seed)
+    D, kop = int(rng.integers(4, 21)), int(rng.integers(1, 9))
+    well = float(rng.choice([-30.0, -5.0, 0.0]))
+    m_max = int(rng.choice([4, 8, 32]))
+    S = int(rng.choice([4, 5, 6, 7, 8]))
+    prob = wl.davidson_problem(D=D, kop=kop, well=well, seed=600 + seed)
+    ev, evec = brute(prob)
+    scale = max(1.0, abs(ev[0]))
+    what = "seed %d D=%d kop=%d well=%g m_max=%d" % (seed, D, kop, well, m_max)
+    for make in (solver, lanczos_solver):
+        sol, keep = make(ozaki, ctx, torch, prob, 0, m_max=m_max, tol=1e-9, max_iter=600)
+        th, st, its, res = sol.run()
+        assert st == "converged", (what, make.__name__, st, its, res)
+        assert abs(th - ev[0]) <= 1e-9 * scale, (what, make.__name__, th - ev[0])
+        x = sol.vector().cpu().numpy()
+        assert abs(abs(x @ evec[:, 0]) - 1) < 1e-8 or ev[1] - ev[0] < 1e-6 * scale, (what, make.__name__)
+        sol.close()
+        sol, keep = make(ozaki, ctx, torch, prob, S, m_max=m_max, tol=1e-8, max_iter=600)
+        th, st, its, res = sol.run()
+        assert st in ("converged", "stagnated"), (what, make.__name__, S, st)
+        assert abs(th - ev[0]) <= 1e-6 * scale, (what, make.__name__, S, th - ev[0])
+        sol.close()
+
+
 # ---------------------------------------------------------------- Lanczos
 def lanczos_solver(ozaki, ctx, torch, prob, S, G=0, m_max=32, tol=1e-8, max_iter=300):
     layout, Lf, Rf, _, triples = wl.flatten_dense(prob.L, prob.R, prob.x0[:, None, :])
