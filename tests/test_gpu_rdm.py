@@ -94,6 +94,29 @@ def test_emulated_accuracy_follows_slices(oz, S):
     check_eigenpairs(A, w, Z, S)
 
 
+@pytest.mark.parametrize("seed", range(8))
+def test_random_symmetric(oz, seed):
+    """Seeded random symmetric matrices: sizes 2..300 (off the 32-row
+    blocks), positive semidefinite of full or deficient rank, or indefinite;
+    a random number of wanted eigenpairs; FP64 or S = 4..7.  Eigenvalues,
+    residuals and orthogonality within the bound of the arithmetic."""
+    rng = np.random.default_rng(700 + seed)
+    n = int(rng.integers(2, 301))
+    kind = int(rng.integers(0, 3))
+    if kind == 0:
+        A = wishart(n, seed=800 + seed)
+    elif kind == 1:
+        A = wishart(n, r=int(rng.integers(1, n + 1)), seed=800 + seed)
+    else:
+        X = np.random.default_rng(800 + seed).standard_normal((n, n))
+        A = (X + X.T) / 2
+    nev = int(rng.integers(1, n + 1))
+    S = int(rng.choice([0, 4, 5, 6, 7]))
+    w, Z, info = solve(oz, A, S, nev=nev)
+    assert info.status in (1, 2, 3), (seed, n, kind, nev, S, info.status)
+    check_eigenpairs(A, w, Z, S)
+
+
 def test_edge_matrices(oz):
     # zero matrix: all eigenvalues 0, orthonormal eigenvectors
     w, Z, info = solve(oz, np.zeros((50, 50)))
