@@ -209,6 +209,29 @@ def test_renormalize_bitexact(oz, S):
         assert_bitexact(got.cpu().numpy(), want, "renormalize S=%d" % S)
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_renormalize_random_bitexact(oz, seed):
+    """Seeded random renormalisations: n = 1..260, D = 1..n, 1 to 4
+    operators with entries spread over 2^-6..2^6, a general (not orthonormal)
+    U, S = 2..8 with every built ndiag: the oracle's bits."""
+    ozaki, ctx, torch = oz
+    rng = np.random.default_rng(900 + seed)
+    n = int(rng.integers(1, 261))
+    D = int(rng.integers(1, n + 1))
+    k = int(rng.integers(1, 5))
+    S = int(rng.integers(2, 9))
+    G = int(rng.choice(sorted({S, S + 1, 2 * S - 1})))
+
+    def spread(shape):
+        return np.ldexp(rng.standard_normal(shape), rng.integers(-6, 7, size=shape))
+
+    U = spread((n, D))
+    ops = [spread((n, n)) for _ in range(k)]
+    out = ctx.renormalize(dev(torch, U), [dev(torch, o) for o in ops], slices=S, ndiag=G)
+    for i, (got, want) in enumerate(zip(out, oracle.renormalize(U, ops, S=S, G=G))):
+        assert_bitexact(got.cpu().numpy(), want, "seed %d n=%d D=%d S=%d G=%d operator %d" % (seed, n, D, S, G, i))
+
+
 def test_renormalize_fp64_and_errors(oz):
     ozaki, ctx, torch = oz
     n, D = 130, 33
