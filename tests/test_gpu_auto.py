@@ -75,6 +75,34 @@ def test_dgemm_auto_automatic_width(oz):
     assert_bitexact(C.cpu().numpy(), want, "automatic width")
 
 
+@pytest.mark.parametrize("seed", range(8))
+def test_automatic_width_random(oz, seed):
+    """Seeded random products (sizes 1..300, entries spread 2^-U..2^U with
+    U = 0..40, rows and columns rescaled by up to 2^+-20, random transposes):
+    the library's (S, G) and rho equal the oracle's, and the automatic-width
+    GEMM gives the oracle's bits at that width."""
+    ozaki, ctx, torch = oz
+    rng = np.random.default_rng(1000 + seed)
+    m, k, n = (int(x) for x in rng.integers(1, 301, size=3))
+    U = int(rng.integers(0, 41))
+    A = np.ldexp(rng.standard_normal((m, k)), rng.integers(-U, U + 1, size=(m, k)))
+    B = np.ldexp(rng.standard_normal((k, n)), rng.integers(-U, U + 1, size=(k, n)))
+    if rng.random() < 0.5:
+        A = np.ldexp(A, rng.integers(-20, 21, size=(m, 1)))
+        B = np.ldexp(B, rng.integers(-20, 21, size=(1, n)))
+    ta, tb = ("T" if rng.random() < 0.5 else "N"), ("T" if rng.random() < 0.5 else "N")
+    As = A.T.copy() if ta == "T" else A
+    Bs = B.T.copy() if tb == "T" else B
+    S, G, st = ctx.choose_slices(dev(torch, As), dev(torch, Bs), transa=ta, transb=tb)
+    what = "seed %d %dx%dx%d U=%d %s%s" % (seed, m, k, n, U, ta, tb)
+    assert (S, G) == oracle.choose_slices(A, B), what
+    assert st["rho_a"] == pytest.approx(oracle.rho(A), rel=1e-12), what
+    assert st["rho_b"] == pytest.approx(oracle.rho(B, by_columns=True), rel=1e-12), what
+    C, s, g = ctx.dgemm_auto(dev(torch, As), dev(torch, Bs), bits=0, transa=ta, transb=tb)
+    assert (s, g) == (S, G), what
+    assert_bitexact(C.cpu().numpy(), oracle.ozaki_dgemm(A, B, s, g), what)
+
+
 def test_dgemm_auto_performant(oz):
     """The first beta = 0 call of a shape times both paths and keeps one; the
     result is the kept path's (bit-exact for the emulated one, FP64 bound for
