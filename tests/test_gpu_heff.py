@@ -375,6 +375,25 @@ def test_plan_argument_errors(oz):
         ozaki.HeffPlan(ctx, bad, dL, dR, triples, slices=6)
 
 
+def test_no_triples(oz):
+    """A plan with an empty triple list: sigma is exactly zero, or exactly
+    diag * psi with a diagonal term (the product added to +0), for FP64 and
+    emulated plans, graph replay on and off."""
+    ozaki, ctx, torch = oz
+    L, R, psi = wl.heff_dense(D=24, kop=2, phys=4, seed=7)
+    layout, Lf, Rf, pf, _ = wl.flatten_dense(L, R, psi)
+    dL, dR, dpsi = dev(torch, Lf), dev(torch, Rf), dev(torch, pf)
+    diag = np.random.default_rng(8).standard_normal(pf.size)
+    for S in (0, 4, 6, 8):
+        for d in (None, diag):
+            plan = ozaki.HeffPlan(ctx, layout, dL, dR, [], diag=None if d is None else dev(torch, d), slices=S)
+            want = np.zeros(pf.size) if d is None else d * pf.ravel()
+            for graphs in (True, False):
+                plan.set_graphs(graphs)
+                assert_bitexact(plan.apply(dpsi).cpu().numpy(), want, "no triples S=%d diag %s" % (S, d is not None))
+            plan.close()
+
+
 def test_apply_argument_errors(oz):
     """psi and sigma whose ranges intersect are refused by the library (equal
     or shifted by one element, either way round); a sigma of the wrong size,
