@@ -223,11 +223,15 @@ int ozaki_dgemm_auto(ozaki_ctx ctx, char transa, char transb, int64_t M, int64_t
             use = it->second ? S : 0;
         } else if (beta == 0.0) {
             hipStream_t s = static_cast<hipStream_t>(stream);
-            hipEvent_t ev[3];
+            hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
             hipError_t e = hipSuccess;
             for (auto &x : ev)
                 if (e == hipSuccess) e = hipEventCreate(&x);
-            if (e != hipSuccess) return hip_fail(e, "ozaki_dgemm_auto: events");
+            if (e != hipSuccess) {
+                for (auto &x : ev)
+                    if (x) hipEventDestroy(x);
+                return hip_fail(e, "ozaki_dgemm_auto: events");
+            }
             float ms_native = 0.f, ms_emul = 0.f;
             // warm both, then time one call of each
             rc = ozaki_dgemm(ctx, transa, transb, M, N, K, alpha, A, lda, B, ldb, 0.0, C, ldc, 0, 0, workspace,
