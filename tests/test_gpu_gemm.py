@@ -56,6 +56,41 @@ def test_split_bitexact(oz, S, by_columns):
         assert np.array_equal(d.cpu().numpy(), rd)
 
 
+@pytest.mark.parametrize("seed", range(8))
+def test_split_and_pair_products_random(oz, seed):
+    """Seeded random shapes (1..260 around the 32-wide groups and K blocks),
+    spreads U = 0..60 with scattered zeros and subnormals, both orientations,
+    S = 2..8 and every built ndiag: the oracle's exponents, digits and int32
+    diagonal sums."""
+    ozaki, ctx, torch = oz
+    rng = np.random.default_rng(1100 + seed)
+    M, N, K = (int(x) for x in rng.integers(1, 261, size=3))
+    S = int(rng.integers(2, 9))
+    G = int(rng.choice(sorted({S, S + 1, 2 * S - 1})))
+    U = int(rng.integers(0, 61))
+
+    def draw(shape):
+        X = wl.wide_normal(rng, shape, U)
+        X[rng.random(shape) < 0.05] = 0.0
+        X[rng.random(shape) < 0.02] *= 2.0 ** -1060
+        return X
+
+    A, B = draw((M, K)), draw((K, N))
+    what = "seed %d %dx%dx%d S=%d G=%d U=%d" % (seed, M, K, N, S, G, U)
+    for X, by_columns in ((A, False), (B, True)):
+        d, e = ctx.split(dev(torch, X), S, by_columns=by_columns)
+        rd, re_, rb = oracle.split(X, S, by_columns=by_columns)
+        if by_columns:
+            rd = np.transpose(rd, (0, 2, 1))
+        assert np.array_equal(e.cpu().numpy(), np.where(rb == 1, ozaki.OZ_EXP_NONFINITE, re_)), what
+        assert np.array_equal(d.cpu().numpy(), rd), what
+    Ad, _, _ = oracle.split(A, S)
+    Bd, _, _ = oracle.split(B, S, by_columns=True)
+    if K <= ozaki.max_exact_k(S, G):
+        Q = ctx.pair_products(dev(torch, Ad), dev(torch, np.transpose(Bd, (0, 2, 1))), S, G)
+        assert np.array_equal(Q.cpu().numpy().astype(np.int64), oracle.pair_products(Ad, Bd, G)), what
+
+
 def test_split_nonfinite_flag(oz):
     ozaki, ctx, torch = oz
     ctx.flags()
