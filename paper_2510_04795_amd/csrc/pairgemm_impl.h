@@ -11,16 +11,26 @@
 // ordered sum of terms for the effective Hamiltonian, raw Q for tests, or
 // int64 carry of a K chunk).
 //
-// Tiling.  256 threads = 2 x 2 waves, one wave per SIMD; a wave owns MB x NB
+// Tiling.  WM x WN waves (4, 8 or 16) per workgroup; a wave owns MB x NB
 // blocks of 32 x 32 outputs (v_mfma_i32_32x32x32_i8) for all G diagonals, so
-// the block tile is (64 MB) x (64 NB).  The inner dimension advances one
-// packed 32-wide K block at a time through a double-buffered LDS stage that
-// is filled by direct global->LDS 16-byte loads (no staging registers): the
-// loads of block kb + 1 are in flight while block kb is multiplied, with one
-// barrier per block.  A stage is the 2S runs of A rows and of B rows exactly
-// as they are stored (internal.h), so every MFMA operand is one 1 KiB read of
-// consecutive LDS addresses.  Rows past the operand are clamped to its last
-// padded row: they only feed outputs that are never stored.
+// the block tile is (32 WM MB) x (32 WN NB); the seven built shapes are
+// listed with variant_fits below.  The inner dimension advances one packed
+// 32-wide K block at a time through LDS stages filled by direct
+// global->LDS 16-byte loads (no staging registers).  A stage is the 2S runs
+// of A rows and of B rows exactly as they are stored (internal.h), so every
+// MFMA operand is one 1 KiB read of consecutive LDS addresses.  Rows past
+// the operand are clamped to its last padded row: they only feed outputs
+// that are never stored.
+//
+// Main loops, chosen per shape at compile time from the register budget:
+// the ring (one block per wave: three stages, loads two blocks ahead, or
+// two stages and one block ahead where a third would cost the second
+// workgroup per CU; explicit vmcnt waits, a bare s_barrier and one
+// generated asm block per step from asm_steps.h), and two double-buffered
+// loops for waves with several blocks (next block's fragments prefetched
+// when two fragment sets fit, else read after the barrier).  The grouped,
+// streamed, resident and paired-term kernels below run the same steps over
+// tile and term lists.
 #pragma once
 
 #include <algorithm>
